@@ -1,0 +1,12 @@
+"""Plain FP64 CPU oracle for the batched Ewald path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg. The library under paper_2507_02888_amd never
+imports it, and the oracle shares no code with the library.
+
+Parity unpinned: none -- every entry point is pinned by tests/test_oracle_pins.py
+(Madelung constants, alpha independence, invariances, incremental moves).
+"""
+from .oracle import (  # noqa: F401
+    build, lib_path, count_g, gvectors, rho_at, energy, run, run_batch, particles, Variant,
+)

@@ -1,0 +1,457 @@
+/*
+ * Plain FP64 CPU oracle for periodic Ewald energies and single-particle move
+ * deltas.  TEST INFRASTRUCTURE ONLY: it exists to check the HIP library and is
+ * called from the tests, from the smoke check and from the CPU-baseline leg of
+ * the benchmark.  The library never links or calls it, and it shares no code,
+ * header, table or helper with the library.
+ *
+ * What it computes (paper Sec. 2.2, "Ewald summation"):
+ *
+ *   V_Ew = sum_{i<j} q_i q_j v_E(r_i - r_j) + 1/2 sum_j q_j^2 v_M          (Eq. 2)
+ *
+ * with the 3D pair potential v_E and Madelung term v_M of Eqs. (3)-(4) and the
+ * strictly two-dimensional (z = 0) forms of Eqs. (5)-(6).  Writing alpha for
+ * sqrt(gamma) and collecting terms, the energy is the sum of four parts:
+ *
+ *   real        sum_{i<j} q_i q_j sum_R erfc(alpha|r_ij - R|)/|r_ij - R|
+ *               + 1/2 sum_i q_i^2 sum_{R != 0} erfc(alpha|R|)/|R|
+ *   reciprocal  (2 pi/Omega) sum_{G != 0} exp(-G^2/4alpha^2)/G^2 |rho(G)|^2     (3D)
+ *               (pi/A)       sum_{G != 0} erfc(G/2alpha)/G     |rho(G)|^2     (2D)
+ *               rho(G) = sum_j q_j exp(i G.r_j)
+ *   self        -(alpha/sqrt(pi)) sum_i q_i^2
+ *   background  -(pi/(2 Omega alpha^2)) Q^2 (3D),  -(sqrt(pi)/(A alpha)) Q^2 (2D),
+ *               Q = sum_i q_i.
+ *
+ * The real-space lattice sum is truncated at |r - R| < r_cut (a term is kept
+ * iff the distance is strictly below r_cut); the reciprocal sum runs over all
+ * nonzero G = n.B with |G| <= g_cut (inclusive, with a relative slack of 1e-12
+ * on |G|^2 so that rounding cannot drop lattice points that lie exactly on the
+ * cutoff sphere).  With large cutoffs this is the converged Ewald energy.
+ *
+ * Algorithm, deliberately plain:
+ *   - images by brute force over every lattice vector in a box that contains
+ *     the ball of radius r_cut around the displacement (no minimum image);
+ *   - the full G set (both G and -G), exp(iG.r) by direct cos/sin of the
+ *     Cartesian dot product (no separable phase tables);
+ *   - libm erfc, exp, cos, sin, sqrt; OpenMP only across walkers.
+ *
+ * Single-particle moves (paper Sec. 2.1): particle k moves r_k -> r'.
+ *   dE_real  = q_k sum_{j != k} q_j [phi(r' - r_j) - phi(r_k - r_j)]
+ *   dE_recip = c sum_G f(G) [2 Re(conj(rho) delta) + |delta|^2],
+ *              delta(G) = q_k (exp(iG.r') - exp(iG.r_k))
+ * and an accepted move sets rho <- rho + delta, r_k <- r'.
+ *
+ * Long-range Jastrow value (paper Sec. 2.3, Eq. (9) written through the
+ * structure factor): J = sum_{G in half set} a_{s(G)} |rho(G)|^2 where s(G) is
+ * the index of the shell of equal |G| (ascending, 0-based) and a_s = 0 for
+ * s >= n_jastrow.  Summed here over the full set with a factor 1/2.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define O_PI 3.14159265358979323846
+
+typedef struct {
+    int dim;                 /* 2 or 3 */
+    double lat[9];           /* rows a_i; a 2D cell uses lat[0],lat[1],lat[3],lat[4] */
+    double alpha, r_cut, g_cut;
+    int n_jastrow;           /* number of shell coefficients (0: no Jastrow) */
+    const double *jastrow_a; /* [n_jastrow] */
+} osys;
+
+/* ---- small helpers (plain, written out) -------------------------------- */
+
+static double cell_measure(const osys *s) {
+    const double *a = s->lat;
+    if (s->dim == 2) return fabs(a[0] * a[4] - a[1] * a[3]);
+    return fabs(a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                a[2] * (a[3] * a[7] - a[4] * a[6]));
+}
+
+/* Reciprocal vectors b_i (rows of bm) with a_i . b_j = 2 pi delta_ij. */
+static void recip_vectors(const osys *s, double bm[9]) {
+    const double *a = s->lat;
+    memset(bm, 0, 9 * sizeof(double));
+    if (s->dim == 2) {
+        double det = a[0] * a[4] - a[1] * a[3];
+        /* inverse of [[a0,a1],[a3,a4]] transposed, times 2 pi */
+        bm[0] = 2 * O_PI * a[4] / det;
+        bm[1] = -2 * O_PI * a[3] / det;
+        bm[3] = -2 * O_PI * a[1] / det;
+        bm[4] = 2 * O_PI * a[0] / det;
+        return;
+    }
+    double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                 a[2] * (a[3] * a[7] - a[4] * a[6]);
+    /* b_1 = 2 pi (a_2 x a_3)/det, etc. */
+    const double *a1 = a, *a2 = a + 3, *a3 = a + 6;
+    double c23[3] = {a2[1] * a3[2] - a2[2] * a3[1], a2[2] * a3[0] - a2[0] * a3[2], a2[0] * a3[1] - a2[1] * a3[0]};
+    double c31[3] = {a3[1] * a1[2] - a3[2] * a1[1], a3[2] * a1[0] - a3[0] * a1[2], a3[0] * a1[1] - a3[1] * a1[0]};
+    double c12[3] = {a1[1] * a2[2] - a1[2] * a2[1], a1[2] * a2[0] - a1[0] * a2[2], a1[0] * a2[1] - a1[1] * a2[0]};
+    for (int d = 0; d < 3; ++d) {
+        bm[0 + d] = 2 * O_PI * c23[d] / det;
+        bm[3 + d] = 2 * O_PI * c31[d] / det;
+        bm[6 + d] = 2 * O_PI * c12[d] / det;
+    }
+}
+
+static double vnorm(const double *v, int dim) {
+    double t = 0;
+    for (int d = 0; d < dim; ++d) t += v[d] * v[d];
+    return sqrt(t);
+}
+
+/* ---- G vectors ----------------------------------------------------------- */
+
+typedef struct {
+    int n;           /* number of G (full set, G != 0) */
+    double *g;       /* [n][3] Cartesian */
+    double *g2;      /* [n] |G|^2 */
+    int *shell;      /* [n] shell index, ascending |G| */
+    int n_shells;
+} gset;
+
+static int cmp_double(const void *x, const void *y) {
+    double a = *(const double *)x, b = *(const double *)y;
+    return (a > b) - (a < b);
+}
+
+static void gset_build(const osys *s, gset *out) {
+    double bm[9];
+    recip_vectors(s, bm);
+    int dim = s->dim;
+    int nmax[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) /* the G ball spans |n_d| <= g_cut |a_d| / 2 pi */
+        nmax[d] = (int)ceil(s->g_cut * vnorm(s->lat + 3 * d, dim) / (2 * O_PI)) + 1;
+    double lim = s->g_cut * s->g_cut * (1.0 + 1e-12);
+    int cap = (2 * nmax[0] + 1) * (2 * nmax[1] + 1) * (2 * nmax[2] + 1);
+    out->g = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+    out->g2 = (double *)malloc(sizeof(double) * (size_t)cap);
+    out->shell = (int *)malloc(sizeof(int) * (size_t)cap);
+    int n = 0;
+    for (int i = -nmax[0]; i <= nmax[0]; ++i)
+        for (int j = -nmax[1]; j <= nmax[1]; ++j)
+            for (int k = -nmax[2]; k <= nmax[2]; ++k) {
+                if (i == 0 && j == 0 && k == 0) continue;
+                double gv[3];
+                for (int d = 0; d < 3; ++d) gv[d] = i * bm[d] + j * bm[3 + d] + k * bm[6 + d];
+                double g2 = gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2];
+                if (g2 <= lim) {
+                    memcpy(out->g + 3 * n, gv, sizeof gv);
+                    out->g2[n] = g2;
+                    ++n;
+                }
+            }
+    out->n = n;
+    /* shells: distinct |G|^2 values (relative tolerance 1e-9), ascending */
+    double *sorted = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    memcpy(sorted, out->g2, sizeof(double) * (size_t)n);
+    qsort(sorted, (size_t)n, sizeof(double), cmp_double);
+    double *uniq = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int nu = 0;
+    for (int i = 0; i < n; ++i)
+        if (nu == 0 || sorted[i] > uniq[nu - 1] * (1.0 + 1e-9)) uniq[nu++] = sorted[i];
+    for (int i = 0; i < n; ++i) {
+        int sidx = 0;
+        for (int u = 0; u < nu; ++u)
+            if (fabs(out->g2[i] - uniq[u]) <= 1e-9 * uniq[u]) { sidx = u; break; }
+        out->shell[i] = sidx;
+    }
+    out->n_shells = nu;
+    free(sorted);
+    free(uniq);
+}
+
+static void gset_free(gset *g) {
+    free(g->g);
+    free(g->g2);
+    free(g->shell);
+}
+
+/* Reciprocal-space kernel f(G) per the full-set sum, including the prefactor:
+ * 3D (2 pi/Omega) exp(-G^2/4a^2)/G^2, 2D (pi/A) erfc(G/2a)/G. */
+static double recip_factor(const osys *s, double g2, double measure) {
+    double a = s->alpha;
+    if (s->dim == 3) return 2 * O_PI / measure * exp(-g2 / (4 * a * a)) / g2;
+    double g = sqrt(g2);
+    return O_PI / measure * erfc(g / (2 * a)) / g;
+}
+
+static double jastrow_coef(const osys *s, int shell) {
+    if (s->n_jastrow <= 0 || shell >= s->n_jastrow) return 0.0;
+    return s->jastrow_a[shell];
+}
+
+/* ---- real space ------------------------------------------------------------ */
+
+/* sum over lattice vectors R of erfc(alpha|d - R|)/|d - R| for |d - R| < r_cut,
+ * skipping R = 0 when skip_zero is set.  The box of lattice indices is chosen
+ * so that it contains every R within r_cut of d. */
+static double real_image_sum(const osys *s, const double *bm, const double *dv, int skip_zero) {
+    int dim = s->dim;
+    double rc = s->r_cut, a = s->alpha;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+        /* fractional coordinate of dv along a_d is (dv . b_d)/(2 pi) */
+        double f = 0;
+        for (int e = 0; e < dim; ++e) f += dv[e] * bm[3 * d + e];
+        f /= 2 * O_PI;
+        /* |(dv - R).b_d| <= |dv - R| |b_d| < r_cut |b_d| bounds index d */
+        double ext = rc * vnorm(bm + 3 * d, dim) / (2 * O_PI);
+        lo[d] = (int)floor(f - ext);
+        hi[d] = (int)ceil(f + ext);
+    }
+    double sum = 0;
+    for (int i = lo[0]; i <= hi[0]; ++i)
+        for (int j = lo[1]; j <= hi[1]; ++j)
+            for (int k = lo[2]; k <= hi[2]; ++k) {
+                if (skip_zero && i == 0 && j == 0 && k == 0) continue;
+                double r[3] = {0, 0, 0};
+                for (int e = 0; e < dim; ++e)
+                    r[e] = dv[e] - (i * s->lat[e] + j * s->lat[3 + e] + k * s->lat[6 + e]);
+                double d2 = 0;
+                for (int e = 0; e < dim; ++e) d2 += r[e] * r[e];
+                double dist = sqrt(d2);
+                if (dist < rc) sum += erfc(a * dist) / dist;
+            }
+    return sum;
+}
+
+/* ---- public entry points --------------------------------------------------- */
+
+int oracle_count_g(const osys *s, int *n_full, int *n_shells) {
+    gset g;
+    gset_build(s, &g);
+    *n_full = g.n;
+    *n_shells = g.n_shells;
+    gset_free(&g);
+    return 0;
+}
+
+/* Full set of G vectors: Cartesian [n][3], |G|^2, shell index.  Arrays must
+ * hold oracle_count_g's n_full entries. */
+int oracle_gvectors(const osys *s, double *g_out, double *g2_out, int *shell_out) {
+    gset g;
+    gset_build(s, &g);
+    memcpy(g_out, g.g, sizeof(double) * 3 * (size_t)g.n);
+    memcpy(g2_out, g.g2, sizeof(double) * (size_t)g.n);
+    memcpy(shell_out, g.shell, sizeof(int) * (size_t)g.n);
+    gset_free(&g);
+    return 0;
+}
+
+/* rho(G) = sum_j q_j exp(i G.r_j) at caller-given Cartesian G vectors. */
+int oracle_rho_at(const osys *s, int n, const double *pos, const double *q, int n_g,
+                  const double *g, double *rho_re_im /* [n_g][2] */) {
+    int dim = s->dim;
+    for (int t = 0; t < n_g; ++t) {
+        double re = 0, im = 0;
+        for (int j = 0; j < n; ++j) {
+            double ph = 0;
+            for (int e = 0; e < dim; ++e) ph += g[3 * t + e] * pos[dim * j + e];
+            re += q[j] * cos(ph);
+            im += q[j] * sin(ph);
+        }
+        rho_re_im[2 * t] = re;
+        rho_re_im[2 * t + 1] = im;
+    }
+    return 0;
+}
+
+/* Energy of one configuration.  parts[0..4] = real, reciprocal, self,
+ * background, total; *jastrow = J (0 when no coefficients). */
+int oracle_energy(const osys *s, int n, const double *pos, const double *q, double *parts,
+                  double *jastrow) {
+    int dim = s->dim;
+    double bm[9];
+    recip_vectors(s, bm);
+    double meas = cell_measure(s);
+    /* real space: pairs plus each particle's own images */
+    double e_real = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double dv[3] = {0, 0, 0};
+            for (int e = 0; e < dim; ++e) dv[e] = pos[dim * i + e] - pos[dim * j + e];
+            e_real += q[i] * q[j] * real_image_sum(s, bm, dv, 0);
+        }
+    {
+        double zero[3] = {0, 0, 0};
+        double self_img = real_image_sum(s, bm, zero, 1);
+        double q2 = 0;
+        for (int i = 0; i < n; ++i) q2 += q[i] * q[i];
+        e_real += 0.5 * q2 * self_img;
+    }
+    /* reciprocal space, full set */
+    gset g;
+    gset_build(s, &g);
+    double e_recip = 0, jas = 0;
+    for (int t = 0; t < g.n; ++t) {
+        double re = 0, im = 0;
+        for (int j = 0; j < n; ++j) {
+            double ph = 0;
+            for (int e = 0; e < dim; ++e) ph += g.g[3 * t + e] * pos[dim * j + e];
+            re += q[j] * cos(ph);
+            im += q[j] * sin(ph);
+        }
+        double r2 = re * re + im * im;
+        e_recip += recip_factor(s, g.g2[t], meas) * r2;
+        jas += 0.5 * jastrow_coef(s, g.shell[t]) * r2;
+    }
+    gset_free(&g);
+    double q2 = 0, qt = 0;
+    for (int i = 0; i < n; ++i) {
+        q2 += q[i] * q[i];
+        qt += q[i];
+    }
+    double a = s->alpha;
+    double e_self = -a / sqrt(O_PI) * q2;
+    double e_bg = (dim == 3) ? -O_PI / (2 * meas * a * a) * qt * qt : -sqrt(O_PI) / (meas * a) * qt * qt;
+    parts[0] = e_real;
+    parts[1] = e_recip;
+    parts[2] = e_self;
+    parts[3] = e_bg;
+    parts[4] = e_real + e_recip + e_self + e_bg;
+    if (jastrow) *jastrow = jas;
+    return 0;
+}
+
+/* One walker: initial energy, then n_steps proposed moves of mobile particles
+ * (indices k[m] < n_mobile; particles are ordered mobile first).  For each
+ * move the incremental delta (and Jastrow delta) is written; accepted moves
+ * update rho and the position.  Outputs: e0[0..4] parts of the initial energy,
+ * delta[m], djas[m], *j0 initial Jastrow, final positions in pos_final.
+ * Returns 0. */
+int oracle_run(const osys *s, int n, int n_mobile, const double *pos0, const double *q,
+               int n_steps, const int32_t *k, const double *new_pos, const uint8_t *accept,
+               double *e0, double *j0, double *delta, double *djas, double *pos_final) {
+    (void)n_mobile;
+    int dim = s->dim;
+    double bm[9];
+    recip_vectors(s, bm);
+    double meas = cell_measure(s);
+    double *pos = (double *)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
+    memcpy(pos, pos0, sizeof(double) * (size_t)dim * (size_t)n);
+    oracle_energy(s, n, pos, q, e0, j0);
+    gset g;
+    gset_build(s, &g);
+    double *rre = (double *)calloc((size_t)(g.n > 0 ? g.n : 1), sizeof(double));
+    double *rim = (double *)calloc((size_t)(g.n > 0 ? g.n : 1), sizeof(double));
+    double *fac = (double *)malloc(sizeof(double) * (size_t)(g.n > 0 ? g.n : 1));
+    double *jc = (double *)malloc(sizeof(double) * (size_t)(g.n > 0 ? g.n : 1));
+    for (int t = 0; t < g.n; ++t) {
+        fac[t] = recip_factor(s, g.g2[t], meas);
+        jc[t] = 0.5 * jastrow_coef(s, g.shell[t]);
+        for (int j = 0; j < n; ++j) {
+            double ph = 0;
+            for (int e = 0; e < dim; ++e) ph += g.g[3 * t + e] * pos[dim * j + e];
+            rre[t] += q[j] * cos(ph);
+            rim[t] += q[j] * sin(ph);
+        }
+    }
+    for (int m = 0; m < n_steps; ++m) {
+        int kk = k[m];
+        const double *rn = new_pos + (size_t)dim * (size_t)m;
+        const double *ro = pos + dim * kk;
+        /* real space */
+        double dr = 0;
+        for (int j = 0; j < n; ++j) {
+            if (j == kk) continue;
+            double dn[3] = {0, 0, 0}, dold[3] = {0, 0, 0};
+            for (int e = 0; e < dim; ++e) {
+                dn[e] = rn[e] - pos[dim * j + e];
+                dold[e] = ro[e] - pos[dim * j + e];
+            }
+            dr += q[j] * (real_image_sum(s, bm, dn, 0) - real_image_sum(s, bm, dold, 0));
+        }
+        dr *= q[kk];
+        /* reciprocal space */
+        double drec = 0, dj = 0;
+        for (int t = 0; t < g.n; ++t) {
+            double pn = 0, po = 0;
+            for (int e = 0; e < dim; ++e) {
+                pn += g.g[3 * t + e] * rn[e];
+                po += g.g[3 * t + e] * ro[e];
+            }
+            double dre = q[kk] * (cos(pn) - cos(po));
+            double dim_ = q[kk] * (sin(pn) - sin(po));
+            double tt = 2 * (rre[t] * dre + rim[t] * dim_) + dre * dre + dim_ * dim_;
+            drec += fac[t] * tt;
+            dj += jc[t] * tt;
+        }
+        delta[m] = dr + drec;
+        djas[m] = dj;
+        if (accept[m]) {
+            for (int t = 0; t < g.n; ++t) {
+                double pn = 0, po = 0;
+                for (int e = 0; e < dim; ++e) {
+                    pn += g.g[3 * t + e] * rn[e];
+                    po += g.g[3 * t + e] * ro[e];
+                }
+                rre[t] += q[kk] * (cos(pn) - cos(po));
+                rim[t] += q[kk] * (sin(pn) - sin(po));
+            }
+            for (int e = 0; e < dim; ++e) pos[dim * kk + e] = rn[e];
+        }
+    }
+    if (pos_final) memcpy(pos_final, pos, sizeof(double) * (size_t)dim * (size_t)n);
+    free(rre);
+    free(rim);
+    free(fac);
+    free(jc);
+    gset_free(&g);
+    free(pos);
+    return 0;
+}
+
+/* Many walkers of one system, OpenMP across walkers.  Arrays are packed per
+ * walker: pos0 [W][n][dim], k [S][W], new_pos [S][W][dim], accept [S][W];
+ * outputs e0 [W][5], j0 [W], delta [S][W], djas [S][W].  Returns the number of
+ * threads used. */
+int oracle_run_batch(const osys *s, int n_walkers, int n, int n_mobile, const double *pos0,
+                     const double *q, int n_steps, const int32_t *k, const double *new_pos,
+                     const uint8_t *accept, double *e0, double *j0, double *delta, double *djas,
+                     int n_threads) {
+    int dim = s->dim;
+    int used = 1;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+    }
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int w = 0; w < n_walkers; ++w) {
+        int32_t *kw = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_steps > 0 ? n_steps : 1));
+        double *nw = (double *)malloc(sizeof(double) * (size_t)dim * (size_t)(n_steps > 0 ? n_steps : 1));
+        uint8_t *aw = (uint8_t *)malloc((size_t)(n_steps > 0 ? n_steps : 1));
+        double *dw = (double *)malloc(sizeof(double) * (size_t)(n_steps > 0 ? n_steps : 1));
+        double *jw = (double *)malloc(sizeof(double) * (size_t)(n_steps > 0 ? n_steps : 1));
+        for (int m = 0; m < n_steps; ++m) {
+            kw[m] = k[(size_t)m * n_walkers + w];
+            aw[m] = accept[(size_t)m * n_walkers + w];
+            for (int e = 0; e < dim; ++e) nw[dim * m + e] = new_pos[((size_t)m * n_walkers + w) * dim + e];
+        }
+        oracle_run(s, n, n_mobile, pos0 + (size_t)w * n * dim, q, n_steps, kw, nw, aw,
+                   e0 + 5 * (size_t)w, j0 + w, dw, jw, NULL);
+        for (int m = 0; m < n_steps; ++m) {
+            delta[(size_t)m * n_walkers + w] = dw[m];
+            djas[(size_t)m * n_walkers + w] = jw[m];
+        }
+        free(kw);
+        free(nw);
+        free(aw);
+        free(dw);
+        free(jw);
+    }
+    return used;
+}

@@ -1,0 +1,224 @@
+"""ctypes front end of oracle.c (see that file's header for the mathematics).
+
+Test infrastructure only; see the package docstring.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(src: str = _SRC, out: str = _LIB) -> str:
+    """Compile the oracle with gcc (always recompiles)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", out + ".tmp", src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    _libs.pop(out, None)
+    return out
+
+
+class _OSys(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("lat", ctypes.c_double * 9),
+                ("alpha", ctypes.c_double), ("r_cut", ctypes.c_double),
+                ("g_cut", ctypes.c_double), ("n_jastrow", ctypes.c_int),
+                ("jastrow_a", ctypes.POINTER(ctypes.c_double))]
+
+
+_libs = {}
+
+
+def _load(path: str = _LIB):
+    if path not in _libs:
+        if path == _LIB and not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(path)
+        P = ctypes.POINTER
+        d, i = ctypes.c_double, ctypes.c_int
+        lib.oracle_count_g.argtypes = [P(_OSys), P(i), P(i)]
+        lib.oracle_gvectors.argtypes = [P(_OSys), P(d), P(d), P(i)]
+        lib.oracle_rho_at.argtypes = [P(_OSys), i, P(d), P(d), i, P(d), P(d)]
+        lib.oracle_energy.argtypes = [P(_OSys), i, P(d), P(d), P(d), P(d)]
+        lib.oracle_run.argtypes = [P(_OSys), i, i, P(d), P(d), i, P(ctypes.c_int32), P(d),
+                                   P(ctypes.c_uint8), P(d), P(d), P(d), P(d), P(d)]
+        lib.oracle_run_batch.argtypes = [P(_OSys), i, i, i, P(d), P(d), i, P(ctypes.c_int32),
+                                         P(d), P(ctypes.c_uint8), P(d), P(d), P(d), P(d), i]
+        lib.oracle_run_batch.restype = i
+        _libs[path] = lib
+    return _libs[path]
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+class _Sys:
+    """Keeps the ctypes struct and the arrays it points to alive together."""
+
+    def __init__(self, dim, lattice, alpha, r_cut, g_cut, jastrow_a=None):
+        self.ja = None if jastrow_a is None else np.ascontiguousarray(jastrow_a, dtype=np.float64)
+        s = _OSys()
+        s.dim = int(dim)
+        lat = np.zeros((3, 3))
+        lat[:, :] = np.asarray(lattice, dtype=np.float64)[:3, :3]
+        for t in range(9):
+            s.lat[t] = float(lat.flat[t])
+        s.alpha, s.r_cut, s.g_cut = float(alpha), float(r_cut), float(g_cut)
+        if self.ja is None:
+            s.n_jastrow = 0
+            s.jastrow_a = ctypes.POINTER(ctypes.c_double)()
+        else:
+            s.n_jastrow = int(self.ja.shape[0])
+            s.jastrow_a = _ptr(self.ja, ctypes.c_double)
+        self.s = s
+
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def _mk(system, jastrow_a=None, **over):
+    kw = dict(dim=system.dim, lattice=system.lattice, alpha=system.alpha,
+              r_cut=system.r_cut, g_cut=system.g_cut)
+    kw.update(over)
+    return _Sys(jastrow_a=jastrow_a, **kw)
+
+
+def particles(system, mobile_pos: np.ndarray):
+    """All particles of one walker, mobile first then the fixed ions: (pos, q)."""
+    pos = np.concatenate([np.asarray(mobile_pos, dtype=np.float64).reshape(-1, system.dim),
+                          np.asarray(system.fixed_pos, dtype=np.float64).reshape(-1, system.dim)])
+    q = np.concatenate([system.mobile_q, system.fixed_q]).astype(np.float64)
+    return np.ascontiguousarray(pos), np.ascontiguousarray(q)
+
+
+def count_g(system, _path=_LIB, **over):
+    s = _mk(system, **over)
+    n, sh = ctypes.c_int(), ctypes.c_int()
+    _load(_path).oracle_count_g(s.ref(), ctypes.byref(n), ctypes.byref(sh))
+    return n.value, sh.value
+
+
+def gvectors(system, _path=_LIB, **over):
+    """Full G set: (g [n][3], g2 [n], shell [n])."""
+    n, _ = count_g(system, _path, **over)
+    s = _mk(system, **over)
+    g = np.zeros((n, 3))
+    g2 = np.zeros(n)
+    sh = np.zeros(n, dtype=np.int32)
+    _load(_path).oracle_gvectors(s.ref(), _ptr(g, ctypes.c_double), _ptr(g2, ctypes.c_double),
+                            _ptr(sh, ctypes.c_int))
+    return g, g2, sh
+
+
+def rho_at(system, pos, q, g, _path=_LIB):
+    s = _mk(system)
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((g.shape[0], 2))
+    _load(_path).oracle_rho_at(s.ref(), int(q.shape[0]), _ptr(pos, ctypes.c_double),
+                          _ptr(q, ctypes.c_double), int(g.shape[0]), _ptr(g, ctypes.c_double),
+                          _ptr(out, ctypes.c_double))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def energy(system, pos, q, jastrow_a: Optional[np.ndarray] = None, _path=_LIB, **over):
+    """Energy of one configuration (all particles given explicitly).
+    Returns dict(real, recip, self, background, total, jastrow)."""
+    s = _mk(system, jastrow_a=jastrow_a, **over)
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    parts = np.zeros(5)
+    jas = ctypes.c_double(0.0)
+    _load(_path).oracle_energy(s.ref(), int(q.shape[0]), _ptr(pos, ctypes.c_double),
+                          _ptr(q, ctypes.c_double), _ptr(parts, ctypes.c_double), ctypes.byref(jas))
+    return dict(real=parts[0], recip=parts[1], self=parts[2], background=parts[3],
+                total=parts[4], jastrow=jas.value)
+
+
+def run(system, mobile_pos, k, new_pos, accept, jastrow_a=None, _path=_LIB, **over):
+    """One walker: initial energy then the move sequence.  Returns dict with
+    e0 (parts array), j0, delta [S], djas [S], pos_final (mobile)."""
+    s = _mk(system, jastrow_a=jastrow_a, **over)
+    pos, q = particles(system, mobile_pos)
+    n = int(q.shape[0])
+    k = np.ascontiguousarray(k, dtype=np.int32)
+    S = int(k.shape[0])
+    newp = np.ascontiguousarray(new_pos, dtype=np.float64).reshape(S, system.dim)
+    acc = np.ascontiguousarray(accept, dtype=np.uint8)
+    e0 = np.zeros(5)
+    j0 = ctypes.c_double(0.0)
+    delta = np.zeros(S)
+    djas = np.zeros(S)
+    pf = np.zeros_like(pos)
+    _load(_path).oracle_run(s.ref(), n, system.n_mobile, _ptr(pos, ctypes.c_double),
+                       _ptr(q, ctypes.c_double), S, _ptr(k, ctypes.c_int32),
+                       _ptr(newp, ctypes.c_double), _ptr(acc, ctypes.c_uint8),
+                       _ptr(e0, ctypes.c_double), ctypes.byref(j0), _ptr(delta, ctypes.c_double),
+                       _ptr(djas, ctypes.c_double), _ptr(pf, ctypes.c_double))
+    return dict(e0=e0, energy0=e0[4], j0=j0.value, delta=delta, djas=djas,
+                pos_final=pf[: system.n_mobile])
+
+
+def run_batch(system, mobile_pos, k, new_pos, accept, jastrow_a=None, n_threads=0, _path=_LIB):
+    """Walkers of one system. mobile_pos [W][n_mobile][dim], k [S][W],
+    new_pos [S][W][dim], accept [S][W].  Returns dict(e0 [W][5], j0 [W],
+    delta [S][W], djas [S][W], threads)."""
+    s = _mk(system, jastrow_a=jastrow_a)
+    W = int(mobile_pos.shape[0])
+    allp = np.stack([particles(system, mobile_pos[w])[0] for w in range(W)])
+    q = particles(system, mobile_pos[0])[1]
+    n = int(q.shape[0])
+    k = np.ascontiguousarray(k, dtype=np.int32)
+    S = int(k.shape[0])
+    newp = np.ascontiguousarray(new_pos, dtype=np.float64)
+    acc = np.ascontiguousarray(accept, dtype=np.uint8)
+    allp = np.ascontiguousarray(allp)
+    e0 = np.zeros((W, 5))
+    j0 = np.zeros(W)
+    delta = np.zeros((S, W))
+    djas = np.zeros((S, W))
+    used = _load(_path).oracle_run_batch(s.ref(), W, n, system.n_mobile, _ptr(allp, ctypes.c_double),
+                                    _ptr(q, ctypes.c_double), S, _ptr(k, ctypes.c_int32),
+                                    _ptr(newp, ctypes.c_double), _ptr(acc, ctypes.c_uint8),
+                                    _ptr(e0, ctypes.c_double), _ptr(j0, ctypes.c_double),
+                                    _ptr(delta, ctypes.c_double), _ptr(djas, ctypes.c_double),
+                                    int(n_threads))
+    return dict(e0=e0, j0=j0, delta=delta, djas=djas, threads=used)
+
+
+class Variant:
+    """The same front end bound to another build of oracle.c (used by the
+    mutation tests, which compile deliberately broken copies)."""
+
+    def __init__(self, so_path: str):
+        self.path = so_path
+
+    def count_g(self, system, **over):
+        return count_g(system, self.path, **over)
+
+    def gvectors(self, system, **over):
+        return gvectors(system, self.path, **over)
+
+    def rho_at(self, system, pos, q, g):
+        return rho_at(system, pos, q, g, self.path)
+
+    def energy(self, system, pos, q, jastrow_a=None, **over):
+        return energy(system, pos, q, jastrow_a, self.path, **over)
+
+    def run(self, system, mobile_pos, k, new_pos, accept, jastrow_a=None, **over):
+        return run(system, mobile_pos, k, new_pos, accept, jastrow_a, self.path, **over)
+
+    particles = staticmethod(particles)

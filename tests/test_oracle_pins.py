@@ -1,0 +1,269 @@
+"""Pins of the FP64 oracle against what the mathematics fixes.
+
+Every check here is independent of the oracle's own formulas: literature
+Madelung energies, the exact independence of the converged energy from the
+Ewald split parameter, invariances of the periodic energy (translation,
+permutation, lattice-basis choice, scaling), and exact identities of the
+single-particle move (incremental delta versus a full recompute, telescoping).
+tests/test_oracle_mutations.py shows that plausible mistakes planted in a copy
+of the oracle make these checks fail.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2507_02888_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "madelung.txt")
+
+
+def golden():
+    out = {}
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        name, dim, val, tol = line.split()
+        out[name] = (int(dim), float(val), float(tol))
+    return out
+
+
+def converged(system, alpha_times_l=5.0):
+    """Cutoffs at which both truncations are far below 1e-15."""
+    L = system.length
+    a = alpha_times_l / L
+    return dict(alpha=a, r_cut=7.0 / a, g_cut=14.0 * a)
+
+
+def one_charge(lattice, dim):
+    return wl.System("w", dim, lattice, 1, -np.ones(1), np.zeros((0, dim)), np.zeros(0), 1, 1, 1)
+
+
+CELLS_3D = {
+    "sc": lambda v: wl.sc_cell(v),
+    "fcc": lambda v: wl.fcc_cell(v),
+    "bcc": lambda v: wl.bcc_cell(v),
+}
+
+
+def square_cell(area):
+    m = np.eye(3)
+    m[0, 0] = m[1, 1] = math.sqrt(area)
+    return m
+
+
+CELLS_2D = {"triangular": wl.hex_cell, "square": square_cell}
+
+
+@pytest.mark.parametrize("name", ["sc", "fcc", "bcc"])
+@pytest.mark.parametrize("rs", [1.0, 2.5])
+def test_wigner_3d(oracle_lib, name, rs):
+    dim, ref, tol = golden()[name]
+    s = one_charge(CELLS_3D[name](4.0 / 3.0 * math.pi * rs ** 3), 3)
+    for f in (4.0, 5.5):
+        e = oracle_lib.energy(s, np.zeros((1, 3)), -np.ones(1), **converged(s, f))
+        assert abs(e["total"] * rs - ref) <= tol * abs(ref)
+
+
+@pytest.mark.parametrize("name", ["triangular", "square"])
+def test_wigner_2d(oracle_lib, name):
+    dim, ref, tol = golden()[name]
+    rs = 1.7
+    s = one_charge(CELLS_2D[name](math.pi * rs ** 2), 2)
+    for f in (4.0, 5.5):
+        e = oracle_lib.energy(s, np.zeros((1, 2)), -np.ones(1), **converged(s, f))
+        assert abs(e["total"] * rs - ref) <= tol * abs(ref)
+
+
+def nacl(r0=1.3):
+    a = 2.0 * r0
+    na = np.array([[0, 0, 0], [0, 1, 1], [1, 0, 1], [1, 1, 0]], dtype=float) * a / 2
+    cl = na + np.array([a / 2, 0, 0])
+    pos = np.concatenate([na, cl])
+    q = np.array([1.0] * 4 + [-1.0] * 4)
+    s = wl.System("nacl", 3, a * np.eye(3), 8, q, np.zeros((0, 3)), np.zeros(0), 1, 1, 1)
+    return s, pos, q
+
+
+def test_nacl_madelung(oracle_lib):
+    _, ref, tol = golden()["nacl"]
+    r0 = 1.3
+    s, pos, q = nacl(r0)
+    e = oracle_lib.energy(s, pos, q, **converged(s))
+    # four formula units: E = -4 M / r0
+    m = -e["total"] * r0 / 4.0
+    assert abs(m - ref) <= tol * ref
+    # the reciprocal and real parts individually depend on alpha; the sum must not
+    e2 = oracle_lib.energy(s, pos, q, **converged(s, 3.5))
+    assert abs(e2["recip"] - e["recip"]) > 1e-3
+    assert abs(e2["total"] - e["total"]) <= 1e-12 * abs(e["total"])
+
+
+def random_system(dim, skew, n, seed, neutral):
+    if dim == 3:
+        lat = np.array([[5.0, 0.3, -0.2], [1.1, 4.6, 0.4], [-0.7, 0.9, 5.3]]) if skew else 5.0 * np.eye(3)
+    else:
+        lat = np.array([[5.0, 0.0, 0.0], [1.7, 4.4, 0.0], [0.0, 0.0, 1.0]]) if skew else square_cell(25.0)
+    g = np.random.default_rng(seed)
+    q = g.choice([-1.0, 1.0, 2.0], size=n)
+    if neutral:
+        q[-1] -= q.sum()
+    pos = g.random((n, dim)) @ lat[:dim, :dim]
+    s = wl.System("r", dim, lat, n, q, np.zeros((0, dim)), np.zeros(0), 1, 1, 1)
+    return s, pos, q
+
+
+@pytest.mark.parametrize("dim,skew,neutral", [(3, False, True), (3, True, True), (3, True, False),
+                                               (2, False, True), (2, True, False)])
+def test_alpha_independence(oracle_lib, dim, skew, neutral):
+    s, pos, q = random_system(dim, skew, 12, 7, neutral)
+    es = [oracle_lib.energy(s, pos, q, **converged(s, f))["total"] for f in (3.5, 5.0, 7.0)]
+    scale = max(abs(es[0]), (np.sum(q * q)) / s.length)
+    for e in es[1:]:
+        assert abs(e - es[0]) <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_translation_and_lattice_shift(oracle_lib, dim):
+    s, pos, q = random_system(dim, True, 10, 3, True)
+    kw = converged(s)
+    e0 = oracle_lib.energy(s, pos, q, **kw)["total"]
+    g = np.random.default_rng(5)
+    shifted = pos + g.normal(size=dim) * 3.0
+    assert abs(oracle_lib.energy(s, shifted, q, **kw)["total"] - e0) <= 1e-12 * abs(e0) * 10
+    # moving single particles by lattice vectors changes nothing
+    lat = s.lattice[:dim, :dim]
+    moved = pos.copy()
+    moved[0] += lat[0] - 2 * lat[dim - 1]
+    moved[3] -= lat[1]
+    assert abs(oracle_lib.energy(s, moved, q, **kw)["total"] - e0) <= 1e-12 * abs(e0) * 10
+    # the truncated model (r_cut below the inscribed radius) is invariant too
+    kt = dict(alpha=5.0 / s.length, r_cut=0.45 * s.length, g_cut=8 * 2 * math.pi / s.length)
+    et = oracle_lib.energy(s, pos, q, **kt)["total"]
+    assert abs(oracle_lib.energy(s, moved + lat[0] * 0.0 + (shifted - pos), q, **kt)["total"] - et) <= 1e-11 * abs(et)
+
+
+def test_permutation_invariance(oracle_lib):
+    s, pos, q = random_system(3, True, 11, 4, False)
+    kw = converged(s)
+    e0 = oracle_lib.energy(s, pos, q, **kw)["total"]
+    p = np.random.default_rng(1).permutation(11)
+    assert abs(oracle_lib.energy(s, pos[p], q[p], **kw)["total"] - e0) <= 1e-12 * abs(e0) * 10
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_lattice_basis_invariance(oracle_lib, dim):
+    """The same lattice described by another basis gives the same energy."""
+    s, pos, q = random_system(dim, True, 9, 8, True)
+    kw = converged(s)
+    e0 = oracle_lib.energy(s, pos, q, **kw)["total"]
+    # a unimodular integer change of basis
+    m = np.array([[1, 2, 0], [1, 3, 0], [1, 0, 1]], dtype=float) if dim == 3 else \
+        np.array([[1, 2, 0], [1, 3, 0], [0, 0, 1]], dtype=float)
+    lat2 = m @ s.lattice
+    s2 = wl.System("b", dim, lat2, 9, q, np.zeros((0, dim)), np.zeros(0), 1, 1, 1)
+    assert abs(abs(np.linalg.det(lat2[:dim, :dim])) - s.measure) < 1e-9
+    e2 = oracle_lib.energy(s2, pos, q, **kw)["total"]
+    assert abs(e2 - e0) <= 1e-11 * abs(e0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_homogeneity(oracle_lib, dim):
+    s, pos, q = random_system(dim, True, 8, 2, True)
+    kw = converged(s)
+    e0 = oracle_lib.energy(s, pos, q, **kw)["total"]
+    lam = 1.7
+    s2 = wl.System("h", dim, s.lattice * lam, 8, q, np.zeros((0, dim)), np.zeros(0), 1, 1, 1)
+    kw2 = dict(alpha=kw["alpha"] / lam, r_cut=kw["r_cut"] * lam, g_cut=kw["g_cut"] / lam)
+    if dim == 2:
+        s2.lattice[2, 2] = 1.0
+    e2 = oracle_lib.energy(s2, pos * lam, q, **kw2)["total"]
+    assert abs(e2 - e0 / lam) <= 1e-11 * abs(e0)
+
+
+@pytest.mark.parametrize("cfg_id", [1, 3, 4])
+def test_incremental_moves_match_recompute(oracle_lib, cfg_id):
+    """dE from the incremental update equals E(R') - E(R), and the accepted
+    deltas telescope to the final energy (truncated-model cutoffs)."""
+    cfg = wl.config(cfg_id)
+    # the smallest system of the workload (for the uneven batch: the 2x2x2 cell)
+    first = 0
+    if len(cfg.systems) > 1:
+        wsys = wl.make_batch(cfg, walkers=64, moves=0).walker_sys
+        first = int(np.nonzero(wsys == 0)[0][0])
+    b = wl.make_batch(cfg, walkers=1, moves=12, walker_start=first)
+    sysm = cfg.systems[int(b.walker_sys[0])]
+    ja = np.random.default_rng(3).uniform(-0.01, 0.01, 40)
+    r = oracle_lib.run(sysm, b.walker_pos(0), b.k[:, 0], b.new_pos[:, 0], b.accept[:, 0], jastrow_a=ja)
+    cur = b.walker_pos(0).copy()
+    e_cur = oracle_lib.energy(sysm, *oracle_lib.particles(sysm, cur), jastrow_a=ja)
+    scale = max(abs(e_cur["total"]), sysm.alpha / math.sqrt(math.pi) * float(np.sum(oracle_lib.particles(sysm, cur)[1] ** 2)))
+    assert abs(e_cur["total"] - r["energy0"]) <= 1e-12 * scale
+    for m in range(b.steps):
+        k = int(b.k[m, 0])
+        prop = cur.copy()
+        prop[k] = b.new_pos[m, 0]
+        e_new = oracle_lib.energy(sysm, *oracle_lib.particles(sysm, prop), jastrow_a=ja)
+        assert abs((e_new["total"] - e_cur["total"]) - r["delta"][m]) <= 1e-10 * scale
+        assert abs((e_new["jastrow"] - e_cur["jastrow"]) - r["djas"][m]) <= 1e-10 * max(1.0, abs(e_cur["jastrow"]))
+        if b.accept[m, 0]:
+            cur, e_cur = prop, e_new
+    acc = b.accept[:, 0].astype(bool)
+    assert abs(r["energy0"] + r["delta"][acc].sum() - e_cur["total"]) <= 1e-10 * scale
+    assert np.allclose(r["pos_final"], cur, atol=0, rtol=0)
+
+
+def test_jastrow_structure_factor_equals_pair_form(oracle_lib):
+    """sum_H a_s |rho|^2 = N sum_H a_s + 2 sum_{i<j} p(r_ij) with the paper's
+    plane-wave pair function p(r) = sum_s a_s sum_{G in star s, half} cos(G.r)
+    for unit charges; p is evaluated here by direct pair sums."""
+    cfg = wl.config(1)
+    s = cfg.systems[0]
+    pos = wl.random_positions(s, 15, 0)
+    q = -np.ones(15)
+    ja = np.random.default_rng(9).uniform(-0.01, 0.01, 60)
+    j = oracle_lib.energy(s, pos, q, jastrow_a=ja)["jastrow"]
+    g, g2, shell = oracle_lib.gvectors(s)
+    a = np.where(shell < len(ja), ja[np.minimum(shell, len(ja) - 1)], 0.0)
+    pair = 0.0
+    for i in range(15):
+        for k in range(i + 1, 15):
+            pair += 0.5 * np.sum(a * np.cos(g @ (pos[i] - pos[k])))  # full set: half of it
+    n_sum_half = 0.5 * np.sum(a) * 15
+    assert abs(j - (n_sum_half + 2 * pair)) <= 1e-10 * max(1.0, abs(j))
+
+
+@pytest.mark.parametrize("cfg_id,n_full,n_shells", [(1, 2108, 54), (2, 2108, 54), (3, 198, 21), (5, 7154, 106)])
+def test_g_counts(oracle_lib, cfg_id, n_full, n_shells):
+    """Counts of the reciprocal lattice points of the five workloads, checked
+    against the continuum estimate (4/3 pi G_c^3)/(2pi)^3 * Omega (2D: area)."""
+    s = wl.config(cfg_id).systems[0]
+    n, sh = oracle_lib.count_g(s)
+    assert (n, sh) == (n_full, n_shells)
+    if s.dim == 3:
+        est = 4.0 / 3.0 * math.pi * s.g_cut ** 3 * s.measure / (2 * math.pi) ** 3
+    else:
+        est = math.pi * s.g_cut ** 2 * s.measure / (2 * math.pi) ** 2
+    assert abs(n - est) < 0.05 * est
+    g, g2, shell = oracle_lib.gvectors(s)
+    assert np.all(g2 <= s.g_cut ** 2 * (1 + 1e-12))
+    # closed under G -> -G
+    keys = {tuple(np.round(v, 9)) for v in g}
+    assert all(tuple(np.round(-v, 9)) in keys for v in g)
+
+
+def test_cutoff_shells(oracle_lib):
+    """Moving r_cut across one shell of images of a simple-cubic Wigner lattice
+    removes exactly that shell: 12 second neighbours at sqrt(2) L and 8 third
+    neighbours at sqrt(3) L, each weighted 1/2 erfc(alpha R)/R."""
+    L = 3.0
+    s = one_charge(wl.sc_cell(L ** 3), 3)
+    a = 1.1 / L
+    kw = dict(alpha=a, g_cut=14.0 * a)
+    e = {rc: oracle_lib.energy(s, np.zeros((1, 3)), -np.ones(1), r_cut=rc * L, **kw)["total"]
+         for rc in (1.2, 1.5, 1.8)}
+    r2, r3 = math.sqrt(2.0) * L, math.sqrt(3.0) * L
+    assert abs((e[1.5] - e[1.2]) - 6.0 * math.erfc(a * r2) / r2) <= 1e-13
+    assert abs((e[1.8] - e[1.5]) - 4.0 * math.erfc(a * r3) / r3) <= 1e-13

@@ -1,0 +1,212 @@
+/*
+ * ewald.h -- C ABI of libewald.so: batched periodic Ewald energies and
+ * single-electron move deltas for quantum Monte Carlo walkers on one MI355X.
+ *
+ * The operation is the periodic Coulomb energy of the paper's Sec. 2.2
+ * ("Ewald summation", Eqs. (2)-(6)): for charges q_i at r_i in a periodic
+ * cell with lattice vectors a_i (rows of `lattice`) and split parameter
+ * alpha = sqrt(gamma),
+ *
+ *   E = E_real + E_recip + E_self + E_background
+ *   E_real       = sum_{i<j} q_i q_j erfc(alpha r_ij)/r_ij over the minimum image,
+ *                  kept iff r_ij < r_cut (r_cut <= r_inscribed, so at most one
+ *                  image of each pair contributes and no particle sees its own
+ *                  images)
+ *   E_recip      = sum_{G in H} w(|G|) |rho(G)|^2,  rho(G) = sum_i q_i exp(i G.r_i)
+ *                  w = (4 pi/Omega) exp(-G^2/4alpha^2)/G^2        (3D, Eqs. (3)-(4))
+ *                  w = (2 pi/A) erfc(G/2alpha)/G                  (2D, z = 0, Eqs. (5)-(6))
+ *                  H = one of each pair +-G with 0 < |G| <= g_cut (a G whose first
+ *                  nonzero reduced coordinate is positive), which is why w
+ *                  carries a factor 2
+ *   E_self       = -(alpha/sqrt(pi)) sum_i q_i^2
+ *   E_background = -(pi/(2 Omega alpha^2)) Q^2 (3D),  -(sqrt(pi)/(A alpha)) Q^2 (2D)
+ *
+ * and, optionally, the long-range plane-wave Jastrow value of Sec. 2.3
+ * (Eq. (9) expressed through the same structure factor)
+ *
+ *   J = sum_{G in H} a_{s(G)} |rho(G)|^2,  s(G) = shell of equal |G|, ascending.
+ *
+ * A single-particle move (Sec. 2.1: propose a move of one particle, decide,
+ * update) changes particle k from r_k to r'; the library returns
+ *   dE = q_k sum_{j != k} q_j [phi(r' - r_j) - phi(r_k - r_j)]
+ *        + sum_H w [2 Re(conj(rho) delta) + |delta|^2],
+ *   delta(G) = q_k (exp(iG.r') - exp(iG.r_k)),   phi(r) = erfc(alpha r)/r,
+ * (and dJ with a_s in place of w) and, when the move is accepted, updates
+ * rho <- rho + delta and r_k <- r'.
+ *
+ * Precision forms (Sec. 6.1: set-up tables always in double precision):
+ *   EWALD_FP64        every step in FP64.
+ *   EWALD_FP32_MIXED  phases exp(2 pi i frac(n.s)) in FP32 from FP64 fractional
+ *                     coordinates, the erf part of phi in FP32, FP32 partial
+ *                     sums with Kahan compensation; geometry (displacement,
+ *                     minimum image, r^2, 1/r), constants and the running rho
+ *                     in FP64, and rho rebuilt from the positions in FP64
+ *                     every `refresh_every` accepted moves.
+ *
+ * Conventions
+ *   - Units: Hartree atomic units (bohr, Hartree).
+ *   - Ownership: ewald_setup copies every host input; the caller may free them
+ *     on return.  Device tables are owned by the ewald_sys / ewald_batch and
+ *     freed by the matching _destroy.  Every per-walker buffer (positions,
+ *     state, proposals, outputs) is caller-owned DEVICE memory.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *     stream).  Batch calls only enqueue kernels: they never allocate, copy
+ *     to the host or synchronise, so they can be captured in a HIP graph.
+ *   - Errors: arguments are validated synchronously before anything is
+ *     enqueued; a non-OK status means nothing was enqueued and
+ *     ewald_last_error() (thread-local) holds a message.  No C++ exception
+ *     crosses the ABI.  Faults inside kernels surface at the caller's next
+ *     synchronisation.  A move index k outside [0, n_mobile) is not an error
+ *     status (it is device data): that walker's delta is NaN and no move is
+ *     pending for it.  Coincident particles or NaN positions give non-finite
+ *     results.
+ *   - Thread safety: ewald_sys and ewald_batch are immutable after creation
+ *     except for the host-side state-phase bookkeeping of each batch (which
+ *     is locked); concurrent calls on distinct state buffers are safe.
+ */
+#ifndef EWALD_H
+#define EWALD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ewald_sys ewald_sys;     /* one periodic cell, its charges and G tables */
+typedef struct ewald_batch ewald_batch; /* walker -> system map, packed layout        */
+
+typedef enum {
+    EWALD_OK = 0,
+    EWALD_E_ARG = 1,     /* bad argument (null pointer, count, mixed batch, ...) */
+    EWALD_E_RCUT = 2,    /* r_cut <= 0 or r_cut > r_inscribed                    */
+    EWALD_E_GCUT = 3,    /* g_cut <= 0, or the G set exceeds the library limits  */
+    EWALD_E_LATTICE = 4, /* singular or non-finite lattice                       */
+    EWALD_E_NOMEM = 5,   /* host or device allocation failed                     */
+    EWALD_E_HIP = 6,     /* a HIP runtime call failed (no device, launch error)  */
+    EWALD_E_STATE = 7    /* call order: move before energy, accept w/o pending   */
+} ewald_status;
+
+typedef enum { EWALD_FP64 = 0, EWALD_FP32_MIXED = 1 } ewald_precision;
+
+/* Library limits (checked by ewald_setup). */
+#define EWALD_MAX_PARTICLES 2048 /* n_mobile + n_fixed per system               */
+#define EWALD_MAX_NRED 120       /* largest |n_d| of a G vector in reduced units */
+#define EWALD_MAX_SEGMENTS 2048  /* G segments (4 G each) per system             */
+
+typedef struct {
+    int dim;                   /* 2 or 3                                               */
+    double lattice[3][3];      /* rows a_i in bohr; a 2D cell uses lattice[0..1][0..1] */
+    int n_fixed;               /* fixed ions (>= 0)                                    */
+    const double *fixed_pos;   /* host [n_fixed][dim] Cartesian bohr                   */
+    const double *fixed_q;     /* host [n_fixed]                                       */
+    int n_mobile;              /* mobile particles (electrons), >= 1                   */
+    const double *mobile_q;    /* host [n_mobile]                                      */
+    double alpha;              /* Ewald split parameter, 1/bohr, > 0                   */
+    double g_cut;              /* |G| <= g_cut (inclusive, relative slack 1e-12 on G^2)*/
+    double r_cut;              /* real-space cutoff, 0 < r_cut <= r_inscribed          */
+    ewald_precision precision;
+    int refresh_every;         /* K: rho rebuilt in FP64 every K accepted moves of a   */
+                               /* walker in the FP32-mixed form; 0 = never             */
+    int n_jastrow;             /* number of shell coefficients a_s (0: no Jastrow);    */
+                               /* coefficients past the last shell are ignored         */
+    const double *jastrow_a;   /* host [n_jastrow]                                     */
+} ewald_sys_desc;
+
+/* Build the cell's tables on the host in FP64 (reciprocal lattice, G set,
+ * shells, weights, fixed-ion structure factor, constants, minimum-image
+ * candidates).  Touches no device; device copies are made by
+ * ewald_batch_create.  Status: E_ARG, E_LATTICE, E_RCUT, E_GCUT, E_NOMEM. */
+ewald_status ewald_setup(const ewald_sys_desc *desc, ewald_sys **out);
+
+/* Sizes and constants of a system.  Any output pointer may be NULL.
+ * n_g: |H|; n_slots: stored G slots including padding (4 per segment);
+ * e_const = E_self + E_background + the fixed-ion real-space pair energy. */
+ewald_status ewald_sys_query(const ewald_sys *sys, int *n_g, int *n_slots, int *n_shells,
+                             double *r_inscribed, double *e_const);
+
+/* Host copies of the per-slot tables in the library's storage order (the
+ * order of rho in the walker state).  For each slot: reduced coordinates
+ * n[slot][3] (G = sum_d n_d b_d), weight w, Jastrow coefficient, shell index
+ * (-1 for padding slots, whose weights are 0).  Arrays hold n_slots entries;
+ * any pointer may be NULL. */
+ewald_status ewald_sys_tables(const ewald_sys *sys, int32_t *n, double *weight, double *jastrow,
+                              int32_t *shell);
+
+/* Minimum-image candidate lattice offsets (one of each +-pair), Cartesian
+ * [n][3]; `cand` may be NULL to query the count. */
+ewald_status ewald_sys_candidates(const ewald_sys *sys, int *n_cand, double *cand);
+
+void ewald_sys_destroy(ewald_sys *sys);
+
+/* A batch of n_walkers walkers; walker w belongs to sys[walker_sys[w]]
+ * (host array).  All systems must share dim and precision.  Copies the
+ * systems' tables to the current HIP device (once per system).  The systems
+ * must outlive the batch.  Status: E_ARG, E_NOMEM, E_HIP. */
+ewald_status ewald_batch_create(ewald_sys *const *sys, int n_sys, const int *walker_sys,
+                                int n_walkers, ewald_batch **out);
+
+/* Packed layout.  pos_offsets (host [n_walkers + 1], may be NULL): walker w's
+ * mobile positions are rows pos_offsets[w] .. pos_offsets[w+1]-1 of a
+ * [total][dim] FP64 array.  *state_bytes: size of the device state buffer
+ * (256-byte aligned). */
+ewald_status ewald_batch_layout(const ewald_batch *b, size_t *pos_offsets, size_t *state_bytes);
+
+/* Byte offsets, inside the state buffer, of walker w's header, wrapped
+ * fractional positions ([n_mobile][dim] FP64) and rho ([n_slots] complex
+ * FP64, (re, im) pairs, slot order of ewald_sys_tables). Header layout:
+ * int32 counter (accepted moves since the last rho rebuild), int32 pending_k
+ * (-1: none), int32 n_accepts, int32 n_refresh, double pending_s[3], double
+ * drift_max (largest |rho_running - rho_rebuilt| seen at a rebuild). */
+ewald_status ewald_state_offsets(const ewald_batch *b, int walker, size_t *hdr, size_t *pos,
+                                 size_t *rho);
+
+void ewald_batch_destroy(ewald_batch *b);
+
+/* Energies of all walkers (Sec. 2.2, Eqs. (2)-(6)).
+ *   pos      device [total][dim] Cartesian positions (ewald_batch_layout order)
+ *   state    device, ewald_batch_layout bytes; (re)initialised: wrapped
+ *            positions, rho in FP64, counters zeroed, no pending move
+ *   energy   device [n_walkers] out
+ *   jastrow  device [n_walkers] out, or NULL */
+ewald_status ewald_energy_batch(ewald_batch *b, const double *pos, void *state, double *energy,
+                                double *jastrow, void *stream);
+
+/* Energy change of one proposed single-particle move per walker (Sec. 2.1).
+ *   k        device [n_walkers] index of the moved particle in [0, n_mobile)
+ *   new_pos  device [n_walkers][dim] Cartesian proposal (any periodic image)
+ *   delta    device [n_walkers] out, E(new) - E(old)
+ *   djastrow device [n_walkers] out, J(new) - J(old), or NULL
+ * Records the move as pending in the state (replacing an earlier pending
+ * move); rho and positions are unchanged.  E_STATE before ewald_energy_batch
+ * on this state buffer. */
+ewald_status ewald_move_delta_batch(ewald_batch *b, void *state, const int32_t *k,
+                                    const double *new_pos, double *delta, double *djastrow,
+                                    void *stream);
+
+/* Apply (accept[w] != 0) or drop (accept[w] == 0) each walker's pending move:
+ * rho <- rho + delta in FP64, r_k <- r', counters; in the FP32-mixed form a
+ * walker reaching refresh_every accepted moves gets rho rebuilt from its
+ * positions in FP64.  E_STATE if no move is pending. */
+ewald_status ewald_accept_batch(ewald_batch *b, void *state, const uint8_t *accept, void *stream);
+
+/* n_steps consecutive proposals per walker in one launch, rho kept on chip.
+ * Same results as n_steps pairs of ewald_move_delta_batch + ewald_accept_batch
+ * (accept decisions must therefore be known in advance, as when the Ewald
+ * energy is evaluated after a sweep of moves).
+ *   k [n_steps][n_walkers], new_pos [n_steps][n_walkers][dim],
+ *   accept [n_steps][n_walkers], delta/djastrow [n_steps][n_walkers] (djastrow
+ *   may be NULL); all device.  E_STATE before ewald_energy_batch. */
+ewald_status ewald_run_moves_batch(ewald_batch *b, void *state, int n_steps, const int32_t *k,
+                                   const double *new_pos, const uint8_t *accept, double *delta,
+                                   double *djastrow, void *stream);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char *ewald_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EWALD_H */

@@ -1,0 +1,745 @@
+// Host side of libewald: argument validation, the FP64 set-up tables of a
+// periodic cell (paper Sec. 2.2; Sec. 6.1 keeps these tables in double
+// precision), walker-batch layout and the C ABI entry points.
+//
+// Nothing here touches a GPU until ewald_batch_create uploads the tables, so
+// every validation path and every table can be checked on a machine without
+// one.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ewald.h"
+#include "ewald_internal.h"
+
+using namespace ewald;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ewald_status fail(ewald_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+// 3x3 helpers on row-major arrays; a 2D cell lives in the upper-left 2x2
+// block with the rest zero.
+double det_n(const double* a, int dim) {
+  if (dim == 2) return a[0] * a[4] - a[1] * a[3];
+  return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+         a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+
+void inverse_n(const double* a, int dim, double* inv) {
+  std::fill(inv, inv + 9, 0.0);
+  double d = det_n(a, dim);
+  if (dim == 2) {
+    inv[0] = a[4] / d;
+    inv[1] = -a[1] / d;
+    inv[3] = -a[3] / d;
+    inv[4] = a[0] / d;
+    return;
+  }
+  inv[0] = (a[4] * a[8] - a[5] * a[7]) / d;
+  inv[1] = (a[2] * a[7] - a[1] * a[8]) / d;
+  inv[2] = (a[1] * a[5] - a[2] * a[4]) / d;
+  inv[3] = (a[5] * a[6] - a[3] * a[8]) / d;
+  inv[4] = (a[0] * a[8] - a[2] * a[6]) / d;
+  inv[5] = (a[2] * a[3] - a[0] * a[5]) / d;
+  inv[6] = (a[3] * a[7] - a[4] * a[6]) / d;
+  inv[7] = (a[1] * a[6] - a[0] * a[7]) / d;
+  inv[8] = (a[0] * a[4] - a[1] * a[3]) / d;
+}
+
+double wrap01(double x) {
+  double f = x - std::floor(x);
+  return f >= 1.0 ? 0.0 : f;
+}
+
+// Minimum over f in the box [c - 1/2, c + 1/2]^dim of f^T M f, M = A A^T the
+// Gram matrix: the squared distance from the origin to the cell-shaped
+// parallelepiped centred on the lattice point c.  Exact: the minimiser of a
+// convex quadratic over a box has each coordinate either at a bound or
+// stationary, so every free/lower/upper pattern is solved and the feasible
+// ones compared.
+double box_min_dist2(const double* M, int dim, const int* c) {
+  double best = INFINITY;
+  int patterns = 1;
+  for (int d = 0; d < dim; ++d) patterns *= 3;
+  for (int pat = 0; pat < patterns; ++pat) {
+    int code[3] = {0, 0, 0};
+    int t = pat;
+    for (int d = 0; d < dim; ++d) {
+      code[d] = t % 3;  // 0 free, 1 lower bound, 2 upper bound
+      t /= 3;
+    }
+    double x[3] = {0, 0, 0};
+    int fr[3], nf = 0;
+    for (int d = 0; d < dim; ++d) {
+      if (code[d] == 1) x[d] = c[d] - 0.5;
+      else if (code[d] == 2) x[d] = c[d] + 0.5;
+      else fr[nf++] = d;
+    }
+    if (nf > 0) {
+      // solve M_FF x_F = -M_FX x_X by Gaussian elimination
+      double m[3][4];
+      for (int i = 0; i < nf; ++i) {
+        double rhs = 0;
+        for (int d = 0; d < dim; ++d)
+          if (code[d] != 0) rhs -= M[fr[i] * 3 + d] * x[d];
+        for (int j = 0; j < nf; ++j) m[i][j] = M[fr[i] * 3 + fr[j]];
+        m[i][nf] = rhs;
+      }
+      bool ok = true;
+      for (int i = 0; i < nf && ok; ++i) {
+        int piv = i;
+        for (int r = i + 1; r < nf; ++r)
+          if (std::fabs(m[r][i]) > std::fabs(m[piv][i])) piv = r;
+        if (std::fabs(m[piv][i]) < 1e-300) { ok = false; break; }
+        for (int j = 0; j <= nf; ++j) std::swap(m[i][j], m[piv][j]);
+        for (int r = 0; r < nf; ++r) {
+          if (r == i) continue;
+          double f = m[r][i] / m[i][i];
+          for (int j = i; j <= nf; ++j) m[r][j] -= f * m[i][j];
+        }
+      }
+      if (!ok) continue;
+      bool feasible = true;
+      for (int i = 0; i < nf; ++i) {
+        double v = m[i][nf] / m[i][i];
+        if (v < c[fr[i]] - 0.5 - 1e-12 || v > c[fr[i]] + 0.5 + 1e-12) feasible = false;
+        x[fr[i]] = v;
+      }
+      if (!feasible) continue;
+    }
+    double q = 0;
+    for (int i = 0; i < dim; ++i)
+      for (int j = 0; j < dim; ++j) q += x[i] * M[i * 3 + j] * x[j];
+    best = std::min(best, q);
+  }
+  return best;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+struct ewald_sys {
+  int dim = 3;
+  int n_mobile = 0, n_fixed = 0;
+  int n_g = 0, n_seg = 0, n_shells = 0;
+  int precision = 0, refresh_every = 0;
+  bool has_jastrow = false;
+  double r_ins = 0, e_const = 0;
+  DevSys dev{};                      // scalars; device pointers once uploaded
+  std::vector<uint32_t> seg_n;       // [n_seg]
+  std::vector<int32_t> slot_n;       // slot-planar [n_slots][3]
+  std::vector<double> w, ja;         // slot-planar [n_slots]
+  std::vector<int32_t> shell;        // slot-planar, -1 for padding
+  std::vector<double> rho_fix;       // slot-planar [n_slots][2]
+  std::vector<double> fixed_s, fixed_q, mobile_q;
+  int device = -1;
+  void* d_block = nullptr;
+  DevSys dev_uploaded{};
+  std::mutex mu;
+
+  int n_slots() const { return n_seg * SEG; }
+  ~ewald_sys() {
+    if (d_block) dev_free(d_block);
+  }
+};
+
+struct ewald_batch {
+  std::vector<ewald_sys*> sys;
+  std::vector<int> walker_sys;
+  std::vector<DevWalker> walkers;
+  std::vector<size_t> pos_offsets;
+  size_t state_bytes = 0;
+  void* d_sys = nullptr;
+  void* d_walk = nullptr;
+  LaunchBatch lb{};
+  std::mutex mu;
+  std::map<const void*, int> phase;  // state buffer -> 1 ready, 2 move pending
+  ~ewald_batch() {
+    if (d_sys) dev_free(d_sys);
+    if (d_walk) dev_free(d_walk);
+  }
+};
+
+extern "C" {
+
+const char* ewald_last_error(void) { return g_last_error.c_str(); }
+
+ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
+  if (!out) return fail(EWALD_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(EWALD_E_ARG, "desc is NULL");
+  const int dim = desc->dim;
+  if (dim != 2 && dim != 3) return fail(EWALD_E_ARG, "dim must be 2 or 3");
+  if (desc->n_mobile < 1) return fail(EWALD_E_ARG, "n_mobile must be >= 1");
+  if (desc->n_fixed < 0) return fail(EWALD_E_ARG, "n_fixed must be >= 0");
+  if (desc->n_mobile + desc->n_fixed > EWALD_MAX_PARTICLES)
+    return fail(EWALD_E_ARG, "n_mobile + n_fixed exceeds EWALD_MAX_PARTICLES");
+  if (!desc->mobile_q) return fail(EWALD_E_ARG, "mobile_q is NULL");
+  if (desc->n_fixed > 0 && (!desc->fixed_pos || !desc->fixed_q))
+    return fail(EWALD_E_ARG, "fixed_pos/fixed_q NULL with n_fixed > 0");
+  if (desc->precision != EWALD_FP64 && desc->precision != EWALD_FP32_MIXED)
+    return fail(EWALD_E_ARG, "unknown precision");
+  if (desc->refresh_every < 0) return fail(EWALD_E_ARG, "refresh_every must be >= 0");
+  if (desc->n_jastrow < 0) return fail(EWALD_E_ARG, "n_jastrow must be >= 0");
+  if (desc->n_jastrow > 0 && !desc->jastrow_a) return fail(EWALD_E_ARG, "jastrow_a is NULL");
+  for (int i = 0; i < desc->n_mobile; ++i)
+    if (!is_fin(desc->mobile_q[i])) return fail(EWALD_E_ARG, "non-finite mobile charge");
+  for (int i = 0; i < desc->n_fixed; ++i) {
+    if (!is_fin(desc->fixed_q[i])) return fail(EWALD_E_ARG, "non-finite fixed charge");
+    for (int d = 0; d < dim; ++d)
+      if (!is_fin(desc->fixed_pos[i * dim + d])) return fail(EWALD_E_ARG, "non-finite fixed position");
+  }
+  for (int i = 0; i < desc->n_jastrow; ++i)
+    if (!is_fin(desc->jastrow_a[i])) return fail(EWALD_E_ARG, "non-finite Jastrow coefficient");
+
+  // ---- lattice ----
+  double A[9] = {0};
+  for (int i = 0; i < dim; ++i)
+    for (int j = 0; j < dim; ++j) {
+      A[i * 3 + j] = desc->lattice[i][j];
+      if (!is_fin(A[i * 3 + j])) return fail(EWALD_E_LATTICE, "non-finite lattice");
+    }
+  double norms[3] = {0, 0, 0};
+  double prod = 1;
+  for (int i = 0; i < dim; ++i) {
+    for (int j = 0; j < dim; ++j) norms[i] += A[i * 3 + j] * A[i * 3 + j];
+    norms[i] = std::sqrt(norms[i]);
+    prod *= norms[i];
+  }
+  const double det = det_n(A, dim);
+  if (!(prod > 0) || std::fabs(det) <= 1e-10 * prod) return fail(EWALD_E_LATTICE, "singular lattice");
+  const double measure = std::fabs(det);  // volume (3D) or area (2D)
+  double Ainv[9];
+  inverse_n(A, dim, Ainv);
+  // reciprocal vectors b_i = 2 pi (A^-T)_i: B[i][e] = 2 pi Ainv[e][i]
+  double Bm[9] = {0};
+  double bnorm[3] = {0, 0, 0};
+  for (int i = 0; i < dim; ++i) {
+    for (int e = 0; e < dim; ++e) {
+      Bm[i * 3 + e] = 2 * kPi * Ainv[e * 3 + i];
+      bnorm[i] += Bm[i * 3 + e] * Bm[i * 3 + e];
+    }
+    bnorm[i] = std::sqrt(bnorm[i]);
+  }
+  double M[9] = {0};  // Gram matrix A A^T
+  for (int i = 0; i < dim; ++i)
+    for (int j = 0; j < dim; ++j)
+      for (int e = 0; e < dim; ++e) M[i * 3 + j] += A[i * 3 + e] * A[j * 3 + e];
+
+  // inscribed radius: half the shortest nonzero lattice vector.  A vector of
+  // length <= l has |n_i| <= l |b_i| / 2 pi.
+  double shortest = *std::min_element(norms, norms + dim);
+  int bound[3] = {0, 0, 0};
+  for (int i = 0; i < dim; ++i) bound[i] = int(std::floor(shortest * bnorm[i] / (2 * kPi))) + 1;
+  for (int i = -bound[0]; i <= bound[0]; ++i)
+    for (int j = -bound[1]; j <= bound[1]; ++j)
+      for (int k = -(dim == 3 ? bound[2] : 0); k <= (dim == 3 ? bound[2] : 0); ++k) {
+        if (i == 0 && j == 0 && k == 0) continue;
+        double v2 = 0;
+        for (int e = 0; e < dim; ++e) {
+          double v = i * A[e] + j * A[3 + e] + k * A[6 + e];
+          v2 += v * v;
+        }
+        shortest = std::min(shortest, std::sqrt(v2));
+      }
+  const double r_ins = 0.5 * shortest;
+
+  const double alpha = desc->alpha, r_cut = desc->r_cut, g_cut = desc->g_cut;
+  if (!is_fin(alpha) || !(alpha > 0)) return fail(EWALD_E_ARG, "alpha must be > 0");
+  if (!is_fin(r_cut) || !(r_cut > 0)) return fail(EWALD_E_RCUT, "r_cut must be > 0");
+  if (r_cut > r_ins) return fail(EWALD_E_RCUT, "r_cut exceeds the inscribed radius (half the shortest lattice vector)");
+  if (!is_fin(g_cut) || !(g_cut > 0)) return fail(EWALD_E_GCUT, "g_cut must be > 0");
+
+  // ---- G set: nonzero n with |n B| <= g_cut; the ball spans |n_d| <= g_cut |a_d| / 2 pi ----
+  int nb[3] = {0, 0, 0};
+  for (int d = 0; d < dim; ++d) {
+    double ext = g_cut * norms[d] / (2 * kPi);
+    if (ext > EWALD_MAX_NRED) return fail(EWALD_E_GCUT, "g_cut too large for the reduced-index range");
+    nb[d] = int(std::ceil(ext));
+  }
+  const double lim = g_cut * g_cut * (1.0 + 1e-12);
+  struct GV { int n[3]; double g2; };
+  std::vector<GV> half;
+  for (int i = -nb[0]; i <= nb[0]; ++i)
+    for (int j = -nb[1]; j <= nb[1]; ++j)
+      for (int k = -(dim == 3 ? nb[2] : 0); k <= (dim == 3 ? nb[2] : 0); ++k) {
+        int n[3] = {i, j, k};
+        // half set: first nonzero reduced coordinate positive
+        int first = 0;
+        for (int d = 0; d < dim; ++d)
+          if (n[d] != 0) { first = n[d]; break; }
+        if (first <= 0) continue;
+        double g2 = 0;
+        for (int e = 0; e < dim; ++e) {
+          double ge = 0;
+          for (int d = 0; d < dim; ++d) ge += n[d] * Bm[d * 3 + e];
+          g2 += ge * ge;
+        }
+        if (g2 <= lim) half.push_back({{i, j, k}, g2});
+      }
+  if (half.empty()) return fail(EWALD_E_GCUT, "no reciprocal lattice vector within g_cut");
+  const int last = dim - 1;
+  // columns: equal leading coordinates, runs along the last coordinate
+  std::sort(half.begin(), half.end(), [&](const GV& a, const GV& b) {
+    for (int d = 0; d < dim; ++d)
+      if (a.n[d] != b.n[d]) return a.n[d] < b.n[d];
+    return false;
+  });
+  struct Seg { int n[3]; };
+  std::vector<Seg> segs;
+  std::vector<std::vector<double>> seg_g2;  // g2 per slot (NaN: padding)
+  for (size_t a = 0; a < half.size();) {
+    size_t b = a;
+    while (b < half.size()) {
+      bool same = true;
+      for (int d = 0; d < last; ++d) same = same && half[b].n[d] == half[a].n[d];
+      if (!same) break;
+      ++b;
+    }
+    // [a, b) is one column; its last coordinates are consecutive (a convex set
+    // meets a line in an interval)
+    for (size_t t = a + 1; t < b; ++t)
+      if (half[t].n[last] != half[t - 1].n[last] + 1)
+        return fail(EWALD_E_GCUT, "internal: non-contiguous G column");
+    for (size_t t = a; t < b; t += SEG) {
+      Seg s;
+      std::copy(half[t].n, half[t].n + 3, s.n);
+      segs.push_back(s);
+      std::vector<double> g2(SEG, std::nan(""));
+      for (int j = 0; j < SEG && t + j < b; ++j) g2[j] = half[t + j].g2;
+      seg_g2.push_back(g2);
+    }
+    a = b;
+  }
+  const int n_seg = int(segs.size());
+  if (n_seg > EWALD_MAX_SEGMENTS) return fail(EWALD_E_GCUT, "G set exceeds EWALD_MAX_SEGMENTS");
+  const int n_slots = n_seg * SEG;
+
+  // shells of equal |G|^2 (relative tolerance 1e-9), ascending
+  std::vector<double> g2s;
+  for (auto& g : half) g2s.push_back(g.g2);
+  std::sort(g2s.begin(), g2s.end());
+  std::vector<double> shells;
+  for (double v : g2s)
+    if (shells.empty() || v > shells.back() * (1.0 + 1e-9)) shells.push_back(v);
+
+  std::unique_ptr<ewald_sys> S(new ewald_sys());
+  S->dim = dim;
+  S->n_mobile = desc->n_mobile;
+  S->n_fixed = desc->n_fixed;
+  S->n_g = int(half.size());
+  S->n_seg = n_seg;
+  S->n_shells = int(shells.size());
+  S->precision = desc->precision;
+  S->refresh_every = desc->refresh_every;
+  S->has_jastrow = desc->n_jastrow > 0;
+  S->r_ins = r_ins;
+  S->seg_n.resize(n_seg);
+  S->slot_n.assign(size_t(n_slots) * 3, 0);
+  S->w.assign(n_slots, 0.0);
+  S->ja.assign(n_slots, 0.0);
+  S->shell.assign(n_slots, -1);
+  S->rho_fix.assign(size_t(n_slots) * 2, 0.0);
+  int nmax[3] = {0, 0, 0};
+  for (auto& g : half)
+    for (int d = 0; d < dim; ++d) nmax[d] = std::max(nmax[d], std::abs(g.n[d]));
+  for (int s = 0; s < n_seg; ++s) {
+    const Seg& sg = segs[s];
+    S->seg_n[s] = pack_n(sg.n[0], sg.n[1], sg.n[2]);
+    for (int j = 0; j < SEG; ++j) {
+      const size_t slot = size_t(j) * n_seg + s;
+      int n[3] = {sg.n[0], sg.n[1], sg.n[2]};
+      n[last] += j;
+      for (int d = 0; d < 3; ++d) S->slot_n[slot * 3 + d] = n[d];
+      const double g2 = seg_g2[s][j];
+      if (std::isnan(g2)) continue;  // padding slot: weight 0
+      const double g = std::sqrt(g2);
+      S->w[slot] = (dim == 3) ? 4 * kPi / measure * std::exp(-g2 / (4 * alpha * alpha)) / g2
+                              : 2 * kPi / measure * std::erfc(g / (2 * alpha)) / g;
+      int sh = int(std::lower_bound(shells.begin(), shells.end(), g2 * (1.0 - 1e-9)) - shells.begin());
+      S->shell[slot] = sh;
+      S->ja[slot] = (sh < desc->n_jastrow) ? desc->jastrow_a[sh] : 0.0;
+    }
+  }
+
+  // ---- charges, fixed ions ----
+  S->mobile_q.assign(desc->mobile_q, desc->mobile_q + desc->n_mobile);
+  S->fixed_q.assign(desc->fixed_q, desc->fixed_q + desc->n_fixed);
+  S->fixed_s.assign(size_t(desc->n_fixed) * dim, 0.0);
+  for (int I = 0; I < desc->n_fixed; ++I)
+    for (int d = 0; d < dim; ++d) {
+      double v = 0;
+      for (int e = 0; e < dim; ++e) v += desc->fixed_pos[I * dim + e] * Ainv[e * 3 + d];
+      S->fixed_s[I * dim + d] = wrap01(v);
+    }
+  for (int I = 0; I < desc->n_fixed; ++I) {
+    for (int slot = 0; slot < n_slots; ++slot) {
+      double x = 0;
+      for (int d = 0; d < dim; ++d) x += S->slot_n[slot * 3 + d] * S->fixed_s[I * dim + d];
+      x -= std::nearbyint(x);
+      S->rho_fix[2 * slot] += S->fixed_q[I] * std::cos(2 * kPi * x);
+      S->rho_fix[2 * slot + 1] += S->fixed_q[I] * std::sin(2 * kPi * x);
+    }
+  }
+
+  // ---- minimum-image candidates: lattice points c != 0 whose cell-shaped box
+  // comes within r_cut of the origin (one of each +-pair) ----
+  std::vector<double> cand;
+  const int cr = 3;
+  for (int i = -cr; i <= cr; ++i)
+    for (int j = -cr; j <= cr; ++j)
+      for (int k = -(dim == 3 ? cr : 0); k <= (dim == 3 ? cr : 0); ++k) {
+        int c[3] = {i, j, k};
+        int first = 0;
+        for (int d = 0; d < dim; ++d)
+          if (c[d] != 0) { first = c[d]; break; }
+        if (first <= 0) continue;
+        // a box that only touches the cutoff sphere holds no point strictly
+        // inside it (the real-space test is |r| < r_cut)
+        double d2 = box_min_dist2(M, dim, c);
+        if (d2 < r_cut * r_cut * (1.0 - 1e-12)) {
+          bool edge = false;
+          for (int d = 0; d < dim; ++d) edge = edge || std::abs(c[d]) == cr;
+          if (edge) return fail(EWALD_E_RCUT, "internal: candidate search range too small");
+          double v[3] = {0, 0, 0}, v2 = 0;
+          for (int e = 0; e < dim; ++e) {
+            for (int d = 0; d < dim; ++d) v[e] += c[d] * A[d * 3 + e];
+            v2 += v[e] * v[e];
+          }
+          cand.insert(cand.end(), {v[0], v[1], v[2], v2});
+        }
+      }
+  const int n_cand = int(cand.size() / 4);
+  if (n_cand > MAX_CAND) return fail(EWALD_E_RCUT, "too many minimum-image candidates for this cell");
+
+  // ---- constants ----
+  double q2 = 0, qt = 0;
+  for (double q : S->mobile_q) { q2 += q * q; qt += q; }
+  for (double q : S->fixed_q) { q2 += q * q; qt += q; }
+  const double e_self = -alpha / std::sqrt(kPi) * q2;
+  const double e_bg = (dim == 3) ? -kPi / (2 * measure * alpha * alpha) * qt * qt
+                                 : -std::sqrt(kPi) / (measure * alpha) * qt * qt;
+  // ion-ion real-space pairs (the ions never move); images by brute force
+  double e_ii = 0;
+  for (int I = 0; I < desc->n_fixed; ++I)
+    for (int J = I + 1; J < desc->n_fixed; ++J) {
+      double f[3] = {0, 0, 0};
+      for (int d = 0; d < dim; ++d) {
+        f[d] = S->fixed_s[I * dim + d] - S->fixed_s[J * dim + d];
+        f[d] -= std::nearbyint(f[d]);
+      }
+      double best = INFINITY;
+      for (int i = -2; i <= 2; ++i)
+        for (int j = -2; j <= 2; ++j)
+          for (int k = -(dim == 3 ? 2 : 0); k <= (dim == 3 ? 2 : 0); ++k) {
+            int c[3] = {i, j, k};
+            double r2 = 0;
+            for (int e = 0; e < dim; ++e) {
+              double v = 0;
+              for (int d = 0; d < dim; ++d) v += (f[d] + c[d]) * A[d * 3 + e];
+              r2 += v * v;
+            }
+            best = std::min(best, r2);
+          }
+      if (best < r_cut * r_cut) {
+        double r = std::sqrt(best);
+        e_ii += S->fixed_q[I] * S->fixed_q[J] * std::erfc(alpha * r) / r;
+      }
+    }
+  S->e_const = e_self + e_bg + e_ii;
+
+  DevSys& D = S->dev;
+  D.dim = dim;
+  D.n_mobile = S->n_mobile;
+  D.n_fixed = S->n_fixed;
+  D.n_seg = n_seg;
+  for (int d = 0; d < 3; ++d) D.nmax[d] = nmax[d];
+  D.nm = std::max(nmax[0], std::max(nmax[1], nmax[2]));
+  D.n_cand = n_cand;
+  D.has_jastrow = S->has_jastrow ? 1 : 0;
+  D.refresh_every = S->refresh_every;
+  D.precision = S->precision;
+  std::copy(A, A + 9, D.A);
+  std::copy(Ainv, Ainv + 9, D.Ainv);
+  D.alpha = alpha;
+  D.rc2 = r_cut * r_cut;
+  D.e_const = S->e_const;
+  for (int c = 0; c < n_cand; ++c)
+    for (int t = 0; t < 4; ++t) D.cand[c][t] = cand[c * 4 + t];
+  *out = S.release();
+  return EWALD_OK;
+} catch (const std::bad_alloc&) {
+  return fail(EWALD_E_NOMEM, "host allocation failed");
+} catch (...) {
+  return fail(EWALD_E_ARG, "unexpected error in ewald_setup");
+}
+
+ewald_status ewald_sys_query(const ewald_sys* s, int* n_g, int* n_slots, int* n_shells,
+                             double* r_inscribed, double* e_const) {
+  if (!s) return fail(EWALD_E_ARG, "sys is NULL");
+  if (n_g) *n_g = s->n_g;
+  if (n_slots) *n_slots = s->n_slots();
+  if (n_shells) *n_shells = s->n_shells;
+  if (r_inscribed) *r_inscribed = s->r_ins;
+  if (e_const) *e_const = s->e_const;
+  return EWALD_OK;
+}
+
+ewald_status ewald_sys_tables(const ewald_sys* s, int32_t* n, double* weight, double* jastrow,
+                              int32_t* shell) {
+  if (!s) return fail(EWALD_E_ARG, "sys is NULL");
+  const size_t ns = size_t(s->n_slots());
+  if (n) std::memcpy(n, s->slot_n.data(), ns * 3 * sizeof(int32_t));
+  if (weight) std::memcpy(weight, s->w.data(), ns * sizeof(double));
+  if (jastrow) std::memcpy(jastrow, s->ja.data(), ns * sizeof(double));
+  if (shell) std::memcpy(shell, s->shell.data(), ns * sizeof(int32_t));
+  return EWALD_OK;
+}
+
+ewald_status ewald_sys_candidates(const ewald_sys* s, int* n_cand, double* cand) {
+  if (!s) return fail(EWALD_E_ARG, "sys is NULL");
+  if (n_cand) *n_cand = s->dev.n_cand;
+  if (cand)
+    for (int c = 0; c < s->dev.n_cand; ++c)
+      for (int e = 0; e < 3; ++e) cand[c * 3 + e] = s->dev.cand[c][e];
+  return EWALD_OK;
+}
+
+void ewald_sys_destroy(ewald_sys* s) { delete s; }
+
+}  // extern "C"
+
+namespace {
+
+// Copy one system's tables to the current device (once).
+ewald_status upload_sys(ewald_sys* s, int device) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->d_block) {
+    if (s->device != device) return fail(EWALD_E_ARG, "system already uploaded to another device");
+    return EWALD_OK;
+  }
+  const size_t ns = size_t(s->n_slots());
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t o_seg = take(s->seg_n.size() * 4);
+  const size_t o_w = take(ns * 8);
+  const size_t o_ja = take(ns * 8);
+  const size_t o_rf = take(ns * 16);
+  const size_t o_fs = take(std::max<size_t>(1, s->fixed_s.size()) * 8);
+  const size_t o_fq = take(std::max<size_t>(1, s->fixed_q.size()) * 8);
+  const size_t o_mq = take(s->mobile_q.size() * 8);
+  std::vector<char> host(off, 0);
+  std::memcpy(host.data() + o_seg, s->seg_n.data(), s->seg_n.size() * 4);
+  std::memcpy(host.data() + o_w, s->w.data(), ns * 8);
+  std::memcpy(host.data() + o_ja, s->ja.data(), ns * 8);
+  std::memcpy(host.data() + o_rf, s->rho_fix.data(), ns * 16);
+  if (!s->fixed_s.empty()) std::memcpy(host.data() + o_fs, s->fixed_s.data(), s->fixed_s.size() * 8);
+  if (!s->fixed_q.empty()) std::memcpy(host.data() + o_fq, s->fixed_q.data(), s->fixed_q.size() * 8);
+  std::memcpy(host.data() + o_mq, s->mobile_q.data(), s->mobile_q.size() * 8);
+  void* d = nullptr;
+  int rc = dev_alloc(&d, off);
+  if (rc) return fail(EWALD_E_NOMEM, std::string("device allocation failed: ") + dev_error_string(rc));
+  rc = dev_upload(d, host.data(), off);
+  if (rc) {
+    dev_free(d);
+    return fail(EWALD_E_HIP, std::string("table upload failed: ") + dev_error_string(rc));
+  }
+  char* base = static_cast<char*>(d);
+  DevSys D = s->dev;
+  D.seg_n = reinterpret_cast<const uint32_t*>(base + o_seg);
+  D.w = reinterpret_cast<const double*>(base + o_w);
+  D.ja = s->has_jastrow ? reinterpret_cast<const double*>(base + o_ja) : nullptr;
+  D.rho_fix = reinterpret_cast<const double*>(base + o_rf);
+  D.fixed_s = reinterpret_cast<const double*>(base + o_fs);
+  D.fixed_q = reinterpret_cast<const double*>(base + o_fq);
+  D.mobile_q = reinterpret_cast<const double*>(base + o_mq);
+  s->dev_uploaded = D;
+  s->d_block = d;
+  s->device = device;
+  return EWALD_OK;
+}
+
+ewald_status check_state(ewald_batch* b, const void* state, int need, int set) {
+  std::lock_guard<std::mutex> lk(b->mu);
+  auto it = b->phase.find(state);
+  int ph = it == b->phase.end() ? 0 : it->second;
+  if (need == 1 && ph < 1) return fail(EWALD_E_STATE, "state not initialised: call ewald_energy_batch first");
+  if (need == 2 && ph != 2) return fail(EWALD_E_STATE, "no pending move: call ewald_move_delta_batch first");
+  if (need == 3 && ph != 1)
+    return fail(EWALD_E_STATE, ph == 0 ? "state not initialised: call ewald_energy_batch first"
+                                       : "a move is pending: accept or reject it first");
+  if (set >= 0) b->phase[state] = set;
+  return EWALD_OK;
+}
+
+ewald_status launch_status(int rc, const char* what) {
+  if (rc == 0) return EWALD_OK;
+  return fail(EWALD_E_HIP, std::string(what) + " launch failed: " + dev_error_string(rc));
+}
+
+}  // namespace
+
+extern "C" {
+
+ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* walker_sys,
+                                int n_walkers, ewald_batch** out) try {
+  if (!out) return fail(EWALD_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!sys || n_sys < 1) return fail(EWALD_E_ARG, "need at least one system");
+  if (!walker_sys || n_walkers < 1) return fail(EWALD_E_ARG, "need at least one walker");
+  for (int i = 0; i < n_sys; ++i)
+    if (!sys[i]) return fail(EWALD_E_ARG, "NULL system");
+  for (int i = 1; i < n_sys; ++i) {
+    if (sys[i]->dim != sys[0]->dim) return fail(EWALD_E_ARG, "systems of a batch must share dim");
+    if (sys[i]->precision != sys[0]->precision)
+      return fail(EWALD_E_ARG, "systems of a batch must share precision");
+  }
+  for (int w = 0; w < n_walkers; ++w)
+    if (walker_sys[w] < 0 || walker_sys[w] >= n_sys) return fail(EWALD_E_ARG, "walker_sys out of range");
+  int device = 0;
+  int rc = dev_current(&device);
+  if (rc) return fail(EWALD_E_HIP, std::string("no HIP device: ") + dev_error_string(rc));
+  for (int i = 0; i < n_sys; ++i) {
+    ewald_status st = upload_sys(sys[i], device);
+    if (st != EWALD_OK) return st;
+  }
+  std::unique_ptr<ewald_batch> B(new ewald_batch());
+  B->sys.assign(sys, sys + n_sys);
+  B->walker_sys.assign(walker_sys, walker_sys + n_walkers);
+  const int dim = sys[0]->dim;
+  B->pos_offsets.assign(size_t(n_walkers) + 1, 0);
+  size_t off = 0;
+  for (int w = 0; w < n_walkers; ++w) {
+    const ewald_sys* s = sys[walker_sys[w]];
+    DevWalker dw;
+    dw.sys = walker_sys[w];
+    dw.n_mobile = s->n_mobile;
+    dw.state_off = (long long)off;
+    dw.pos_off = (long long)B->pos_offsets[w];
+    B->walkers.push_back(dw);
+    B->pos_offsets[w + 1] = B->pos_offsets[w] + size_t(s->n_mobile);
+    off += walker_state_bytes(s->n_mobile, dim, s->n_seg);
+  }
+  B->state_bytes = off;
+  std::vector<DevSys> ds;
+  LaunchBatch& L = B->lb;
+  L.n_walkers = n_walkers;
+  L.dim = dim;
+  L.mixed = sys[0]->precision == EWALD_FP32_MIXED ? 1 : 0;
+  for (int i = 0; i < n_sys; ++i) {
+    ds.push_back(sys[i]->dev_uploaded);
+    L.has_jastrow |= sys[i]->has_jastrow ? 1 : 0;
+    L.max_n_seg = std::max(L.max_n_seg, sys[i]->n_seg);
+    L.max_nm = std::max(L.max_nm, sys[i]->dev.nm);
+    L.max_particles = std::max(L.max_particles, sys[i]->n_mobile);
+    L.max_fixed = std::max(L.max_fixed, sys[i]->n_fixed);
+    L.refresh_every = std::max(L.refresh_every, L.mixed ? sys[i]->refresh_every : 0);
+  }
+  rc = dev_alloc(&B->d_sys, ds.size() * sizeof(DevSys));
+  if (rc) return fail(EWALD_E_NOMEM, "device allocation failed");
+  rc = dev_alloc(&B->d_walk, B->walkers.size() * sizeof(DevWalker));
+  if (rc) return fail(EWALD_E_NOMEM, "device allocation failed");
+  rc = dev_upload(B->d_sys, ds.data(), ds.size() * sizeof(DevSys));
+  if (!rc) rc = dev_upload(B->d_walk, B->walkers.data(), B->walkers.size() * sizeof(DevWalker));
+  if (rc) return fail(EWALD_E_HIP, std::string("upload failed: ") + dev_error_string(rc));
+  L.d_sys = static_cast<const DevSys*>(B->d_sys);
+  L.d_walk = static_cast<const DevWalker*>(B->d_walk);
+  *out = B.release();
+  return EWALD_OK;
+} catch (const std::bad_alloc&) {
+  return fail(EWALD_E_NOMEM, "host allocation failed");
+} catch (...) {
+  return fail(EWALD_E_ARG, "unexpected error in ewald_batch_create");
+}
+
+ewald_status ewald_batch_layout(const ewald_batch* b, size_t* pos_offsets, size_t* state_bytes) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (pos_offsets) std::copy(b->pos_offsets.begin(), b->pos_offsets.end(), pos_offsets);
+  if (state_bytes) *state_bytes = b->state_bytes;
+  return EWALD_OK;
+}
+
+ewald_status ewald_state_offsets(const ewald_batch* b, int walker, size_t* hdr, size_t* pos,
+                                 size_t* rho) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (walker < 0 || walker >= int(b->walkers.size())) return fail(EWALD_E_ARG, "walker out of range");
+  const DevWalker& w = b->walkers[walker];
+  const size_t base = size_t(w.state_off);
+  if (hdr) *hdr = base;
+  if (pos) *pos = base + HDR_BYTES;
+  if (rho) *rho = base + HDR_BYTES + walker_pos_bytes(w.n_mobile, b->lb.dim);
+  return EWALD_OK;
+}
+
+void ewald_batch_destroy(ewald_batch* b) { delete b; }
+
+ewald_status ewald_energy_batch(ewald_batch* b, const double* pos, void* state, double* energy,
+                                double* jastrow, void* stream) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (!pos || !state || !energy) return fail(EWALD_E_ARG, "pos, state and energy must be non-NULL");
+  int rc = launch_energy(b->lb, pos, static_cast<char*>(state), energy, jastrow, stream);
+  if (rc) return launch_status(rc, "energy");
+  return check_state(b, state, 0, 1);
+}
+
+ewald_status ewald_move_delta_batch(ewald_batch* b, void* state, const int32_t* k,
+                                    const double* new_pos, double* delta, double* djastrow,
+                                    void* stream) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (!state || !k || !new_pos || !delta) return fail(EWALD_E_ARG, "state, k, new_pos and delta must be non-NULL");
+  ewald_status st = check_state(b, state, 1, -1);
+  if (st != EWALD_OK) return st;
+  int rc = launch_delta(b->lb, static_cast<char*>(state), k, new_pos, delta, djastrow, stream);
+  if (rc) return launch_status(rc, "move_delta");
+  return check_state(b, state, 0, 2);
+}
+
+ewald_status ewald_accept_batch(ewald_batch* b, void* state, const uint8_t* accept, void* stream) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (!state || !accept) return fail(EWALD_E_ARG, "state and accept must be non-NULL");
+  ewald_status st = check_state(b, state, 2, -1);
+  if (st != EWALD_OK) return st;
+  int rc = launch_accept(b->lb, static_cast<char*>(state), accept, stream);
+  if (rc) return launch_status(rc, "accept");
+  return check_state(b, state, 0, 1);
+}
+
+ewald_status ewald_run_moves_batch(ewald_batch* b, void* state, int n_steps, const int32_t* k,
+                                   const double* new_pos, const uint8_t* accept, double* delta,
+                                   double* djastrow, void* stream) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (n_steps < 0) return fail(EWALD_E_ARG, "n_steps must be >= 0");
+  if (!state) return fail(EWALD_E_ARG, "state must be non-NULL");
+  ewald_status st = check_state(b, state, 3, -1);
+  if (st != EWALD_OK) return st;
+  if (n_steps == 0) return EWALD_OK;
+  if (!k || !new_pos || !accept || !delta)
+    return fail(EWALD_E_ARG, "k, new_pos, accept and delta must be non-NULL");
+  int rc = launch_run(b->lb, static_cast<char*>(state), n_steps, k, new_pos, accept, delta, djastrow, stream);
+  if (rc) return launch_status(rc, "run_moves");
+  return EWALD_OK;
+}
+
+}  // extern "C"

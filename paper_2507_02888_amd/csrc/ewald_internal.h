@@ -1,0 +1,113 @@
+// Internal layout shared by the host set-up (ewald_host.cpp) and the HIP
+// kernels (ewald_device.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#if defined(__HIPCC__) || defined(__HIP__)
+#define EW_HD __host__ __device__
+#else
+#define EW_HD
+#endif
+
+namespace ewald {
+
+constexpr int SEG = 4;            // G slots per segment: consecutive n along the last reduced index
+constexpr int BLOCK = 256;        // threads per workgroup of every kernel
+constexpr int MAX_CAND = 16;      // +-pairs of minimum-image candidate offsets
+constexpr int HDR_BYTES = 256;    // per-walker state header
+constexpr int MAX_SPT = 8;        // segments per thread held in registers (MAX_SEGMENTS / BLOCK)
+constexpr int TILE_P = 8;         // particles per phase-table tile when rebuilding rho
+
+// Per-walker state header (first bytes of the walker's state block).
+struct WalkerHdr {
+  int32_t counter;      // accepted moves since rho was last rebuilt
+  int32_t pending_k;    // -1: no pending move
+  int32_t n_accepts;
+  int32_t n_refresh;
+  double pending_s[3];  // wrapped fractional position of the pending move
+  double drift_max;     // max |rho_running - rho_rebuilt| (bits updated with atomicMax)
+};
+static_assert(sizeof(WalkerHdr) <= HDR_BYTES, "header too large");
+
+// One system as the kernels see it (lives in device memory).
+struct DevSys {
+  int dim;
+  int n_mobile;
+  int n_fixed;
+  int n_seg;            // segments of SEG slots
+  int nmax[3];          // largest |n_d| over the G set
+  int nm;               // max(nmax): phase tables hold n in [-nm, nm]
+  int n_cand;           // +-pairs of candidate offsets
+  int has_jastrow;
+  int refresh_every;
+  int precision;        // 0 FP64, 1 FP32-mixed
+  double A[9];          // lattice rows a_i (row-major 3x3)
+  double Ainv[9];       // s = r Ainv for row vectors
+  double alpha;
+  double rc2;           // r_cut^2
+  double e_const;       // E_self + E_background + fixed-ion real-space energy
+  double cand[MAX_CAND][4];  // (v_x, v_y, v_z, |v|^2) of one of each +-pair
+  // device tables (slot-planar: slot j of segment s lives at j * n_seg + s)
+  const uint32_t* seg_n;     // [n_seg] packed n of the segment's first slot (int8 x3)
+  const double* w;           // [SEG * n_seg] weight, 0 for padding
+  const double* ja;          // [SEG * n_seg] Jastrow coefficient, or nullptr
+  const double* rho_fix;     // [SEG * n_seg][2] fixed-ion structure factor
+  const double* fixed_s;     // [n_fixed][dim] wrapped fractional ion positions
+  const double* fixed_q;     // [n_fixed]
+  const double* mobile_q;    // [n_mobile]
+};
+
+struct DevWalker {
+  int sys;
+  int n_mobile;
+  long long state_off;  // byte offset of the walker's state block
+  long long pos_off;    // first row in the packed position input
+};
+
+EW_HD inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+EW_HD inline size_t walker_pos_bytes(int n_mobile, int dim) { return align256(size_t(n_mobile) * dim * 8); }
+EW_HD inline size_t walker_state_bytes(int n_mobile, int dim, int n_seg) {
+  return HDR_BYTES + walker_pos_bytes(n_mobile, dim) + align256(size_t(n_seg) * SEG * 16);
+}
+
+inline uint32_t pack_n(int a, int b, int c) {
+  return uint32_t(a & 0xff) | (uint32_t(b & 0xff) << 8) | (uint32_t(c & 0xff) << 16);
+}
+
+// ---- launch interface implemented in ewald_device.hip ----------------------
+
+struct LaunchBatch {
+  const DevSys* d_sys;      // device array [n_sys]
+  const DevWalker* d_walk;  // device array [n_walkers]
+  int n_walkers;
+  int dim;
+  int mixed;
+  int has_jastrow;          // any system with Jastrow coefficients
+  int max_n_seg;
+  int max_nm;
+  int max_particles;        // max n_mobile over systems
+  int max_fixed;
+  int refresh_every;        // max over systems (0: no rebuild kernel needed)
+};
+
+// Each returns 0 on success or the hipError_t of the failed launch.
+int launch_energy(const LaunchBatch& b, const double* pos, char* state, double* energy,
+                  double* jastrow, void* stream);
+int launch_delta(const LaunchBatch& b, char* state, const int32_t* k, const double* new_pos,
+                 double* delta, double* djastrow, void* stream);
+int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void* stream);
+int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k,
+               const double* new_pos, const uint8_t* accept, double* delta, double* djastrow,
+               void* stream);
+
+// Device memory helpers (ewald_device.hip); return 0 on success.
+int dev_alloc(void** p, size_t bytes);
+int dev_free(void* p);
+int dev_upload(void* dst, const void* src, size_t bytes);
+int dev_current(int* device);
+const char* dev_error_string(int code);
+
+}  // namespace ewald

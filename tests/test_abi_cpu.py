@@ -1,0 +1,214 @@
+"""CPU checks of the C-ABI library: exports, argument validation, and the host
+set-up tables (G set, half set, shells, weights, constants, minimum-image
+candidates) against the oracle.  No kernel is launched here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_02888_amd import ewald as ew
+from paper_2507_02888_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ewald.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ew.LIB_PATH):
+        from paper_2507_02888_amd import build
+        build.build()
+    return ew.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ewald_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_match_header(lib):
+    names = declared_functions()
+    assert set(names) == set(ew.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def make(cfg_id=1, **kw):
+    s = wl.config(cfg_id).systems[0]
+    return ew.System(s, **kw)
+
+
+def test_setup_and_query(lib):
+    s = make(5, jastrow_a=np.arange(200) * 1e-3)
+    info = s.info
+    assert info["n_g"] == 3577 and info["n_shells"] == 106
+    assert info["n_slots"] % 4 == 0 and info["n_slots"] >= info["n_g"]
+    L = s.system.length
+    assert abs(info["r_inscribed"] - 0.5 * math.sqrt(3.0) / 2 * (2 * s.system.measure) ** (1 / 3)) < 1e-9
+    assert info["r_inscribed"] >= 0.5 * L
+
+
+def status_of(fn):
+    with pytest.raises(ew.EwaldError) as e:
+        fn()
+    return e.value.status
+
+
+def test_validation_errors(lib):
+    base = wl.config(1).systems[0]
+    L = base.length
+
+    def setup(**kw):
+        args = dict(dim=3, lattice=base.lattice, mobile_q=base.mobile_q, alpha=base.alpha,
+                    g_cut=base.g_cut, r_cut=base.r_cut)
+        args.update(kw)
+        return ew.ewald_setup(**args)
+
+    assert status_of(lambda: setup(dim=4)) == ew.EWALD_E_ARG
+    assert status_of(lambda: setup(lattice=np.zeros((3, 3)))) == ew.EWALD_E_LATTICE
+    sing = base.lattice.copy()
+    sing[2] = sing[0] + sing[1]
+    assert status_of(lambda: setup(lattice=sing)) == ew.EWALD_E_LATTICE
+    nan_lat = base.lattice.copy()
+    nan_lat[0, 0] = np.nan
+    assert status_of(lambda: setup(lattice=nan_lat)) == ew.EWALD_E_LATTICE
+    assert status_of(lambda: setup(r_cut=0.51 * L)) == ew.EWALD_E_RCUT
+    assert status_of(lambda: setup(r_cut=-1.0)) == ew.EWALD_E_RCUT
+    assert status_of(lambda: setup(g_cut=0.0)) == ew.EWALD_E_GCUT
+    assert status_of(lambda: setup(g_cut=1e4)) == ew.EWALD_E_GCUT
+    assert status_of(lambda: setup(alpha=0.0)) == ew.EWALD_E_ARG
+    assert status_of(lambda: setup(mobile_q=np.zeros(0))) == ew.EWALD_E_ARG
+    assert status_of(lambda: setup(mobile_q=np.zeros(3000))) == ew.EWALD_E_ARG
+    assert status_of(lambda: setup(precision=7)) == ew.EWALD_E_ARG
+    assert status_of(lambda: setup(refresh_every=-1)) == ew.EWALD_E_ARG
+    assert status_of(lambda: setup(mobile_q=np.array([np.inf, 1.0]))) == ew.EWALD_E_ARG
+    # NULL descriptor / output
+    assert lib.ewald_setup(None, None) == ew.EWALD_E_ARG
+    h = ctypes.c_void_p()
+    assert lib.ewald_setup(None, ctypes.byref(h)) == ew.EWALD_E_ARG
+    assert ew.ewald_last_error()
+    # calls on NULL handles
+    assert lib.ewald_energy_batch(None, None, None, None, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_move_delta_batch(None, None, None, None, None, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_accept_batch(None, None, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_run_moves_batch(None, None, 1, None, None, None, None, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_sys_query(None, None, None, None, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_batch_layout(None, None, None) == ew.EWALD_E_ARG
+
+
+def test_batch_create_validation(lib):
+    s = make(1)
+    arr = (ctypes.c_void_p * 1)(ctypes.c_void_p(s.handle))
+    h = ctypes.c_void_p()
+    bad = np.array([0, 1], dtype=np.int32)
+    assert lib.ewald_batch_create(arr, 1, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 2,
+                                  ctypes.byref(h)) == ew.EWALD_E_ARG
+    s2 = ew.System(wl.config(3).systems[0])
+    arr2 = (ctypes.c_void_p * 2)(ctypes.c_void_p(s.handle), ctypes.c_void_p(s2.handle))
+    ok = np.array([0, 1], dtype=np.int32)
+    assert lib.ewald_batch_create(arr2, 2, ok.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 2,
+                                  ctypes.byref(h)) == ew.EWALD_E_ARG  # 3D with 2D
+
+
+def cart_g(system, n):
+    d = system.dim
+    B = 2 * math.pi * np.linalg.inv(system.lattice[:d, :d]).T
+    g = np.zeros((n.shape[0], 3))
+    g[:, :d] = n[:, :d] @ B
+    return g
+
+
+@pytest.mark.parametrize("cfg_id", [1, 2, 3, 5])
+def test_half_set_matches_oracle(lib, oracle_lib, cfg_id):
+    system = wl.config(cfg_id).systems[0]
+    s = ew.System(system)
+    t = s.tables()
+    valid = t["shell"] >= 0
+    assert valid.sum() == s.info["n_g"]
+    assert np.all(t["weight"][~valid] == 0)
+    g = cart_g(system, t["n"][valid])
+    og, og2, osh = oracle_lib.gvectors(system)
+    assert 2 * g.shape[0] == og.shape[0]
+    full = np.concatenate([g, -g])
+    key = lambda a: set(map(tuple, np.round(a, 8)))
+    assert key(full) == key(og)
+    assert len(key(g) & key(-g)) == 0
+    # shells: ascending |G|, same partition as the oracle's
+    g2 = np.sum(g * g, axis=1)
+    order = np.argsort(g2)
+    assert np.all(np.diff(t["shell"][valid][order]) >= 0)
+    assert t["shell"][valid].max() + 1 == s.info["n_shells"] == osh.max() + 1
+    # the segment structure: consecutive along the last reduced index
+    ns = t["n"].shape[0] // 4
+    nn = t["n"].reshape(4, ns, 3)
+    last = system.dim - 1
+    assert np.all(nn[1:, :, last] - nn[:-1, :, last] == 1)
+
+
+@pytest.mark.parametrize("cfg_id", [1, 3])
+def test_weights_give_oracle_reciprocal_energy(lib, oracle_lib, cfg_id):
+    """sum_H w |rho|^2 with rho from the oracle equals the oracle's E_recip."""
+    system = wl.config(cfg_id).systems[0]
+    s = ew.System(system, jastrow_a=np.linspace(-0.01, 0.01, 30))
+    t = s.tables()
+    valid = t["shell"] >= 0
+    pos = wl.random_positions(system, 20, 1)
+    q = -np.ones(20)
+    g = cart_g(system, t["n"][valid])
+    rho = oracle_lib.rho_at(system, pos, q, g)
+    e = oracle_lib.energy(system, pos, q, jastrow_a=np.linspace(-0.01, 0.01, 30))
+    er = np.sum(t["weight"][valid] * np.abs(rho) ** 2)
+    ej = np.sum(t["jastrow"][valid] * np.abs(rho) ** 2)
+    assert abs(er - e["recip"]) <= 1e-12 * max(1.0, abs(e["recip"]))
+    assert abs(ej - e["jastrow"]) <= 1e-12 * max(1.0, abs(e["jastrow"]))
+
+
+def test_constant_with_fixed_ions(lib, oracle_lib):
+    system = wl.config(4).systems[0]
+    s = ew.System(system)
+    pos, q = oracle_lib.particles(system, wl.random_positions(system, system.n_mobile, 2))
+    parts = oracle_lib.energy(system, pos, q)
+    ions = oracle_lib.energy(system, system.fixed_pos, system.fixed_q)
+    expect = parts["self"] + parts["background"] + ions["real"]
+    assert abs(s.info["e_const"] - expect) <= 1e-11 * abs(expect)
+
+
+@pytest.mark.parametrize("cfg_id,expect", [(1, 0), (2, 3), (3, 2), (4, 3), (5, 3)])
+def test_min_image_candidates(lib, cfg_id, expect):
+    """rint reduction plus the candidate images finds every image within r_cut
+    (checked against a +-2 brute-force image box on random displacements)."""
+    system = wl.config(cfg_id).systems[0]
+    s = ew.System(system)
+    cand = ew.ewald_sys_candidates(s.handle)
+    assert cand.shape[0] == expect
+    d = system.dim
+    A = system.lattice[:d, :d]
+    g = np.random.default_rng(11)
+    f = g.random((100000, d)) - 0.5
+    r0 = f @ A
+    r2 = np.sum(r0 * r0, axis=1)
+    best = r2.copy()
+    for v in cand[:, :d]:
+        best = np.minimum(best, np.sum((r0 + v) ** 2, axis=1))
+        best = np.minimum(best, np.sum((r0 - v) ** 2, axis=1))
+    import itertools
+    brute = np.full_like(r2, np.inf)
+    for c in itertools.product(range(-2, 3), repeat=d):
+        brute = np.minimum(brute, np.sum((r0 + np.array(c) @ A) ** 2, axis=1))
+    inside = brute < system.r_cut ** 2
+    assert np.allclose(best[inside], brute[inside], rtol=1e-12, atol=1e-12)
+    assert np.all(best[~inside] >= system.r_cut ** 2 * (1 - 1e-12))
+
+
+def test_batch_create_without_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    s = make(1)
+    with pytest.raises(ew.EwaldError) as e:
+        ew.ewald_batch_create([s.handle], np.zeros(2, dtype=np.int32))
+    assert e.value.status == ew.EWALD_E_HIP

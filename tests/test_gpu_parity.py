@@ -1,0 +1,344 @@
+"""GPU parity of libewald against the FP64 oracle, called through the C ABI.
+
+Tolerances (relative to E_ref = max(|E_oracle|, (alpha/sqrt(pi)) sum q^2)):
+  FP64 form   energies and move deltas within 1e-10 E_ref;
+  FP32-mixed  energies within 1e-6 E_ref, each move delta within 1e-5 Ha.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2507_02888_amd import ewald as ew
+from paper_2507_02888_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED = ew.EWALD_FP64, ew.EWALD_FP32_MIXED
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ew.load()
+
+
+def e_scale(system):
+    q = np.concatenate([system.mobile_q, system.fixed_q])
+    return system.alpha / math.sqrt(math.pi) * float(np.sum(q * q))
+
+
+class Case:
+    """Seeded inputs of a workload subset, uploaded, with a library batch."""
+
+    def __init__(self, cfg_id, walkers, moves, precision, walker_start=0, refresh_every=None, jastrow=True):
+        self.cfg = wl.config(cfg_id)
+        self.b = wl.make_batch(self.cfg, walkers=walkers, moves=moves, walker_start=walker_start)
+        K = self.cfg.refresh_every if refresh_every is None else refresh_every
+        self.ja = self.b.jastrow_a if jastrow else None
+        if self.ja is None and jastrow and cfg_id != 5:
+            self.ja = np.random.default_rng([7, cfg_id]).uniform(-0.01, 0.01, 64)
+        self.systems = [ew.System(s, precision=precision, refresh_every=K if precision == MIXED else 0,
+                                  jastrow_a=self.ja) for s in self.cfg.systems]
+        self.batch = ew.Batch(self.systems, self.b.walker_sys)
+        W, S, d = self.b.walkers, self.b.steps, self.cfg.systems[0].dim
+        self.W, self.S, self.dim = W, S, d
+        dev = "cuda"
+        self.pos = torch.tensor(self.b.pos, dtype=torch.float64, device=dev)
+        self.k = torch.tensor(self.b.k, dtype=torch.int32, device=dev)
+        self.new_pos = torch.tensor(self.b.new_pos, dtype=torch.float64, device=dev)
+        self.accept = torch.tensor(self.b.accept, dtype=torch.uint8, device=dev)
+        self.energy = torch.zeros(W, dtype=torch.float64, device=dev)
+        self.jastrow = torch.zeros(W, dtype=torch.float64, device=dev)
+
+    def system(self, w):
+        return self.cfg.systems[int(self.b.walker_sys[w])]
+
+    def run_energy(self):
+        self.batch.energy(self.pos, self.energy, self.jastrow)
+        torch.cuda.synchronize()
+        return self.energy.cpu().numpy().copy(), self.jastrow.cpu().numpy().copy()
+
+    def per_step(self):
+        d = torch.zeros((self.S, self.W), dtype=torch.float64, device="cuda")
+        dj = torch.zeros_like(d)
+        for m in range(self.S):
+            self.batch.move_delta(self.k[m], self.new_pos[m], d[m], dj[m])
+            self.batch.accept(self.accept[m])
+        torch.cuda.synchronize()
+        return d.cpu().numpy(), dj.cpu().numpy()
+
+    def fused(self, steps=None):
+        S = self.S if steps is None else steps
+        d = torch.zeros((S, self.W), dtype=torch.float64, device="cuda")
+        dj = torch.zeros_like(d)
+        self.batch.run_moves(self.k[:S].contiguous(), self.new_pos[:S].contiguous(), self.accept[:S].contiguous(), d, dj)
+        torch.cuda.synchronize()
+        return d.cpu().numpy(), dj.cpu().numpy()
+
+    def oracle(self, oracle_lib, w, steps=None):
+        S = self.S if steps is None else steps
+        return oracle_lib.run(self.system(w), self.b.walker_pos(w), self.b.k[:S, w], self.b.new_pos[:S, w],
+                              self.b.accept[:S, w], jastrow_a=self.ja)
+
+    def final_cartesian(self):
+        """Positions currently in the state, as a Cartesian packed array."""
+        out = np.zeros_like(self.b.pos)
+        for w in range(self.W):
+            s = self.batch.walker_positions(w)
+            lat = self.system(w).lattice[: self.dim, : self.dim]
+            out[self.b.pos_offsets[w]: self.b.pos_offsets[w + 1]] = s @ lat
+        return out
+
+
+SUBSETS = {1: (1, 54, 0), 2: (3, 24, 0), 3: (3, 24, 0), 4: (6, 12, 0), 5: (2, 6, 0)}
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [1, 2, 3, 4, 5])
+def test_energy_parity(oracle_lib, cfg_id, precision):
+    W, S, w0 = SUBSETS[cfg_id]
+    say(f"[energy] cfg={cfg_id} precision={precision} walkers={W}")
+    c = Case(cfg_id, W, 0, precision, walker_start=w0)
+    e, j = c.run_energy()
+    tol = 1e-10 if precision == FP64 else 1e-6
+    for w in range(W):
+        sysw = c.system(w)
+        ref = oracle_lib.energy(sysw, *oracle_lib.particles(sysw, c.b.walker_pos(w)), jastrow_a=c.ja)
+        scale = max(abs(ref["total"]), e_scale(sysw))
+        assert abs(e[w] - ref["total"]) <= tol * scale, (w, e[w], ref["total"])
+        assert abs(j[w] - ref["jastrow"]) <= tol * max(1.0, abs(ref["jastrow"]))
+
+
+@pytest.mark.parametrize("cfg_id", [2, 3, 4])
+def test_rho_elementwise(oracle_lib, cfg_id):
+    say(f"[rho] cfg={cfg_id}")
+    c = Case(cfg_id, 2, 0, FP64)
+    c.run_energy()
+    for w in range(2):
+        sysw = c.system(w)
+        t = c.systems[int(c.b.walker_sys[w])].tables()
+        valid = t["shell"] >= 0
+        d = sysw.dim
+        B = 2 * math.pi * np.linalg.inv(sysw.lattice[:d, :d]).T
+        g = np.zeros((int(valid.sum()), 3))
+        g[:, :d] = t["n"][valid][:, :d] @ B
+        ref = oracle_lib.rho_at(sysw, *oracle_lib.particles(sysw, c.b.walker_pos(w)), g)
+        got = c.batch.walker_rho(w)[valid]
+        assert np.max(np.abs(got - ref)) <= 1e-9 * math.sqrt(sysw.n_mobile + sysw.n_fixed)
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [1, 2, 3, 4, 5])
+def test_moves_per_step(oracle_lib, cfg_id, precision):
+    W, S, w0 = SUBSETS[cfg_id]
+    say(f"[moves per-step] cfg={cfg_id} precision={precision} walkers={W} steps={S}")
+    c = Case(cfg_id, W, S, precision, walker_start=w0)
+    e0, j0 = c.run_energy()
+    d, dj = c.per_step()
+    for w in range(W):
+        sysw = c.system(w)
+        r = c.oracle(oracle_lib, w)
+        scale = max(abs(r["energy0"]), e_scale(sysw))
+        if precision == FP64:
+            assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale
+            assert np.max(np.abs(dj[:, w] - r["djas"])) <= 1e-10 * max(1.0, abs(r["j0"]))
+        else:
+            assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5
+            assert np.max(np.abs(dj[:, w] - r["djas"])) <= 1e-5
+    # telescoping: E0 + sum of accepted deltas equals a fresh energy of the final state
+    acc = c.b.accept.astype(bool)
+    final = torch.tensor(c.final_cartesian(), dtype=torch.float64, device="cuda")
+    e_tel = e0 + np.sum(np.where(acc, d, 0.0), axis=0)
+    c2 = Case(cfg_id, W, 0, precision, walker_start=w0)
+    c2.pos = final
+    e_fin, _ = c2.run_energy()
+    for w in range(W):
+        scale = max(abs(e_fin[w]), e_scale(c.system(w)))
+        tol = 1e-10 * scale if precision == FP64 else 1e-6 * scale + 1e-5 * S
+        assert abs(e_tel[w] - e_fin[w]) <= tol
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [2, 3, 4, 5])
+def test_fused_matches_per_step(cfg_id, precision):
+    W, S, w0 = SUBSETS[cfg_id]
+    say(f"[fused vs per-step] cfg={cfg_id} precision={precision}")
+    a = Case(cfg_id, W, S, precision, walker_start=w0, refresh_every=5)
+    a.run_energy()
+    d1, j1 = a.per_step()
+    b = Case(cfg_id, W, S, precision, walker_start=w0, refresh_every=5)
+    b.run_energy()
+    d2, j2 = b.fused()
+    tol = 1e-12 if precision == FP64 else 1e-7
+    scale = max(abs(x) for x in a.energy.cpu().numpy())
+    assert np.max(np.abs(d1 - d2)) <= tol * max(1.0, scale)
+    assert np.max(np.abs(j1 - j2)) <= tol * max(1.0, scale)
+    for w in range(W):
+        ha, hb = a.batch.walker_header(w), b.batch.walker_header(w)
+        assert ha["n_accepts"] == hb["n_accepts"] == int(a.b.accept[:, w].sum())
+        assert np.array_equal(a.batch.walker_positions(w), b.batch.walker_positions(w))
+        ra, rb = a.batch.walker_rho(w), b.batch.walker_rho(w)
+        assert np.max(np.abs(ra - rb)) <= (1e-12 if precision == FP64 else 1e-9) * math.sqrt(a.system(w).n_mobile)
+
+
+def test_mixed_refresh(oracle_lib):
+    """FP32-mixed: rho is rebuilt in FP64 every K accepted moves; the running
+    rho stays within the drift bound and matches a fresh FP64 rho."""
+    K = 4
+    say("[refresh] cfg=2 K=4")
+    c = Case(2, 2, 40, MIXED, refresh_every=K)
+    c.run_energy()
+    c.per_step()
+    f = Case(2, 2, 40, MIXED, refresh_every=K)
+    f.run_energy()
+    f.fused()
+    for case in (c, f):
+        for w in range(2):
+            h = case.batch.walker_header(w)
+            acc = int(c.b.accept[:, w].sum())
+            assert h["n_accepts"] == acc
+            assert h["n_refresh"] == acc // K
+            assert 0.0 < h["drift_max"] < 1e-5
+            # running rho vs an FP64 rebuild of the final positions
+            sysw = case.system(w)
+            t = case.systems[0].tables()
+            valid = t["shell"] >= 0
+            B = 2 * math.pi * np.linalg.inv(sysw.lattice).T
+            g = t["n"][valid] @ B
+            pos = case.batch.walker_positions(w) @ sysw.lattice
+            ref = oracle_lib.rho_at(sysw, pos, sysw.mobile_q, g)
+            assert np.max(np.abs(case.batch.walker_rho(w)[valid] - ref)) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["sc", "bcc", "fcc"])
+def test_single_charge_madelung(name):
+    """One charge per cell with alpha large enough that no image lies within
+    the (inscribed) cutoff: the library's energy is the converged Madelung
+    energy of the Wigner lattice (golden values, tests/golden/madelung.txt)."""
+    from tests.test_oracle_pins import golden, CELLS_3D
+    _, ref, tol = golden()[name]
+    lat = CELLS_3D[name](4.0 / 3.0 * math.pi)
+    s = wl.System(name, 3, lat, 1, -np.ones(1), np.zeros((0, 3)), np.zeros(0), 1, 1, 1)
+    L = s.length
+    a = 7.0 / L
+    r_ins = ew.System(s, alpha=a, g_cut=12.5 * a, r_cut=0.1).info["r_inscribed"]
+    say(f"[madelung] {name}")
+    sysh = ew.System(s, alpha=a, g_cut=12.5 * a, r_cut=r_ins)
+    batch = ew.Batch([sysh], np.zeros(1, dtype=np.int32))
+    pos = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    batch.energy(pos, e)
+    torch.cuda.synchronize()
+    assert abs(e.item() - ref) <= tol * abs(ref)
+
+
+def test_determinism():
+    say("[determinism] cfg=3 mixed")
+    out = []
+    for _ in range(2):
+        c = Case(3, 3, 16, MIXED, refresh_every=3)
+        e, _ = c.run_energy()
+        d, _ = c.per_step()
+        d2, _ = c.fused(8)
+        out.append((e, d, d2, c.batch.walker_rho(1)))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_invalid_k_gives_nan_and_no_move():
+    say("[invalid k]")
+    c = Case(2, 3, 1, FP64)
+    c.run_energy()
+    rho0 = c.batch.walker_rho(1)
+    k = torch.tensor([0, -1, 250], dtype=torch.int32, device="cuda")
+    d = torch.zeros(3, dtype=torch.float64, device="cuda")
+    c.batch.move_delta(k, c.new_pos[0], d)
+    c.batch.accept(torch.ones(3, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    dn = d.cpu().numpy()
+    assert np.isfinite(dn[0]) and np.isnan(dn[1]) and np.isnan(dn[2])
+    assert np.array_equal(c.batch.walker_rho(1), rho0)
+    assert c.batch.walker_header(1)["n_accepts"] == 0
+    assert c.batch.walker_header(0)["n_accepts"] == 1
+
+
+def test_call_order_errors():
+    say("[call order]")
+    c = Case(1, 1, 2, FP64)
+    d = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ew.EwaldError) as e:
+        c.batch.move_delta(c.k[0], c.new_pos[0], d)
+    assert e.value.status == ew.EWALD_E_STATE
+    c.run_energy()
+    with pytest.raises(ew.EwaldError) as e:
+        c.batch.accept(c.accept[0])
+    assert e.value.status == ew.EWALD_E_STATE
+    c.batch.move_delta(c.k[0], c.new_pos[0], d)
+    with pytest.raises(ew.EwaldError) as e:
+        c.fused(1)
+    assert e.value.status == ew.EWALD_E_STATE
+    c.batch.accept(c.accept[0])
+    c.fused(1)
+
+
+def test_two_particles_and_ions(oracle_lib):
+    """Smallest even system plus fixed ions (the pair bookkeeping's edge cases)."""
+    lat = np.array([[6.0, 0.3, 0.0], [0.5, 5.5, 0.2], [0.1, -0.4, 6.2]])
+    ions = np.array([[1.0, 1.0, 1.0], [3.0, 2.0, 4.0], [4.5, 4.0, 0.5]])
+    s = wl.System("tiny", 3, lat, 2, np.array([-1.0, -2.0]), ions, np.array([1.0, 1.0, 1.0]),
+                  1.1, 2.6, 8 * 2 * math.pi / 6.0)
+    say("[tiny]")
+    for prec in (FP64, MIXED):
+        sysh = ew.System(s, precision=prec, refresh_every=2 if prec == MIXED else 0)
+        batch = ew.Batch([sysh], np.zeros(1, dtype=np.int32))
+        p0 = np.array([[0.2, 0.3, 0.1], [5.0, 1.0, 3.0]])
+        pos = torch.tensor(p0, device="cuda")
+        e = torch.zeros(1, dtype=torch.float64, device="cuda")
+        batch.energy(pos, e)
+        ks = np.array([1, 0, 1, 1], dtype=np.int32)
+        newp = np.array([[2.0, 2.5, 3.0], [1.1, 1.2, 1.0], [-3.0, 7.0, 2.0], [3.2, 2.1, 4.1]])
+        acc = np.array([1, 1, 0, 1], dtype=np.uint8)
+        d = torch.zeros(4, dtype=torch.float64, device="cuda")
+        for m in range(4):
+            batch.move_delta(torch.tensor(ks[m:m + 1], device="cuda"),
+                             torch.tensor(newp[m:m + 1], device="cuda"), d[m:m + 1])
+            batch.accept(torch.tensor(acc[m:m + 1], device="cuda"))
+        torch.cuda.synchronize()
+        r = oracle_lib.run(s, p0, ks, newp, acc)
+        scale = max(abs(r["energy0"]), e_scale(s))
+        tol = 1e-10 * scale if prec == FP64 else 1e-5
+        assert abs(e.item() - r["energy0"]) <= (1e-10 if prec == FP64 else 1e-6) * scale
+        assert np.max(np.abs(d.cpu().numpy() - r["delta"])) <= tol
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_full_size_sampled(oracle_lib, precision):
+    """The N=1024 workload at its full 8192 walkers, in the launch shape the
+    benchmark uses: sampled walkers against the oracle."""
+    cfg = wl.config(5)
+    say(f"[full size] precision={precision}")
+    c = Case(5, cfg.walkers, 4, precision)
+    e, j = c.run_energy()
+    d, dj = c.fused()
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(d))
+    tol_e = 1e-10 if precision == FP64 else 1e-6
+    for w in (0, 4097, cfg.walkers - 1):
+        sysw = c.system(w)
+        r = c.oracle(oracle_lib, w)
+        scale = max(abs(r["energy0"]), e_scale(sysw))
+        assert abs(e[w] - r["energy0"]) <= tol_e * scale
+        if precision == FP64:
+            assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale
+        else:
+            assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5

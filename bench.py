@@ -1,0 +1,257 @@
+"""Benchmark of the batched Ewald path on one MI355X.
+
+One step = the whole hot path over the N=1024 workload: the energy of every
+walker (wrap, rho(G) in FP64, reciprocal, Jastrow and real-space sums), then a
+sweep of 1024 single-electron moves per walker (move delta, accept/reject,
+rho update, FP64 rho rebuild every K accepted moves in the FP32-mixed form)
+through the fused multi-move call.  Inputs are seeded and synthetic and are
+resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is FP32-mixed deltas/s over the whole step
+(energy time included); the FP64 form is reported beside it under "fp64".
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np
+
+METRIC = "electron-move Ewald deltas/sec at N=1024 (FP32-mixed vs FP64) + % VALU roofline"
+CFG_ID = 5
+PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, FP64 and unpacked FP32
+PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+# algorithmic work, counted as in the scope table: FMA = 2 flops
+FLOP_PER_G_DELTA = 36        # two table phases (old/new), delta, t(G), weighted accumulate
+FLOP_PER_PAIR_DELTA = 55     # FP64 geometry, erfc, 1/r per pair evaluation
+FLOP_PER_G_PARTICLE = 10     # one phase product and one complex accumulate when rebuilding rho
+FLOP_PER_PAIR_ENERGY = 55
+
+
+def algorithmic_flops_per_delta(n_g: int, n_part: int) -> float:
+    return n_g * FLOP_PER_G_DELTA + 2 * (n_part - 1) * FLOP_PER_PAIR_DELTA
+
+
+def algorithmic_flops_per_rebuild(n_g: int, n_part: int) -> float:
+    return n_g * n_part * FLOP_PER_G_PARTICLE
+
+
+def algorithmic_flops_per_energy(n_g: int, n_part: int) -> float:
+    return algorithmic_flops_per_rebuild(n_g, n_part) + n_part * (n_part - 1) / 2 * FLOP_PER_PAIR_ENERGY
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2507_02888_amd", "csrc", "ewald_device.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(form: str):
+    """Measured HBM bytes per fused launch from the committed counter summary,
+    or None when it is missing or was taken on another kernel source."""
+    p = os.path.join(ROOT, "profiles", "k_run_n1024_counters.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    f = d.get("forms", {}).get(form)
+    return None if f is None else f.get("hbm_bytes_per_launch")
+
+
+def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int):
+    import torch
+    from paper_2507_02888_amd import ewald as ew
+    cfg, b = batch_inputs["cfg"], batch_inputs["b"]
+    dev = "cuda"
+    sysm = cfg.systems[0]
+    s = ew.System(sysm, precision=precision, refresh_every=K if precision == ew.EWALD_FP32_MIXED else 0,
+                  jastrow_a=b.jastrow_a)
+    batch = ew.Batch([s], b.walker_sys, device=dev)
+    t = batch_inputs["tensors"]
+    W, S = b.walkers, b.steps
+    energy = torch.zeros(W, dtype=torch.float64, device=dev)
+    jas = torch.zeros(W, dtype=torch.float64, device=dev)
+    delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
+    djas = torch.zeros((S, W), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        batch.energy(t["pos"], energy, jas)
+        if ev is not None:
+            ev[1].record(stream)
+        batch.run_moves(t["k"], t["new_pos"], t["accept"], delta, djas)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    e_ms = [a.elapsed_time(b_) for a, b_, _ in evs]
+    r_ms = [b_.elapsed_time(c) for _, b_, c in evs]
+    hdr = [batch.walker_header(w) for w in (0, W // 2, W - 1)]
+    n_refresh_total = None
+    # every walker follows the same accept pattern statistics; count exactly
+    acc_per_walker = b.accept.sum(axis=0)
+    if precision == ew.EWALD_FP32_MIXED and K > 0:
+        n_refresh_total = int(np.sum(acc_per_walker // K))
+    else:
+        n_refresh_total = 0
+    assert all(h["n_refresh"] == (int(acc_per_walker[w]) // K if precision and K else 0)
+               for h, w in zip(hdr, (0, W // 2, W - 1)))
+    d = delta.cpu().numpy()
+    assert np.all(np.isfinite(d))
+    out = dict(elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, energy_ms=float(np.mean(e_ms)),
+               run_ms=float(np.mean(r_ms)), n_refresh=n_refresh_total, sample_delta=d[:4, 0].tolist(),
+               drift_max=max(h["drift_max"] for h in hdr))
+    # per-step path (move_delta + accept per call), a short sweep for its rate
+    n_ps = 16
+    batch.energy(t["pos"], energy, jas)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for m in range(n_ps):
+        batch.move_delta(t["k"][m], t["new_pos"][m], delta[m], djas[m])
+        batch.accept(t["accept"][m])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out["per_step_ms_per_move"] = e0.elapsed_time(e1) / n_ps
+    batch.close()
+    s.close()
+    return out
+
+
+def cpu_baseline(cfg, n_walkers: int, threads: int):
+    import oracle
+    from paper_2507_02888_amd import workloads as wl
+    b = wl.make_batch(cfg, walkers=n_walkers)
+    sysm = cfg.systems[0]
+    pos = b.pos.reshape(n_walkers, sysm.n_mobile, sysm.dim)
+    t0 = time.perf_counter()
+    r = oracle.run_batch(sysm, pos, b.k, b.new_pos, b.accept, jastrow_a=b.jastrow_a, n_threads=threads)
+    el = time.perf_counter() - t0
+    return dict(value=n_walkers * b.steps / el, unit="deltas/s", cores=int(r["threads"]), kind="oracle",
+                sample=f"{n_walkers} walkers x {b.steps} moves (energy + one sweep each) of the same "
+                       f"workload, FP64 oracle, OpenMP over walkers; {el:.1f} s wall",
+                seconds=el)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--walkers", type=int, default=None, help="subset of the 8192 walkers (testing only)")
+    ap.add_argument("--moves", type=int, default=None, help="subset of the 1024 moves (testing only)")
+    ap.add_argument("--refresh-every", type=int, default=None)
+    ap.add_argument("--cpu-walkers", type=int, default=64)
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="mixed,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (walkers shard "
+              "trivially across GPUs, but this build measures the one-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_02888_amd import ewald as ew
+    from paper_2507_02888_amd import workloads as wl
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ew.load()
+
+    cfg = wl.config(CFG_ID)
+    K = cfg.refresh_every if args.refresh_every is None else args.refresh_every
+    b = wl.make_batch(cfg, walkers=args.walkers, moves=args.moves)
+    dev = "cuda"
+    tensors = dict(pos=torch.tensor(b.pos, device=dev), k=torch.tensor(b.k, device=dev),
+                   new_pos=torch.tensor(b.new_pos, device=dev),
+                   accept=torch.tensor(b.accept, device=dev))
+    torch.cuda.synchronize()
+    inputs = dict(cfg=cfg, b=b, tensors=tensors)
+    sysm = cfg.systems[0]
+    info = ew.System(sysm).info
+    n_g, n_part = info["n_g"], sysm.n_mobile
+    W, S = b.walkers, b.steps
+    deltas_per_step = W * S
+
+    results = {}
+    for form in args.forms.split(","):
+        prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
+        r = run_form(prec, inputs, args.steps, args.warmup, K)
+        flops_run = deltas_per_step * algorithmic_flops_per_delta(n_g, n_part) + \
+            r["n_refresh"] * algorithmic_flops_per_rebuild(n_g, n_part)
+        achieved = flops_run / (r["run_ms"] * 1e-3) / 1e12
+        traffic = traffic_from_profiles(form)
+        r["value"] = deltas_per_step / (r["ms_per_step"] * 1e-3)
+        r["roofline"] = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+                             frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=traffic,
+                             kernel=f"k_run ({form}), fused {S}-move sweep of {W} walkers",
+                             flop_per_launch=flops_run, launch_ms=round(r["run_ms"], 4),
+                             frac_of_packed_fp32_peak=round(achieved / PEAK_FP32_PACKED_TFLOPS, 4)
+                             if form == "mixed" else None)
+        e_flops = W * algorithmic_flops_per_energy(n_g, n_part)
+        r["energies_per_s"] = W / (r["energy_ms"] * 1e-3)
+        r["energy_kernel"] = dict(ms=round(r["energy_ms"], 4), achieved_tflops=round(e_flops / (r["energy_ms"] * 1e-3) / 1e12, 3))
+        r["per_step_deltas_per_s"] = W / (r["per_step_ms_per_move"] * 1e-3)
+        results[form] = r
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cfg, args.cpu_walkers, args.cpu_threads)
+
+    head = results.get("mixed") or results[next(iter(results))]
+    line = {
+        "metric": METRIC,
+        "value": round(head["value"], 1),
+        "unit": "deltas/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-mixed" if "mixed" in results else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D electron gas, bcc-shaped cell, N={n_part} at rs=1, {W} walkers x {S} "
+                               f"moves per step, |G|<=12(2pi/L) ({n_g} G in the half set), Jastrow "
+                               f"plane-wave term, FP64 rho rebuild every {K} accepts (mixed form)",
+                   "walkers": W, "moves_per_walker": S, "particles": n_part, "n_g_half": n_g,
+                   "refresh_every": K, "call": "ewald_energy_batch + ewald_run_moves_batch"},
+        "roofline": head["roofline"],
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "energies_per_s": round(head["energies_per_s"], 1),
+        "per_step_path_deltas_per_s": round(head["per_step_deltas_per_s"], 1),
+    }
+    if "fp64" in results and "mixed" in results:
+        f = results["fp64"]
+        line["fp64"] = {"value": round(f["value"], 1), "unit": "deltas/s", "ms_per_step": round(f["ms_per_step"], 3),
+                        "roofline": f["roofline"], "energies_per_s": round(f["energies_per_s"], 1),
+                        "per_step_path_deltas_per_s": round(f["per_step_deltas_per_s"], 1)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

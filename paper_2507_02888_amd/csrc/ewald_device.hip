@@ -59,25 +59,84 @@ __device__ __forceinline__ void to_frac(const double* r, const double* Ainv, dou
   }
 }
 
-// exp(2 pi i n s) from the reduced phase frac(n s) in [-1/2, 1/2].
-__device__ __forceinline__ cplx<double> phase(double s, int n, double) {
-  double x = double(n) * s;
+// exp(2 pi i x) in turns: reduce x to the nearest quarter turn q and a
+// remainder of at most half a quarter turn (exact in FP64), evaluate the
+// Taylor series of cos and sin at theta = remainder * pi/2 (|theta| <= pi/4;
+// the first omitted terms are below 1e-19 in FP64 and 1e-11 in FP32), and
+// rotate by i^q.  Small and register-light, unlike a general sincos.
+__device__ __forceinline__ void quarter_turns(double x, double& r, int& q) {
   x -= rint(x);
-  double sn, cs;
-  sincospi(2.0 * x, &sn, &cs);
-  return {cs, sn};
+  const double y = 4.0 * x;
+  const double qd = rint(y);
+  r = y - qd;
+  q = int(qd) & 3;
 }
-__device__ __forceinline__ cplx<float> phase(double s, int n, float) {
-  double x = double(n) * s;
-  x -= rint(x);
-  float sn, cs;
-  sincospif(float(2.0 * x), &sn, &cs);
-  return {cs, sn};
+
+template <typename R>
+__device__ __forceinline__ cplx<R> rotate_quarter(R c, R s, int q) {
+  const R x = (q & 1) ? -s : c, y = (q & 1) ? c : s;
+  return (q & 2) ? cplx<R>{-x, -y} : cplx<R>{x, y};
+}
+
+__device__ __forceinline__ cplx<double> turn(double x, double) {
+  double r;
+  int q;
+  quarter_turns(x, r, q);
+  const double th = r * 1.5707963267948966, t2 = th * th;
+  double sp = 2.8114572543455206e-15;
+  sp = fma(sp, t2, -7.6471637318198165e-13);
+  sp = fma(sp, t2, 1.6059043836821613e-10);
+  sp = fma(sp, t2, -2.5052108385441720e-08);
+  sp = fma(sp, t2, 2.7557319223985893e-06);
+  sp = fma(sp, t2, -1.9841269841269841e-04);
+  sp = fma(sp, t2, 8.3333333333333333e-03);
+  sp = fma(sp, t2, -1.6666666666666667e-01);
+  sp = fma(sp, t2 * th, th);
+  double cp = -1.5619206968586225e-16;
+  cp = fma(cp, t2, 4.7794773323873853e-14);
+  cp = fma(cp, t2, -1.1470745597729725e-11);
+  cp = fma(cp, t2, 2.0876756987868099e-09);
+  cp = fma(cp, t2, -2.7557319223985891e-07);
+  cp = fma(cp, t2, 2.4801587301587302e-05);
+  cp = fma(cp, t2, -1.3888888888888889e-03);
+  cp = fma(cp, t2, 4.1666666666666667e-02);
+  cp = fma(cp, t2, -0.5);
+  cp = fma(cp, t2, 1.0);
+  return rotate_quarter<double>(cp, sp, q);
+}
+
+__device__ __forceinline__ cplx<float> turn(double x, float) {
+  double r;
+  int q;
+  quarter_turns(x, r, q);
+  const float th = float(r * 1.5707963267948966), t2 = th * th;
+  float sp = -2.5052108e-08f;
+  sp = fmaf(sp, t2, 2.7557319e-06f);
+  sp = fmaf(sp, t2, -1.9841270e-04f);
+  sp = fmaf(sp, t2, 8.3333333e-03f);
+  sp = fmaf(sp, t2, -1.6666667e-01f);
+  sp = fmaf(sp, t2 * th, th);
+  float cp = 2.0876757e-09f;
+  cp = fmaf(cp, t2, -2.7557319e-07f);
+  cp = fmaf(cp, t2, 2.4801587e-05f);
+  cp = fmaf(cp, t2, -1.3888889e-03f);
+  cp = fmaf(cp, t2, 4.1666667e-02f);
+  cp = fmaf(cp, t2, -0.5f);
+  cp = fmaf(cp, t2, 1.0f);
+  return rotate_quarter<float>(cp, sp, q);
+}
+
+// exp(2 pi i n s) for a fractional coordinate s.
+template <typename R>
+__device__ __forceinline__ cplx<R> phase(double s, int n, R) {
+  return turn(double(n) * s, R(0));
 }
 
 // Squared minimum-image distance between fractional positions a and b:
-// reduce the fractional difference to [-1/2, 1/2], go Cartesian, then compare
-// with the candidate images r0 +- v_c (|r0 +- v|^2 = |r0|^2 + |v|^2 -+ 2 r0.v).
+// reduce the fractional difference to [-1/2, 1/2], go Cartesian in the frame
+// where the lattice rows are lower-triangular (Lrot; distances are frame
+// independent), then compare with the candidate images r0 +- v_c
+// (|r0 +- v|^2 = |r0|^2 + |v|^2 -+ 2 r0.v).
 template <int DIM>
 __device__ __forceinline__ double min_r2(const double* a, const double* b, const DevSys* __restrict__ S,
                                          int n_cand) {
@@ -87,13 +146,15 @@ __device__ __forceinline__ double min_r2(const double* a, const double* b, const
     f[d] = a[d] - b[d];
     f[d] -= rint(f[d]);
   }
+  const double* L = S->Lrot;
   double r[DIM];
-#pragma unroll
-  for (int e = 0; e < DIM; ++e) {
-    double v = 0.0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) v = fma(f[d], S->A[d * 3 + e], v);
-    r[e] = v;
+  if (DIM == 3) {
+    r[0] = fma(f[2], L[6], fma(f[1], L[3], f[0] * L[0]));
+    r[1] = fma(f[2], L[7], f[1] * L[4]);
+    r[DIM - 1] = f[DIM - 1] * L[8];
+  } else {
+    r[0] = fma(f[1], L[3], f[0] * L[0]);
+    r[DIM - 1] = f[DIM - 1] * L[4];
   }
   double r0sq = 0.0;
 #pragma unroll
@@ -120,44 +181,116 @@ struct Kahan {
   __device__ __forceinline__ double value() const { return double(s) - double(c); }
 };
 
-// Pair potential accumulator phi(r) = erfc(alpha r)/r for r^2 < rc2.
-// FP64 form: one FP64 sum.  Mixed form: phi = 1/r - erf(alpha r)/r with 1/r
-// in FP64 (it carries the close-pair singularity) and the bounded erf part in
-// FP32 with a Kahan sum.
-template <bool MIXED>
+// Pair potential phi(r) = erfc(alpha r)/r = 1/r - alpha g(alpha^2 r^2) for
+// r^2 < rc2, where g(y) = erf(sqrt y)/sqrt y is entire.  On [0, r_cut] g is
+// one polynomial in t = 2 r^2 / r_cut^2 - 1 (degree PD, fitted in FP64 by the
+// set-up), so a pair costs one reciprocal square root and PD FMAs.
+// FP64 form: everything in FP64.  Mixed form: 1/r in FP64 (it carries the
+// close-pair singularity) and the bounded erf part in FP32 (degree 12 or 22)
+// summed with Kahan compensation.
+template <bool MIXED, int PD>
 struct PairAcc;
 
-template <>
-struct PairAcc<false> {
+// Pair terms are evaluated four at a time: the four Horner chains interleave
+// (latency hiding) and take their coefficients straight from scalar registers.
+// A term enters iff r2 < r_cut^2; callers pad with r2 = r_cut^2 and q = 0.
+template <int PD>
+struct PairAcc<false, PD> {
   double s = 0.0;
-  __device__ __forceinline__ void add(double q, double r2, double alpha, double rc2) {
-    if (r2 < rc2) {
-      double r = sqrt(r2);
-      s = fma(q, erfc(alpha * r) / r, s);
+  __device__ __forceinline__ void add4(const double (&q)[4], const double (&r2)[4], const DevSys* __restrict__ S) {
+    double ir[4], t[4], p[4];
+    const double scale = S->poly_scale;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ir[e] = rsqrt(r2[e]);
+      t[e] = fma(r2[e], scale, -1.0);
+      p[e] = S->p64[PD];
+    }
+#pragma unroll
+    for (int i = PD - 1; i >= 0; --i) {
+      const double c = S->p64[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p[e] = fma(p[e], t[e], c);
+    }
+    const double rc2 = S->rc2, alpha = S->alpha;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double phi = fma(-alpha, p[e], ir[e]);
+      s = fma(r2[e] < rc2 ? q[e] : 0.0, phi, s);
     }
   }
-  __device__ __forceinline__ void sub(double q, double r2, double alpha, double rc2) { add(-q, r2, alpha, rc2); }
   __device__ __forceinline__ double value() const { return s; }
 };
 
-template <>
-struct PairAcc<true> {
+template <int PD>
+struct PairAcc<true, PD> {
+  static constexpr int PF = PD == 16 ? 12 : 22;
   double inv = 0.0;
   Kahan erfpart;
-  __device__ __forceinline__ void add(double q, double r2, double alpha, double rc2) {
-    if (r2 < rc2) {
-      double ir = rsqrt(r2);
-      inv = fma(q, ir, inv);
-      float rf = float(r2 * ir);
-      erfpart.add(float(q) * (erff(float(alpha) * rf) * float(ir)));
+  __device__ __forceinline__ void add4(const double (&q)[4], const double (&r2)[4], const DevSys* __restrict__ S) {
+    float t[4], p[4];
+    double ir[4];
+    const float scale = float(S->poly_scale);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ir[e] = rsqrt(r2[e]);
+      t[e] = fmaf(float(r2[e]), scale, -1.0f);
+      p[e] = S->p32[PF];
+    }
+#pragma unroll
+    for (int i = PF - 1; i >= 0; --i) {
+      const float c = S->p32[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p[e] = fmaf(p[e], t[e], c);
+    }
+    const double rc2 = S->rc2;
+    const float alpha = float(S->alpha);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double qe = r2[e] < rc2 ? q[e] : 0.0;
+      inv = fma(qe, ir[e], inv);
+      erfpart.add(float(qe) * (alpha * p[e]));
     }
   }
-  __device__ __forceinline__ void sub(double q, double r2, double alpha, double rc2) { add(-q, r2, alpha, rc2); }
   __device__ __forceinline__ double value() const { return inv - erfpart.value(); }
 };
 
-// Sum NV values over the workgroup; the result is valid in thread 0.
-template <int NV>
+// Real-space part of a move of particle k from so to sn, summed over the
+// mobile particles j != k (positions pos, charges q) and the fixed ions:
+// sum_j q_j [phi(sn - s_j) - phi(so - s_j)].  Threads take j = tid, tid + NT, ...
+// two particles (four pair terms) per round.
+template <int DIM, bool MIXED, int PD, int NT>
+__device__ __forceinline__ double real_move(const double* sn, const double* so, int k, const double* pos,
+                                            const double* q, int n, const DevSys* __restrict__ S) {
+  PairAcc<MIXED, PD> pr;
+  const int n_cand = S->n_cand, nfix = S->n_fixed;
+  const double rc2 = S->rc2;
+  const int ntot = n + nfix;
+  for (int j0 = threadIdx.x; j0 < ntot; j0 += 2 * NT) {
+    double qq[4], r2[4];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int j = j0 + c * NT;
+      const bool mob = j < n, fix = !mob && j < ntot;
+      const bool ok = (mob && j != k) || fix;
+      double sj[DIM];
+      const double* src = mob ? pos + j * DIM : S->fixed_s + (fix ? j - n : 0) * DIM;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sj[d] = ok ? src[d] : 0.0;
+      const double qj = ok ? (mob ? q[j] : S->fixed_q[j - n]) : 0.0;
+      r2[2 * c] = ok ? min_r2<DIM>(sn, sj, S, n_cand) : rc2;
+      r2[2 * c + 1] = ok ? min_r2<DIM>(so, sj, S, n_cand) : rc2;
+      qq[2 * c] = qj;
+      qq[2 * c + 1] = -qj;
+    }
+    pr.add4(qq, r2, S);
+  }
+  return pr.value();
+}
+
+// Sum NV values over a workgroup of NT threads; the result is valid in
+// thread 0.  red must hold NV * NT / 64 doubles.
+template <int NV, int NT = BLOCK>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 #pragma unroll
   for (int i = 0; i < NV; ++i)
@@ -166,14 +299,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
-    for (int i = 0; i < NV; ++i) red[i * (BLOCK / 64) + wv] = v[i];
+    for (int i = 0; i < NV; ++i) red[i * (NT / 64) + wv] = v[i];
   __syncthreads();
   if (threadIdx.x == 0)
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < BLOCK / 64; ++k) t += red[i * (BLOCK / 64) + k];
+      for (int k = 0; k < NT / 64; ++k) t += red[i * (NT / 64) + k];
       v[i] = t;
     }
 }
@@ -202,18 +335,18 @@ __device__ __forceinline__ cplx<R> anchor(const cplx<R>* tab, uint32_t pn, int n
   return e;
 }
 
-// Rebuild rho over the segments segs[i] = seg0 + i * BLOCK (i < NS) of one
+// Rebuild rho over the segments segs[i] = seg0 + i * NT (i < NS) of one
 // walker in FP64: rho = rho_fix + sum_p q_p exp(i G.r_p), particles taken
 // TILE_P at a time through LDS phase tables (tabs: TILE_P * DIM * (2nm+1)).
-// `pos` may point to global or LDS memory.  All threads must call it.
-template <int DIM, int NS>
+// `pos` may point to global or LDS memory.  All NT threads must call it.
+template <int DIM, int NS, int NT = BLOCK>
 __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[NS], int seg0,
                             const DevSys* __restrict__ S, const double* pos, const double* q, int n,
                             cplx<double>* tabs) {
   const int nseg = S->n_seg, nm = S->nm, tbl = 2 * nm + 1;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const int s = seg0 + i * BLOCK;
+    const int s = seg0 + i * NT;
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
       if (s < nseg) {
@@ -226,7 +359,7 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
   }
   for (int p0 = 0; p0 < n; p0 += TILE_P) {
     const int np = min(TILE_P, n - p0);
-    for (int e = threadIdx.x; e < np * DIM * (nm + 1); e += BLOCK) {
+    for (int e = threadIdx.x; e < np * DIM * (nm + 1); e += NT) {
       const int p = e / (DIM * (nm + 1));
       double sp[DIM];
 #pragma unroll
@@ -240,7 +373,7 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
       const cplx<double> u = tp[(DIM - 1) * tbl + nm + 1];
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        if (seg0 + i * BLOCK < nseg) {
+        if (seg0 + i * NT < nseg) {
           cplx<double> e = anchor<DIM, double>(tp, an[i], nm);
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
@@ -257,8 +390,12 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
 
 // ---------------------------------------------------------------------------
 // Energy: wrap positions, rho in FP64, reciprocal and Jastrow sums, real-space
-// pairs, constants.  SPT = segments per thread held in registers.
-template <int DIM, bool MIXED, int SPT>
+// pairs, constants.  SPT = segments per thread held in registers.  Both
+// precision forms sum the pair terms in FP64: the energy adds ~N^2/4 terms of
+// one sign (like charges), so any FP32 rounding bias of the pair function
+// would add up coherently, while in a move delta it cancels between the old
+// and new terms.
+template <int DIM, bool MIXED, int SPT, int PD>
 __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ systems,
                                                   const DevWalker* __restrict__ walkers,
                                                   const double* __restrict__ pos, char* __restrict__ state,
@@ -329,25 +466,35 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
 
   // real space: each unordered mobile pair once (pair i with i+1..i+(n-1)/2
   // cyclically, plus i+n/2 for i < n/2 when n is even), then mobile-ion pairs
-  const double alpha = S->alpha, rc2 = S->rc2;
-  PairAcc<MIXED> pr;
+  PairAcc<false, PD> pr;
+  const double rc2 = S->rc2;
+  // partners of particle i: i+1 .. i+half cyclically, i + n/2 when n is even
+  // and i < n/2 (each unordered mobile pair once), then every fixed ion
   const int half = (n - 1) / 2;
   for (int i = tid; i < n; i += BLOCK) {
     double si[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) si[d] = lpos[i * DIM + d];
     const double qi = lq[i];
-    for (int m = 1; m <= half; ++m) {
-      int j = i + m;
-      if (j >= n) j -= n;
-      pr.add(qi * lq[j], min_r2<DIM>(si, lpos + j * DIM, S, n_cand), alpha, rc2);
+    const int n_mob = half + (((n & 1) == 0 && i < n / 2) ? 1 : 0);
+    const int n_part = n_mob + nfix;
+    for (int m0 = 0; m0 < n_part; m0 += 4) {
+      double qq[4], r2[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int m = m0 + c;
+        const bool mob = m < n_mob, fix = !mob && m < n_part;
+        int j = i + m + 1;
+        if (j >= n) j -= n;
+        const double* src = mob ? lpos + j * DIM : S->fixed_s + (fix ? m - n_mob : 0) * DIM;
+        double sj[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) sj[d] = (mob || fix) ? src[d] : 0.0;
+        qq[c] = mob ? qi * lq[j] : fix ? qi * S->fixed_q[m - n_mob] : 0.0;
+        r2[c] = (mob || fix) ? min_r2<DIM>(si, sj, S, n_cand) : rc2;
+      }
+      pr.add4(qq, r2, S);
     }
-    if ((n & 1) == 0 && i < n / 2) {
-      const int j = i + n / 2;
-      pr.add(qi * lq[j], min_r2<DIM>(si, lpos + j * DIM, S, n_cand), alpha, rc2);
-    }
-    for (int I = 0; I < nfix; ++I)
-      pr.add(qi * S->fixed_q[I], min_r2<DIM>(si, S->fixed_s + I * DIM, S, n_cand), alpha, rc2);
   }
   double v[3] = {pr.value(), er, ej};
   block_sum<3>(v, red);
@@ -360,7 +507,7 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
 // ---------------------------------------------------------------------------
 // Move delta: dE and dJ of moving particle k to new_pos; records the pending
 // move.  rho is streamed from the state once (slot-planar, coalesced).
-template <int DIM, bool MIXED>
+template <int DIM, bool MIXED, int PD>
 __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ systems,
                                                  const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                                  const int32_t* __restrict__ kk, const double* __restrict__ new_pos,
@@ -434,22 +581,8 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
     }
   }
   // real space
-  const double alpha = S->alpha, rc2 = S->rc2;
-  PairAcc<MIXED> pr;
-  for (int j = tid; j < n; j += BLOCK) {
-    if (j == k) continue;
-    const double* sj = spos + j * DIM;
-    const double qj = S->mobile_q[j];
-    pr.add(qj, min_r2<DIM>(sn, sj, S, n_cand), alpha, rc2);
-    pr.sub(qj, min_r2<DIM>(so, sj, S, n_cand), alpha, rc2);
-  }
-  for (int I = tid; I < nfix; I += BLOCK) {
-    const double* sj = S->fixed_s + I * DIM;
-    const double qj = S->fixed_q[I];
-    pr.add(qj, min_r2<DIM>(sn, sj, S, n_cand), alpha, rc2);
-    pr.sub(qj, min_r2<DIM>(so, sj, S, n_cand), alpha, rc2);
-  }
-  double v[2] = {(MIXED ? accE32.value() : accE64) + qk * pr.value(), MIXED ? accJ32.value() : accJ64};
+  const double er = real_move<DIM, MIXED, PD, BLOCK>(sn, so, k, spos, S->mobile_q, n, S);
+  double v[2] = {(MIXED ? accE32.value() : accE64) + qk * er, MIXED ? accJ32.value() : accJ64};
   block_sum<2>(v, red);
   if (tid == 0) {
     delta[w] = v[0];
@@ -570,35 +703,42 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
 // ---------------------------------------------------------------------------
 // Fused multi-move: n_steps proposals per walker with rho, weights and the
 // segment anchors in registers and positions in LDS for the whole sequence.
-template <int DIM, bool MIXED, int SPT, bool JAS>
-__global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ systems,
-                                               const DevWalker* __restrict__ walkers, char* __restrict__ state,
-                                               int n_steps, int n_walkers, const int32_t* __restrict__ kk,
-                                               const double* __restrict__ new_pos, const uint8_t* __restrict__ accept,
-                                               double* __restrict__ delta, double* __restrict__ djas, int lds_pos,
-                                               int lds_tab) {
+// NT threads per walker, SPT segments per thread.  Two barriers per move:
+// after the phase tables are built, and inside the final reduction.
+template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
+__global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
+                                            const DevWalker* __restrict__ walkers, char* __restrict__ state,
+                                            int n_steps, int n_walkers, const int32_t* __restrict__ kk,
+                                            const double* __restrict__ new_pos, const uint8_t* __restrict__ accept,
+                                            double* __restrict__ delta, double* __restrict__ djas, int lds_pos,
+                                            int lds_tab, int lds_wtab) {
   using R = typename std::conditional<MIXED, float, double>::type;
+  // the mixed form multiplies weights with FP32 terms, so it keeps them in FP32
+  using WT = R;
+  using WT2 = cplx<WT>;  // (weight, Jastrow coefficient)
+  constexpr int NRED = 2 * (NT / 64) + NT / 64;
   extern __shared__ double smem[];
   const int w = blockIdx.x, tid = threadIdx.x;
   const DevWalker W = walkers[w];
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm, nfix = S->n_fixed, n_cand = S->n_cand;
   const int K = S->refresh_every, tbl = 2 * nm + 1;
-  // the mixed form multiplies weights with FP32 terms, so it keeps them in FP32
-  using WT = R;
   char* st = state + W.state_off;
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
   double* spos = reinterpret_cast<double*>(st + HDR_BYTES);
   double* rho = reinterpret_cast<double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
   double* lpos = smem;                  // [n][DIM]
   double* lq = smem + lds_pos * DIM;    // [n]
-  double* red = lq + lds_pos;           // 16
-  cplx<R>* to = reinterpret_cast<cplx<R>*>(red + 16);
+  double* red = lq + lds_pos;           // NRED (rounded up to even)
+  cplx<R>* to = reinterpret_cast<cplx<R>*>(red + ((NRED + 1) & ~1));
   cplx<R>* tn = to + DIM * tbl;
-  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(red + 16 + lds_tab);  // rebuild tiles
+  WT2* ltab = reinterpret_cast<WT2*>(red + ((NRED + 1) & ~1) + lds_tab);                   // shell table
+  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(red + ((NRED + 1) & ~1) + lds_tab + lds_wtab);  // rebuild tiles
+  // every system of the batch has its shell table in LDS (checked by the launcher)
+  for (int i = tid; i < S->n_wtab; i += NT) ltab[i] = {WT(S->wa_tab[2 * i]), WT(S->wa_tab[2 * i + 1])};
 
-  for (int i = tid; i < n * DIM; i += BLOCK) lpos[i] = spos[i];
-  for (int i = tid; i < n; i += BLOCK) lq[i] = S->mobile_q[i];
+  for (int i = tid; i < n * DIM; i += NT) lpos[i] = spos[i];
+  for (int i = tid; i < n; i += NT) lq[i] = S->mobile_q[i];
   int counter = hdr->counter;
   int n_acc = hdr->n_accepts, n_ref = hdr->n_refresh;
   double drift = hdr->drift_max;
@@ -606,22 +746,31 @@ __global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ system
 
   uint32_t an[SPT];
   cplx<double> rv[SPT][SEG];
-  WT wv[SPT][SEG], av[SPT][SEG];
+  uint32_t shp[SPT][SEG / 2];  // two 16-bit shell indices per register
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
-    const int s = tid + i * BLOCK;
+    const int s = tid + i * NT;
     an[i] = s < nseg ? S->seg_n[s] : 0u;
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
       const size_t g = size_t(j) * nseg + s;
       rv[i][j] = s < nseg ? cplx<double>{rho[2 * g], rho[2 * g + 1]} : cplx<double>{0.0, 0.0};
-      wv[i][j] = s < nseg ? WT(S->w[g]) : WT(0);
-      av[i][j] = (JAS && s < nseg) ? WT(S->ja[g]) : WT(0);
+    }
+#pragma unroll
+    for (int j = 0; j < SEG; j += 2) {
+      const size_t g = size_t(j) * nseg + s;
+      shp[i][j / 2] = s < nseg ? uint32_t(S->slot_shell[g]) | (uint32_t(S->slot_shell[g + nseg]) << 16) : 0u;
     }
   }
   __syncthreads();
 
-  const double alpha = S->alpha, rc2 = S->rc2;
+  // position of the previous move (all threads keep it, so the next move can
+  // read its old position before thread 0's LDS update is synchronised)
+  int k_prev = -1;
+  double s_prev[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) s_prev[d] = 0.0;
+
   for (int m = 0; m < n_steps; ++m) {
     const size_t idx = size_t(m) * n_walkers + w;
     const int k = kk[idx];
@@ -640,10 +789,10 @@ __global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ system
       for (int d = 0; d < DIM; ++d) r[d] = new_pos[idx * DIM + d];
       to_frac<DIM>(r, S->Ainv, sn);
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) so[d] = lpos[k * DIM + d];
+      for (int d = 0; d < DIM; ++d) so[d] = (k == k_prev) ? s_prev[d] : lpos[k * DIM + d];
     }
     const double qk = lq[k];
-    for (int e = tid; e < 2 * DIM * (nm + 1); e += BLOCK) {
+    for (int e = tid; e < 2 * DIM * (nm + 1); e += NT) {
       if (e < DIM * (nm + 1)) fill_tables<DIM, R>(to, so, nm, e);
       else fill_tables<DIM, R>(tn, sn, nm, e - DIM * (nm + 1));
     }
@@ -655,19 +804,21 @@ __global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ system
     Kahan accE32, accJ32;
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
-      if (tid + i * BLOCK < nseg) {
+      if (tid + i * NT < nseg) {
         cplx<R> eo = anchor<DIM, R>(to, an[i], nm);
         cplx<R> en = anchor<DIM, R>(tn, an[i], nm);
 #pragma unroll
         for (int j = 0; j < SEG; ++j) {
+          const WT2 wa = ltab[(shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu];
+          const WT wgt = wa.x, ajs = wa.y;
           const R dx = en.x - eo.x, dy = en.y - eo.y;
           const R t = R(2) * q * (R(rv[i][j].x) * dx + R(rv[i][j].y) * dy) + q2 * (dx * dx + dy * dy);
           if (MIXED) {
-            accE32.add(float(wv[i][j]) * float(t));
-            if (JAS) accJ32.add(float(av[i][j]) * float(t));
+            accE32.add(float(wgt) * float(t));
+            if (JAS) accJ32.add(float(ajs) * float(t));
           } else {
-            accE64 = fma(wv[i][j], double(t), accE64);
-            if (JAS) accJ64 = fma(av[i][j], double(t), accJ64);
+            accE64 = fma(double(wgt), double(t), accE64);
+            if (JAS) accJ64 = fma(double(ajs), double(t), accJ64);
           }
           if (acc) {
             rv[i][j].x += double(q * dx);
@@ -678,22 +829,11 @@ __global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ system
         }
       }
     }
-    PairAcc<MIXED> pr;
-    for (int j = tid; j < n; j += BLOCK) {
-      if (j == k) continue;
-      const double* sj = lpos + j * DIM;
-      const double qj = lq[j];
-      pr.add(qj, min_r2<DIM>(sn, sj, S, n_cand), alpha, rc2);
-      pr.sub(qj, min_r2<DIM>(so, sj, S, n_cand), alpha, rc2);
-    }
-    for (int I = tid; I < nfix; I += BLOCK) {
-      const double* sj = S->fixed_s + I * DIM;
-      const double qj = S->fixed_q[I];
-      pr.add(qj, min_r2<DIM>(sn, sj, S, n_cand), alpha, rc2);
-      pr.sub(qj, min_r2<DIM>(so, sj, S, n_cand), alpha, rc2);
-    }
-    double v[2] = {(MIXED ? accE32.value() : accE64) + qk * pr.value(), MIXED ? accJ32.value() : accJ64};
-    block_sum<2>(v, red);
+    const double er = real_move<DIM, MIXED, PD, NT>(sn, so, k, lpos, lq, n, S);
+    double v[2] = {(MIXED ? accE32.value() : accE64) + qk * er, MIXED ? accJ32.value() : accJ64};
+    block_sum<2, NT>(v, red);
+    // every thread has passed the reduction barrier, so nobody reads lpos[k]
+    // of this move any more; the next move's reads follow its table barrier
     if (tid == 0) {
       delta[idx] = v[0];
       if (djas) djas[idx] = v[1];
@@ -704,13 +844,16 @@ __global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ system
     if (acc) {
       counter += 1;
       n_acc += 1;
+      k_prev = k;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) s_prev[d] = sn[d];
     }
-    __syncthreads();
     if (MIXED && K > 0 && counter >= K) {  // uniform
+      __syncthreads();  // lpos[k] update visible to the rebuild
       // park the running rho in the state, rebuild in registers, compare
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
-        const int s = tid + i * BLOCK;
+        const int s = tid + i * NT;
         if (s < nseg)
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
@@ -719,11 +862,11 @@ __global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ system
             rho[2 * g + 1] = rv[i][j].y;
           }
       }
-      rebuild_rho<DIM, SPT>(rv, an, tid, S, lpos, lq, n, tabs);
+      rebuild_rho<DIM, SPT, NT>(rv, an, tid, S, lpos, lq, n, tabs);
       double dm = 0.0;
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
-        const int s = tid + i * BLOCK;
+        const int s = tid + i * NT;
         if (s < nseg)
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
@@ -732,19 +875,19 @@ __global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ system
           }
       }
       for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, 64));
-      if ((tid & 63) == 0) red[8 + (tid >> 6)] = dm;
+      if ((tid & 63) == 0) red[2 * (NT / 64) + (tid >> 6)] = dm;
       __syncthreads();
-      for (int k2 = 0; k2 < BLOCK / 64; ++k2) drift = fmax(drift, red[8 + k2]);
-      __syncthreads();
+      for (int k2 = 0; k2 < NT / 64; ++k2) drift = fmax(drift, red[2 * (NT / 64) + k2]);
       counter = 0;
       n_ref += 1;
     }
   }
+  __syncthreads();
 
   // write back
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
-    const int s = tid + i * BLOCK;
+    const int s = tid + i * NT;
     if (s < nseg)
 #pragma unroll
       for (int j = 0; j < SEG; ++j) {
@@ -753,7 +896,7 @@ __global__ __launch_bounds__(BLOCK) void k_run(const DevSys* __restrict__ system
         rho[2 * g + 1] = rv[i][j].y;
       }
   }
-  for (int i = tid; i < n * DIM; i += BLOCK) spos[i] = lpos[i];
+  for (int i = tid; i < n * DIM; i += NT) spos[i] = lpos[i];
   if (tid == 0) {
     hdr->counter = counter;
     hdr->n_accepts = n_acc;
@@ -792,22 +935,34 @@ int allow_lds(F* kernel, size_t bytes) {
 
 int even(int x) { return (x + 1) & ~1; }
 
-template <int DIM, bool MIXED>
-int energy_dim(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
-               void* stream) {
+template <int DIM, bool MIXED, int SPT, int PD>
+int energy_inst(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
+                void* stream) {
   const int lds_pos = even(b.max_particles);
   const size_t tab = size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>);
   const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + 16 * 8 + tab;
-  dim3 grid(b.n_walkers), block(BLOCK);
-  hipStream_t st = as_stream(stream);
-  int rc = 0;
+  if (int rc = allow_lds(k_energy<DIM, MIXED, SPT, PD>, lds)) return rc;
+  hipLaunchKernelGGL((k_energy<DIM, MIXED, SPT, PD>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
+                     b.d_sys, b.d_walk, pos, state, energy, jastrow, lds_pos);
+  return last_launch();
+}
+
+template <int DIM, bool MIXED, int PD>
+int energy_pd(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
+              void* stream) {
   switch (spt_for(b.max_n_seg)) {
-    case 1: if (!(rc = allow_lds(k_energy<DIM, MIXED, 1>, lds))) hipLaunchKernelGGL((k_energy<DIM, MIXED, 1>), grid, block, lds, st, b.d_sys, b.d_walk, pos, state, energy, jastrow, lds_pos); break;
-    case 2: if (!(rc = allow_lds(k_energy<DIM, MIXED, 2>, lds))) hipLaunchKernelGGL((k_energy<DIM, MIXED, 2>), grid, block, lds, st, b.d_sys, b.d_walk, pos, state, energy, jastrow, lds_pos); break;
-    case 4: if (!(rc = allow_lds(k_energy<DIM, MIXED, 4>, lds))) hipLaunchKernelGGL((k_energy<DIM, MIXED, 4>), grid, block, lds, st, b.d_sys, b.d_walk, pos, state, energy, jastrow, lds_pos); break;
-    default: if (!(rc = allow_lds(k_energy<DIM, MIXED, 8>, lds))) hipLaunchKernelGGL((k_energy<DIM, MIXED, 8>), grid, block, lds, st, b.d_sys, b.d_walk, pos, state, energy, jastrow, lds_pos); break;
+    case 1: return energy_inst<DIM, MIXED, 1, PD>(b, pos, state, energy, jastrow, stream);
+    case 2: return energy_inst<DIM, MIXED, 2, PD>(b, pos, state, energy, jastrow, stream);
+    case 4: return energy_inst<DIM, MIXED, 4, PD>(b, pos, state, energy, jastrow, stream);
+    default: return energy_inst<DIM, MIXED, 8, PD>(b, pos, state, energy, jastrow, stream);
   }
-  return rc ? rc : last_launch();
+}
+
+template <int DIM, bool MIXED>
+int energy_dim(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
+               void* stream) {
+  return b.poly_deg <= 16 ? energy_pd<DIM, MIXED, 16>(b, pos, state, energy, jastrow, stream)
+                          : energy_pd<DIM, MIXED, 32>(b, pos, state, energy, jastrow, stream);
 }
 
 template <int DIM, bool MIXED>
@@ -815,8 +970,12 @@ int delta_dim(const LaunchBatch& b, char* state, const int32_t* k, const double*
               double* djas, void* stream) {
   using R = typename std::conditional<MIXED, float, double>::type;
   const size_t lds = 16 * 8 + size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
-  hipLaunchKernelGGL((k_delta<DIM, MIXED>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), b.d_sys,
-                     b.d_walk, state, k, new_pos, delta, djas);
+  if (b.poly_deg <= 16)
+    hipLaunchKernelGGL((k_delta<DIM, MIXED, 16>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
+                       b.d_sys, b.d_walk, state, k, new_pos, delta, djas);
+  else
+    hipLaunchKernelGGL((k_delta<DIM, MIXED, 32>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
+                       b.d_sys, b.d_walk, state, k, new_pos, delta, djas);
   return last_launch();
 }
 
@@ -835,36 +994,46 @@ int accept_dim(const LaunchBatch& b, char* state, const uint8_t* accept, void* s
   return last_launch();
 }
 
-template <int DIM, bool MIXED, int SPT, bool JAS>
+template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
 int run_inst(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
              const uint8_t* accept, double* delta, double* djas, void* stream) {
   using R = typename std::conditional<MIXED, float, double>::type;
   const int lds_pos = even(b.max_particles);
+  const int nred = even(3 * (NT / 64));
   const size_t mtab = size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
   const int lds_tab = even(int((mtab + 7) / 8));  // in doubles
   const size_t rtab = MIXED ? size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>) : 0;
-  const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + 16 * 8 + size_t(lds_tab) * 8 + rtab;
-  if (int rc = allow_lds(k_run<DIM, MIXED, SPT, JAS>, lds)) return rc;
-  hipLaunchKernelGGL((k_run<DIM, MIXED, SPT, JAS>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
+  const int lds_wtab = even(int((size_t(b.max_wtab) * sizeof(cplx<R>) + 7) / 8));  // in doubles
+  const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + size_t(nred) * 8 + size_t(lds_tab) * 8 +
+                     size_t(lds_wtab) * 8 + rtab;
+  if (int rc = allow_lds(k_run<DIM, MIXED, NT, SPT, JAS, PD>, lds)) return rc;
+  hipLaunchKernelGGL((k_run<DIM, MIXED, NT, SPT, JAS, PD>), dim3(b.n_walkers), dim3(NT), lds, as_stream(stream),
                      b.d_sys, b.d_walk, state, n_steps, b.n_walkers, k, new_pos, accept, delta, djas, lds_pos,
-                     lds_tab);
+                     lds_tab, lds_wtab);
   return last_launch();
+}
+
+template <int DIM, bool MIXED, bool JAS, int PD>
+int run_jp(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
+           const uint8_t* accept, double* delta, double* djas, void* stream) {
+  // threads per walker and segments per thread from the largest G set
+  if (b.max_n_seg <= 256)
+    return run_inst<DIM, MIXED, 256, 1, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+  if (b.max_n_seg <= 512)
+    return run_inst<DIM, MIXED, 256, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+  if (b.max_n_seg <= 1024)
+    return run_inst<DIM, MIXED, 512, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+  return run_inst<DIM, MIXED, 512, 4, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
 }
 
 template <int DIM, bool MIXED>
 int run_dim(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
             const uint8_t* accept, double* delta, double* djas, void* stream) {
-  const bool jas = b.has_jastrow != 0;
-  switch (spt_for(b.max_n_seg)) {
-    case 1: return jas ? run_inst<DIM, MIXED, 1, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-                       : run_inst<DIM, MIXED, 1, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-    case 2: return jas ? run_inst<DIM, MIXED, 2, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-                       : run_inst<DIM, MIXED, 2, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-    case 4: return jas ? run_inst<DIM, MIXED, 4, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-                       : run_inst<DIM, MIXED, 4, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-    default: return jas ? run_inst<DIM, MIXED, 8, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-                        : run_inst<DIM, MIXED, 8, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-  }
+  const bool jas = b.has_jastrow != 0, p16 = b.poly_deg <= 16;
+  if (jas) return p16 ? run_jp<DIM, MIXED, true, 16>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
+                      : run_jp<DIM, MIXED, true, 32>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+  return p16 ? run_jp<DIM, MIXED, false, 16>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
+             : run_jp<DIM, MIXED, false, 32>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
 }
 
 }  // namespace
@@ -892,6 +1061,17 @@ int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void
 
 int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
                const uint8_t* accept, double* delta, double* djas, void* stream) {
+  if (!b.all_wtab_lds) {
+    // a shell table too large for LDS: the same sequence through the per-step kernels
+    const size_t W = size_t(b.n_walkers);
+    for (int m = 0; m < n_steps; ++m) {
+      int rc = launch_delta(b, state, k + m * W, new_pos + m * W * b.dim, delta + m * W, djas ? djas + m * W : nullptr,
+                            stream);
+      if (!rc) rc = launch_accept(b, state, accept + m * W, stream);
+      if (rc) return rc;
+    }
+    return 0;
+  }
   if (b.dim == 3) return b.mixed ? run_dim<3, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
                                  : run_dim<3, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
   return b.mixed ? run_dim<2, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)

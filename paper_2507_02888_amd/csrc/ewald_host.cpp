@@ -132,6 +132,62 @@ double box_min_dist2(const double* M, int dim, const int* c) {
   return best;
 }
 
+// g(y) = erf(sqrt(y))/sqrt(y), an entire function of y with g(0) = 2/sqrt(pi).
+double g_erf(double y) {
+  if (y < 1e-300) return 2.0 / std::sqrt(kPi);
+  const double r = std::sqrt(y);
+  return std::erf(r) / r;
+}
+
+// Degree-deg polynomial in t = 2y/Y - 1 interpolating g at Chebyshev nodes of
+// [0, Y], returned as monomial coefficients in t (Horner-ready).  The
+// Chebyshev-to-monomial conversion runs in long double.
+std::vector<double> fit_g(double Y, int deg) {
+  const int n = deg + 1;
+  std::vector<long double> c(n, 0.0L);
+  for (int j = 0; j < n; ++j) {
+    long double acc = 0.0L;
+    for (int k = 0; k < n; ++k) {
+      const long double th = kPi * (k + 0.5L) / n;
+      acc += (long double)g_erf(0.5 * Y * (1.0 + double(std::cos(th)))) * std::cos(j * th);
+    }
+    c[j] = 2.0L * acc / n;
+  }
+  c[0] *= 0.5L;
+  // T_0 = 1, T_1 = t, T_{j+1} = 2 t T_j - T_{j-1}
+  std::vector<long double> tm1(n, 0.0L), t0(n, 0.0L), mono(n, 0.0L);
+  tm1[0] = 1.0L;
+  if (n > 1) t0[1] = 1.0L;
+  mono[0] += c[0];
+  if (n > 1) mono[1] += c[1];
+  for (int j = 2; j < n; ++j) {
+    std::vector<long double> tn(n, 0.0L);
+    for (int i = 0; i < n; ++i) {
+      if (i > 0) tn[i] += 2.0L * t0[i - 1];
+      tn[i] -= tm1[i];
+    }
+    for (int i = 0; i < n; ++i) mono[i] += c[j] * tn[i];
+    tm1 = t0;
+    t0 = tn;
+  }
+  return std::vector<double>(mono.begin(), mono.end());
+}
+
+// Largest relative error of the Horner evaluation (in T) over [0, Y].
+template <typename T>
+double fit_error(const std::vector<double>& m, double Y) {
+  double worst = 0.0;
+  for (int k = 0; k <= 4000; ++k) {
+    const double y = Y * k / 4000.0;
+    const T t = T(2.0 * y / Y - 1.0);
+    T p = T(m.back());
+    for (int i = int(m.size()) - 2; i >= 0; --i) p = p * t + T(m[i]);
+    const double ref = g_erf(y);
+    worst = std::max(worst, std::fabs(double(p) - ref) / ref);
+  }
+  return worst;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -150,6 +206,7 @@ struct ewald_sys {
   std::vector<int32_t> shell;        // slot-planar, -1 for padding
   std::vector<double> rho_fix;       // slot-planar [n_slots][2]
   std::vector<double> fixed_s, fixed_q, mobile_q;
+  std::vector<double> cand_cart;     // [n_cand][3] candidate offsets, caller's frame
   int device = -1;
   void* d_block = nullptr;
   DevSys dev_uploaded{};
@@ -267,6 +324,10 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   if (!is_fin(r_cut) || !(r_cut > 0)) return fail(EWALD_E_RCUT, "r_cut must be > 0");
   if (r_cut > r_ins) return fail(EWALD_E_RCUT, "r_cut exceeds the inscribed radius (half the shortest lattice vector)");
   if (!is_fin(g_cut) || !(g_cut > 0)) return fail(EWALD_E_GCUT, "g_cut must be > 0");
+  // the pair potential's erf part is one polynomial on [0, r_cut]; it is
+  // built for alpha r_cut <= 5.5, where erfc(alpha r_cut) < 1e-14 already
+  if (alpha * r_cut > 5.5)
+    return fail(EWALD_E_RCUT, "alpha * r_cut above 5.5 (the real-space sum is converged below 1e-14 there)");
 
   // ---- G set: nonzero n with |n B| <= g_cut; the ball spans |n_d| <= g_cut |a_d| / 2 pi ----
   int nb[3] = {0, 0, 0};
@@ -466,6 +527,36 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
     }
   S->e_const = e_self + e_bg + e_ii;
 
+  // polynomial for erf(alpha r)/(alpha r) on r in [0, r_cut]
+  const double Y = alpha * alpha * r_cut * r_cut;
+  const int deg64 = (Y <= 8.0) ? 16 : 32;
+  const int deg32 = (Y <= 8.0) ? 12 : 22;
+  const std::vector<double> p64 = fit_g(Y, deg64);
+  const std::vector<double> p32 = fit_g(Y, deg32);
+  if (fit_error<double>(p64, Y) > 1e-12 || fit_error<float>(p32, Y) > 1e-6)
+    return fail(EWALD_E_RCUT, "internal: pair-potential polynomial inaccurate");
+  // rows of the lattice in an orthonormal frame where they are lower-triangular
+  // (Gram-Schmidt); distances are invariant under this rotation
+  double Lrot[9] = {0};
+  {
+    double e[3][3] = {{0}};
+    for (int i = 0; i < dim; ++i) {
+      double v[3] = {A[i * 3], A[i * 3 + 1], A[i * 3 + 2]};
+      for (int j = 0; j < i; ++j) {
+        double d = v[0] * e[j][0] + v[1] * e[j][1] + v[2] * e[j][2];
+        for (int x = 0; x < 3; ++x) v[x] -= d * e[j][x];
+      }
+      double nv = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      for (int x = 0; x < 3; ++x) e[i][x] = v[x] / nv;
+    }
+    for (int i = 0; i < dim; ++i)
+      for (int j = 0; j <= i; ++j)
+        Lrot[i * 3 + j] = A[i * 3] * e[j][0] + A[i * 3 + 1] * e[j][1] + A[i * 3 + 2] * e[j][2];
+  }
+
+  for (int c = 0; c < n_cand; ++c)
+    for (int e = 0; e < 3; ++e) S->cand_cart.push_back(cand[c * 4 + e]);
+
   DevSys& D = S->dev;
   D.dim = dim;
   D.n_mobile = S->n_mobile;
@@ -479,11 +570,32 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   D.precision = S->precision;
   std::copy(A, A + 9, D.A);
   std::copy(Ainv, Ainv + 9, D.Ainv);
+  std::copy(Lrot, Lrot + 9, D.Lrot);
   D.alpha = alpha;
   D.rc2 = r_cut * r_cut;
+  D.poly_scale = 2.0 / (r_cut * r_cut);
+  D.poly_deg = deg64;
+  for (int i = 0; i <= POLY_MAX; ++i) D.p64[i] = i <= deg64 ? p64[i] : 0.0;
+  for (int i = 0; i <= POLY32_MAX; ++i) D.p32[i] = i <= deg32 ? float(p32[i]) : 0.0f;
   D.e_const = S->e_const;
-  for (int c = 0; c < n_cand; ++c)
-    for (int t = 0; t < 4; ++t) D.cand[c][t] = cand[c * 4 + t];
+  // candidate offsets in the rotated frame: c . Lrot
+  for (int c = 0; c < n_cand; ++c) {
+    int ci[3] = {0, 0, 0};
+    // recover the integer combination: cand = ci . A  =>  ci = cand . Ainv
+    for (int d = 0; d < dim; ++d) {
+      double v = 0;
+      for (int e = 0; e < dim; ++e) v += cand[c * 4 + e] * Ainv[e * 3 + d];
+      ci[d] = int(std::lround(v));
+    }
+    double v2 = 0;
+    for (int e = 0; e < 3; ++e) {
+      double v = 0;
+      for (int d = 0; d < dim; ++d) v += ci[d] * Lrot[d * 3 + e];
+      D.cand[c][e] = v;
+      v2 += v * v;
+    }
+    D.cand[c][3] = v2;
+  }
   *out = S.release();
   return EWALD_OK;
 } catch (const std::bad_alloc&) {
@@ -519,7 +631,7 @@ ewald_status ewald_sys_candidates(const ewald_sys* s, int* n_cand, double* cand)
   if (n_cand) *n_cand = s->dev.n_cand;
   if (cand)
     for (int c = 0; c < s->dev.n_cand; ++c)
-      for (int e = 0; e < 3; ++e) cand[c * 3 + e] = s->dev.cand[c][e];
+      for (int e = 0; e < 3; ++e) cand[c * 3 + e] = s->cand_cart[c * 3 + e];
   return EWALD_OK;
 }
 
@@ -550,6 +662,20 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   const size_t o_fs = take(std::max<size_t>(1, s->fixed_s.size()) * 8);
   const size_t o_fq = take(std::max<size_t>(1, s->fixed_q.size()) * 8);
   const size_t o_mq = take(s->mobile_q.size() * 8);
+  // shell table: (w, a) per shell and a zero entry for padding slots
+  const int n_wtab = s->n_shells + 1;
+  std::vector<double> wa(size_t(n_wtab) * 2, 0.0);
+  std::vector<uint16_t> sl(ns, uint16_t(n_wtab - 1));
+  const bool sh16 = n_wtab <= 65535;
+  for (size_t g = 0; g < ns; ++g) {
+    const int sh = s->shell[g];
+    if (sh < 0) continue;
+    wa[2 * size_t(sh)] = s->w[g];
+    wa[2 * size_t(sh) + 1] = s->ja[g];
+    if (sh16) sl[g] = uint16_t(sh);
+  }
+  const size_t o_wa = take(wa.size() * 8);
+  const size_t o_sl = take(sl.size() * 2);
   std::vector<char> host(off, 0);
   std::memcpy(host.data() + o_seg, s->seg_n.data(), s->seg_n.size() * 4);
   std::memcpy(host.data() + o_w, s->w.data(), ns * 8);
@@ -558,6 +684,8 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   if (!s->fixed_s.empty()) std::memcpy(host.data() + o_fs, s->fixed_s.data(), s->fixed_s.size() * 8);
   if (!s->fixed_q.empty()) std::memcpy(host.data() + o_fq, s->fixed_q.data(), s->fixed_q.size() * 8);
   std::memcpy(host.data() + o_mq, s->mobile_q.data(), s->mobile_q.size() * 8);
+  std::memcpy(host.data() + o_wa, wa.data(), wa.size() * 8);
+  std::memcpy(host.data() + o_sl, sl.data(), sl.size() * 2);
   void* d = nullptr;
   int rc = dev_alloc(&d, off);
   if (rc) return fail(EWALD_E_NOMEM, std::string("device allocation failed: ") + dev_error_string(rc));
@@ -575,6 +703,10 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   D.fixed_s = reinterpret_cast<const double*>(base + o_fs);
   D.fixed_q = reinterpret_cast<const double*>(base + o_fq);
   D.mobile_q = reinterpret_cast<const double*>(base + o_mq);
+  D.wa_tab = reinterpret_cast<const double*>(base + o_wa);
+  D.slot_shell = reinterpret_cast<const uint16_t*>(base + o_sl);
+  D.n_wtab = n_wtab;
+  D.wtab_lds = (sh16 && n_wtab <= WTAB_MAX) ? 1 : 0;
   s->dev_uploaded = D;
   s->d_block = d;
   s->device = device;
@@ -645,6 +777,7 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
   B->state_bytes = off;
   std::vector<DevSys> ds;
   LaunchBatch& L = B->lb;
+  L.all_wtab_lds = 1;
   L.n_walkers = n_walkers;
   L.dim = dim;
   L.mixed = sys[0]->precision == EWALD_FP32_MIXED ? 1 : 0;
@@ -656,6 +789,9 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
     L.max_particles = std::max(L.max_particles, sys[i]->n_mobile);
     L.max_fixed = std::max(L.max_fixed, sys[i]->n_fixed);
     L.refresh_every = std::max(L.refresh_every, L.mixed ? sys[i]->refresh_every : 0);
+    L.poly_deg = std::max(L.poly_deg, sys[i]->dev.poly_deg);
+    L.max_wtab = std::max(L.max_wtab, sys[i]->dev_uploaded.wtab_lds ? sys[i]->dev_uploaded.n_wtab : 0);
+    L.all_wtab_lds &= sys[i]->dev_uploaded.wtab_lds;
   }
   rc = dev_alloc(&B->d_sys, ds.size() * sizeof(DevSys));
   if (rc) return fail(EWALD_E_NOMEM, "device allocation failed");

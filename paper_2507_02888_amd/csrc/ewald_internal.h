@@ -19,6 +19,9 @@ constexpr int MAX_CAND = 16;      // +-pairs of minimum-image candidate offsets
 constexpr int HDR_BYTES = 256;    // per-walker state header
 constexpr int MAX_SPT = 8;        // segments per thread held in registers (MAX_SEGMENTS / BLOCK)
 constexpr int TILE_P = 8;         // particles per phase-table tile when rebuilding rho
+constexpr int WTAB_MAX = 1024;    // largest shell table kept in LDS by the fused kernel
+constexpr int POLY_MAX = 32;      // largest degree of the pair-potential polynomial (FP64)
+constexpr int POLY32_MAX = 22;    // largest degree of its FP32 counterpart
 
 // Per-walker state header (first bytes of the walker's state block).
 struct WalkerHdr {
@@ -43,17 +46,27 @@ struct DevSys {
   int has_jastrow;
   int refresh_every;
   int precision;        // 0 FP64, 1 FP32-mixed
+  int poly_deg;         // 16 or 32: degree of p64 (p32 uses 12 or 22)
   double A[9];          // lattice rows a_i (row-major 3x3)
   double Ainv[9];       // s = r Ainv for row vectors
+  double Lrot[9];       // the lattice rotated to lower-triangular form (distances only)
   double alpha;
   double rc2;           // r_cut^2
+  double poly_scale;    // 2 / r_cut^2: t = r^2 poly_scale - 1 maps [0, r_cut^2] to [-1, 1]
   double e_const;       // E_self + E_background + fixed-ion real-space energy
-  double cand[MAX_CAND][4];  // (v_x, v_y, v_z, |v|^2) of one of each +-pair
+  double cand[MAX_CAND][4];  // (v_x, v_y, v_z, |v|^2) of one of each +-pair, rotated frame
+  // erf(alpha r)/(alpha r) = sum_i p64[i] t^i for r < r_cut (p32: FP32 copy of lower accuracy)
+  double p64[POLY_MAX + 1];
+  float p32[POLY32_MAX + 1];
   // device tables (slot-planar: slot j of segment s lives at j * n_seg + s)
   const uint32_t* seg_n;     // [n_seg] packed n of the segment's first slot (int8 x3)
   const double* w;           // [SEG * n_seg] weight, 0 for padding
   const double* ja;          // [SEG * n_seg] Jastrow coefficient, or nullptr
   const double* rho_fix;     // [SEG * n_seg][2] fixed-ion structure factor
+  const uint16_t* slot_shell;  // [SEG * n_seg] index into wa_tab (n_wtab - 1 for padding)
+  const double* wa_tab;      // [n_wtab][2] (weight, Jastrow coefficient) per shell
+  int n_wtab;                // n_shells + 1 (a zero entry for padding slots)
+  int wtab_lds;              // 1 if n_wtab <= WTAB_MAX: the fused kernel reads wa_tab from LDS
   const double* fixed_s;     // [n_fixed][dim] wrapped fractional ion positions
   const double* fixed_q;     // [n_fixed]
   const double* mobile_q;    // [n_mobile]
@@ -91,6 +104,9 @@ struct LaunchBatch {
   int max_particles;        // max n_mobile over systems
   int max_fixed;
   int refresh_every;        // max over systems (0: no rebuild kernel needed)
+  int poly_deg;             // max pair-polynomial degree over systems (16 or 32)
+  int max_wtab;             // largest LDS shell table over systems (0: none in LDS)
+  int all_wtab_lds;         // every system's shell table fits in LDS
 };
 
 // Each returns 0 on success or the hipError_t of the failed launch.

@@ -78,6 +78,7 @@ def test_validation_errors(lib):
     assert status_of(lambda: setup(lattice=nan_lat)) == ew.EWALD_E_LATTICE
     assert status_of(lambda: setup(r_cut=0.51 * L)) == ew.EWALD_E_RCUT
     assert status_of(lambda: setup(r_cut=-1.0)) == ew.EWALD_E_RCUT
+    assert status_of(lambda: setup(alpha=6.0 / (0.45 * L), r_cut=0.45 * L)) == ew.EWALD_E_RCUT
     assert status_of(lambda: setup(g_cut=0.0)) == ew.EWALD_E_GCUT
     assert status_of(lambda: setup(g_cut=1e4)) == ew.EWALD_E_GCUT
     assert status_of(lambda: setup(alpha=0.0)) == ew.EWALD_E_ARG

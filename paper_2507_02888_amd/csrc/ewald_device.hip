@@ -311,6 +311,27 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
     }
 }
 
+// Wave64 sum with DPP row operations (no LDS round trips); the total lands in
+// lane 63.  Steps: swap neighbours, swap pairs, mirror half rows, mirror rows
+// (every lane of a row then holds the row sum), then add row 0 into row 1 and
+// row 2 into row 3 (row_bcast15), and rows 0-1 into rows 2-3 (row_bcast31).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_take(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_to_lane63(double v) {
+  v += dpp_take<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_take<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_take<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_take<0x140, 0xF>(v);  // row_mirror
+  v += dpp_take<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
+  v += dpp_take<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3
+  return v;
+}
+
 // Per-dimension phase tables of one position, n in [-nm, nm]:
 // tab[d * (2 nm + 1) + nm + n] = exp(2 pi i n s_d).  Entries are written by
 // threads [t0, t0 + DIM (nm + 1)) of the calling group.
@@ -517,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
   const int w = blockIdx.x, tid = threadIdx.x;
   const DevWalker W = walkers[w];
   const DevSys* __restrict__ S = systems + W.sys;
-  const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm, nfix = S->n_fixed, n_cand = S->n_cand;
+  const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
   const int tbl = 2 * nm + 1;
   char* st = state + W.state_off;
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
@@ -701,10 +722,18 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
 }
 
 // ---------------------------------------------------------------------------
-// Fused multi-move: n_steps proposals per walker with rho, weights and the
-// segment anchors in registers and positions in LDS for the whole sequence.
-// NT threads per walker, SPT segments per thread.  Two barriers per move:
-// after the phase tables are built, and inside the final reduction.
+// Fused multi-move: n_steps proposals per walker with rho, the shell indices
+// and the segment anchors in registers, and positions, charges, the shell
+// table and the phase tables in LDS for the whole sequence.  NT threads per
+// walker, SPT segments per thread.
+//
+// One barrier per move.  During move m the last threads also build the phase
+// tables of move m+1 (double buffer): the old position of move m+1 is
+// already known (it is the new position of move m when the same particle was
+// just accepted).  Each wave reduces its partial sums with DPP and parks them
+// in LDS; the cross-wave sums of a chunk of RUN_CHUNK moves are formed once,
+// in a fixed order, at the start of the next chunk.  Proposals are staged
+// per chunk in a two-slot ring.
 template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
 __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
@@ -713,32 +742,39 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                                             double* __restrict__ delta, double* __restrict__ djas, int lds_pos,
                                             int lds_tab, int lds_wtab) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  // the mixed form multiplies weights with FP32 terms, so it keeps them in FP32
-  using WT = R;
+  using WT = R;          // the mixed form multiplies weights with FP32 terms
   using WT2 = cplx<WT>;  // (weight, Jastrow coefficient)
-  constexpr int NRED = 2 * (NT / 64) + NT / 64;
+  constexpr int NW = NT / 64;
+  constexpr int REDN = (NW + 2 * DIM + 1) & ~1;  // drift scratch + parked old positions
   extern __shared__ double smem[];
-  const int w = blockIdx.x, tid = threadIdx.x;
+  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const DevWalker W = walkers[w];
   const DevSys* __restrict__ S = systems + W.sys;
-  const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm, nfix = S->n_fixed, n_cand = S->n_cand;
+  const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
   const int K = S->refresh_every, tbl = 2 * nm + 1;
+  const int nfill = 2 * DIM * (nm + 1);  // table entries per move
   char* st = state + W.state_off;
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
   double* spos = reinterpret_cast<double*>(st + HDR_BYTES);
   double* rho = reinterpret_cast<double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
-  double* lpos = smem;                  // [n][DIM]
-  double* lq = smem + lds_pos * DIM;    // [n]
-  double* red = lq + lds_pos;           // NRED (rounded up to even)
-  cplx<R>* to = reinterpret_cast<cplx<R>*>(red + ((NRED + 1) & ~1));
-  cplx<R>* tn = to + DIM * tbl;
-  WT2* ltab = reinterpret_cast<WT2*>(red + ((NRED + 1) & ~1) + lds_tab);                   // shell table
-  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(red + ((NRED + 1) & ~1) + lds_tab + lds_wtab);  // rebuild tiles
-  // every system of the batch has its shell table in LDS (checked by the launcher)
-  for (int i = tid; i < S->n_wtab; i += NT) ltab[i] = {WT(S->wa_tab[2 * i]), WT(S->wa_tab[2 * i + 1])};
+  // LDS layout (in doubles): positions, charges, reduction scratch, two phase
+  // table buffers, shell table, proposal ring, partial-sum ring, rebuild tiles
+  double* lpos = smem;
+  double* lq = lpos + lds_pos * DIM;
+  double* red = lq + lds_pos;                                     // NW
+  double* so_buf = red + NW;                                      // [2][DIM] old position per table buffer
+  cplx<R>* tabs2 = reinterpret_cast<cplx<R>*>(red + REDN);         // [2][2 * DIM * tbl]
+  WT2* ltab = reinterpret_cast<WT2*>(red + REDN + 2 * lds_tab);
+  double* r_sn = red + REDN + 2 * lds_tab + lds_wtab;              // [2][RUN_CHUNK][DIM]
+  double* r_part = r_sn + 2 * RUN_CHUNK * DIM;                     // [2][RUN_CHUNK][NW][2]
+  int* r_k = reinterpret_cast<int*>(r_part + 2 * RUN_CHUNK * NW * 2);  // [2][RUN_CHUNK]
+  int* r_acc = r_k + 2 * RUN_CHUNK;                                     // [2][RUN_CHUNK]
+  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(r_acc + 2 * RUN_CHUNK);  // rebuild tiles
 
   for (int i = tid; i < n * DIM; i += NT) lpos[i] = spos[i];
   for (int i = tid; i < n; i += NT) lq[i] = S->mobile_q[i];
+  // every system of the batch has its shell table in LDS (checked by the launcher)
+  for (int i = tid; i < S->n_wtab; i += NT) ltab[i] = {WT(S->wa_tab[2 * i]), WT(S->wa_tab[2 * i + 1])};
   int counter = hdr->counter;
   int n_acc = hdr->n_accepts, n_ref = hdr->n_refresh;
   double drift = hdr->drift_max;
@@ -762,94 +798,156 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
       shp[i][j / 2] = s < nseg ? uint32_t(S->slot_shell[g]) | (uint32_t(S->slot_shell[g + nseg]) << 16) : 0u;
     }
   }
-  __syncthreads();
 
-  // position of the previous move (all threads keep it, so the next move can
-  // read its old position before thread 0's LDS update is synchronised)
-  int k_prev = -1;
-  double s_prev[DIM];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) s_prev[d] = 0.0;
-
-  for (int m = 0; m < n_steps; ++m) {
-    const size_t idx = size_t(m) * n_walkers + w;
-    const int k = kk[idx];
-    if (k < 0 || k >= n) {  // uniform
-      if (tid == 0) {
-        delta[idx] = NAN;
-        if (djas) djas[idx] = NAN;
-      }
-      continue;
-    }
-    const bool acc = accept[idx] != 0;
-    double sn[DIM], so[DIM];
-    {
-      double r[DIM];
+  // stage the proposals of chunk c into ring slot c & 1 (one thread per move)
+  auto stage = [&](int c) {
+    const int m0 = c * RUN_CHUNK, cnt = min(RUN_CHUNK, n_steps - m0), par = c & 1;
+    if (tid < cnt) {
+      const size_t idx = size_t(m0 + tid) * n_walkers + w;
+      const int kv = kk[idx];
+      r_k[par * RUN_CHUNK + tid] = (kv < 0 || kv >= n) ? -1 : kv;
+      r_acc[par * RUN_CHUNK + tid] = accept[idx] != 0;
+      double r[DIM], sv[DIM];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) r[d] = new_pos[idx * DIM + d];
-      to_frac<DIM>(r, S->Ainv, sn);
+      to_frac<DIM>(r, S->Ainv, sv);
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) so[d] = (k == k_prev) ? s_prev[d] : lpos[k * DIM + d];
+      for (int d = 0; d < DIM; ++d) r_sn[(par * RUN_CHUNK + tid) * DIM + d] = sv[d];
     }
-    const double qk = lq[k];
-    for (int e = tid; e < 2 * DIM * (nm + 1); e += NT) {
-      if (e < DIM * (nm + 1)) fill_tables<DIM, R>(to, so, nm, e);
-      else fill_tables<DIM, R>(tn, sn, nm, e - DIM * (nm + 1));
-    }
-    __syncthreads();
-
-    const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
-    const R q = R(qk), q2 = R(qk * qk);
-    double accE64 = 0.0, accJ64 = 0.0;
-    Kahan accE32, accJ32;
+  };
+  // fill the phase tables of move m (buffer m & 1) from its old position so
+  // and its staged new position; run by the last nfill threads
+  auto prepare = [&](int m, const double* so) {
+    const int par = (m / RUN_CHUNK) & 1, mm = m % RUN_CHUNK;
+    cplx<R>* to = tabs2 + (m & 1) * 2 * DIM * tbl;
+    cplx<R>* tn = to + DIM * tbl;
+    if (tid == NT - 1)
 #pragma unroll
-    for (int i = 0; i < SPT; ++i) {
-      if (tid + i * NT < nseg) {
-        cplx<R> eo = anchor<DIM, R>(to, an[i], nm);
-        cplx<R> en = anchor<DIM, R>(tn, an[i], nm);
+      for (int d = 0; d < DIM; ++d) so_buf[(m & 1) * DIM + d] = so[d];
+    for (int e = tid - (NT - nfill); e < nfill; e += NT) {
+      if (e < 0) continue;
+      if (e < DIM * (nm + 1)) {
+        fill_tables<DIM, R>(to, so, nm, e);
+      } else {
+        double sn[DIM];
 #pragma unroll
-        for (int j = 0; j < SEG; ++j) {
-          const WT2 wa = ltab[(shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu];
-          const WT wgt = wa.x, ajs = wa.y;
-          const R dx = en.x - eo.x, dy = en.y - eo.y;
-          const R t = R(2) * q * (R(rv[i][j].x) * dx + R(rv[i][j].y) * dy) + q2 * (dx * dx + dy * dy);
-          if (MIXED) {
-            accE32.add(float(wgt) * float(t));
-            if (JAS) accJ32.add(float(ajs) * float(t));
-          } else {
-            accE64 = fma(double(wgt), double(t), accE64);
-            if (JAS) accJ64 = fma(double(ajs), double(t), accJ64);
-          }
-          if (acc) {
-            rv[i][j].x += double(q * dx);
-            rv[i][j].y += double(q * dy);
-          }
-          eo = cmul(eo, uo);
-          en = cmul(en, un);
-        }
+        for (int d = 0; d < DIM; ++d) sn[d] = r_sn[(par * RUN_CHUNK + mm) * DIM + d];
+        fill_tables<DIM, R>(tn, sn, nm, e - DIM * (nm + 1));
       }
     }
-    const double er = real_move<DIM, MIXED, PD, NT>(sn, so, k, lpos, lq, n, S);
-    double v[2] = {(MIXED ? accE32.value() : accE64) + qk * er, MIXED ? accJ32.value() : accJ64};
-    block_sum<2, NT>(v, red);
-    // every thread has passed the reduction barrier, so nobody reads lpos[k]
-    // of this move any more; the next move's reads follow its table barrier
-    if (tid == 0) {
-      delta[idx] = v[0];
-      if (djas) djas[idx] = v[1];
-      if (acc)
+  };
+  // sum the wave partials of chunk c (fixed order) and write its outputs
+  auto flush = [&](int c) {
+    const int m0 = c * RUN_CHUNK, cnt = min(RUN_CHUNK, n_steps - m0), par = c & 1;
+    if (tid < cnt) {
+      const size_t idx = size_t(m0 + tid) * n_walkers + w;
+      double e = 0.0, j = 0.0;
+      if (r_k[par * RUN_CHUNK + tid] < 0) {
+        e = j = NAN;
+      } else {
+        const double* pp = r_part + (par * RUN_CHUNK + tid) * NW * 2;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) lpos[k * DIM + d] = sn[d];
+        for (int v = 0; v < NW; ++v) {
+          e += pp[2 * v];
+          j += pp[2 * v + 1];
+        }
+      }
+      delta[idx] = e;
+      if (djas) djas[idx] = j;
+    }
+  };
+
+  if (n_steps > 0) stage(0);
+  __syncthreads();
+  if (n_steps > 0 && r_k[0] >= 0) {
+    double so0[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) so0[d] = lpos[r_k[0] * DIM + d];
+    prepare(0, so0);
+  }
+  if (n_steps > RUN_CHUNK) stage(1);
+  __syncthreads();
+
+  for (int m = 0; m < n_steps; ++m) {
+    const int c = m / RUN_CHUNK, mm = m % RUN_CHUNK, par = c & 1;
+    if (mm == 0 && c > 0) {
+      flush(c - 1);  // partials of the previous chunk are complete
+      if ((c + 1) * RUN_CHUNK < n_steps) stage(c + 1);  // ring slot of chunk c-1 is free now
+    }
+    const int k = r_k[par * RUN_CHUNK + mm];
+    const bool acc = k >= 0 && r_acc[par * RUN_CHUNK + mm] != 0;
+    double sn[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) sn[d] = r_sn[(par * RUN_CHUNK + mm) * DIM + d];
+    if (acc && tid == 0)  // nobody reads the old position of k after the last barrier
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) lpos[k * DIM + d] = sn[d];
+    // tables of the next move
+    if (m + 1 < n_steps) {
+      const int c1 = (m + 1) / RUN_CHUNK, mm1 = (m + 1) % RUN_CHUNK;
+      const int k1 = r_k[(c1 & 1) * RUN_CHUNK + mm1];
+      if (k1 >= 0) {
+        double so1[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) so1[d] = (acc && k1 == k) ? sn[d] : lpos[k1 * DIM + d];
+        prepare(m + 1, so1);
+      }
+    }
+    double v0 = 0.0, v1 = 0.0;
+    if (k >= 0) {  // uniform
+      const cplx<R>* to = tabs2 + (m & 1) * 2 * DIM * tbl;
+      const cplx<R>* tn = to + DIM * tbl;
+      double so[DIM];  // old position of k, parked by the threads that built the tables
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) so[d] = so_buf[(m & 1) * DIM + d];
+      const double qk = lq[k];
+      const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
+      const R q = R(qk), q2 = R(qk * qk);
+      double accE64 = 0.0, accJ64 = 0.0;
+      Kahan accE32, accJ32;
+#pragma unroll
+      for (int i = 0; i < SPT; ++i) {
+        if (tid + i * NT < nseg) {
+          cplx<R> eo = anchor<DIM, R>(to, an[i], nm);
+          cplx<R> en = anchor<DIM, R>(tn, an[i], nm);
+#pragma unroll
+          for (int j = 0; j < SEG; ++j) {
+            const WT2 wa = ltab[(shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu];
+            const R dx = en.x - eo.x, dy = en.y - eo.y;
+            const R t = R(2) * q * (R(rv[i][j].x) * dx + R(rv[i][j].y) * dy) + q2 * (dx * dx + dy * dy);
+            if (MIXED) {
+              accE32.add(float(wa.x) * float(t));
+              if (JAS) accJ32.add(float(wa.y) * float(t));
+            } else {
+              accE64 = fma(double(wa.x), double(t), accE64);
+              if (JAS) accJ64 = fma(double(wa.y), double(t), accJ64);
+            }
+            if (acc) {
+              rv[i][j].x += double(q * dx);
+              rv[i][j].y += double(q * dy);
+            }
+            eo = cmul(eo, uo);
+            en = cmul(en, un);
+          }
+        }
+      }
+      v0 = (MIXED ? accE32.value() : accE64);
+      v1 = MIXED ? accJ32.value() : accJ64;
+      v0 += qk * real_move<DIM, MIXED, PD, NT>(sn, so, k, lpos, lq, n, S);
+    }
+    v0 = wave_sum_to_lane63(v0);
+    v1 = wave_sum_to_lane63(v1);
+    if (lane == 63) {
+      double* pp = r_part + ((par * RUN_CHUNK + mm) * NW + wave) * 2;
+      pp[0] = v0;
+      pp[1] = v1;
     }
     if (acc) {
       counter += 1;
       n_acc += 1;
-      k_prev = k;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) s_prev[d] = sn[d];
     }
+    __syncthreads();  // the one barrier of the move
     if (MIXED && K > 0 && counter >= K) {  // uniform
-      __syncthreads();  // lpos[k] update visible to the rebuild
       // park the running rho in the state, rebuild in registers, compare
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
@@ -875,14 +973,15 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           }
       }
       for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, 64));
-      if ((tid & 63) == 0) red[2 * (NT / 64) + (tid >> 6)] = dm;
+      if (lane == 0) red[wave] = dm;
       __syncthreads();
-      for (int k2 = 0; k2 < NT / 64; ++k2) drift = fmax(drift, red[2 * (NT / 64) + k2]);
+      for (int k2 = 0; k2 < NW; ++k2) drift = fmax(drift, red[k2]);
+      __syncthreads();
       counter = 0;
       n_ref += 1;
     }
   }
-  __syncthreads();
+  if (n_steps > 0) flush((n_steps - 1) / RUN_CHUNK);
 
   // write back
 #pragma unroll
@@ -998,14 +1097,15 @@ template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
 int run_inst(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
              const uint8_t* accept, double* delta, double* djas, void* stream) {
   using R = typename std::conditional<MIXED, float, double>::type;
+  const int redn = (NT / 64 + 2 * DIM + 1) & ~1;
   const int lds_pos = even(b.max_particles);
-  const int nred = even(3 * (NT / 64));
   const size_t mtab = size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
-  const int lds_tab = even(int((mtab + 7) / 8));  // in doubles
+  const int lds_tab = even(int((mtab + 7) / 8));  // one table buffer, in doubles
   const size_t rtab = MIXED ? size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>) : 0;
   const int lds_wtab = even(int((size_t(b.max_wtab) * sizeof(cplx<R>) + 7) / 8));  // in doubles
-  const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + size_t(nred) * 8 + size_t(lds_tab) * 8 +
-                     size_t(lds_wtab) * 8 + rtab;
+  const size_t ring = size_t(2) * RUN_CHUNK * (DIM + 2 * (NT / 64)) * 8 + size_t(2) * RUN_CHUNK * 2 * 4;
+  const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + size_t(redn) * 8 + size_t(2 * lds_tab) * 8 +
+                     size_t(lds_wtab) * 8 + ring + rtab;
   if (int rc = allow_lds(k_run<DIM, MIXED, NT, SPT, JAS, PD>, lds)) return rc;
   hipLaunchKernelGGL((k_run<DIM, MIXED, NT, SPT, JAS, PD>), dim3(b.n_walkers), dim3(NT), lds, as_stream(stream),
                      b.d_sys, b.d_walk, state, n_steps, b.n_walkers, k, new_pos, accept, delta, djas, lds_pos,
@@ -1017,12 +1117,15 @@ template <int DIM, bool MIXED, bool JAS, int PD>
 int run_jp(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
            const uint8_t* accept, double* delta, double* djas, void* stream) {
   // threads per walker and segments per thread from the largest G set
+  static_assert(RUN_CHUNK <= 256, "staging uses one thread per move");
   if (b.max_n_seg <= 256)
     return run_inst<DIM, MIXED, 256, 1, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
   if (b.max_n_seg <= 512)
     return run_inst<DIM, MIXED, 256, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
   if (b.max_n_seg <= 1024)
-    return run_inst<DIM, MIXED, 512, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+    return b.run_threads == 256
+               ? run_inst<DIM, MIXED, 256, 4, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
+               : run_inst<DIM, MIXED, 512, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
   return run_inst<DIM, MIXED, 512, 4, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
 }
 

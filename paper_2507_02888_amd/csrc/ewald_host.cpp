@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -793,6 +794,8 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
     L.max_wtab = std::max(L.max_wtab, sys[i]->dev_uploaded.wtab_lds ? sys[i]->dev_uploaded.n_wtab : 0);
     L.all_wtab_lds &= sys[i]->dev_uploaded.wtab_lds;
   }
+  // tuning override of the fused kernel's workgroup size (256 or 512)
+  if (const char* env = std::getenv("EWALD_RUN_THREADS")) L.run_threads = std::atoi(env);
   rc = dev_alloc(&B->d_sys, ds.size() * sizeof(DevSys));
   if (rc) return fail(EWALD_E_NOMEM, "device allocation failed");
   rc = dev_alloc(&B->d_walk, B->walkers.size() * sizeof(DevWalker));

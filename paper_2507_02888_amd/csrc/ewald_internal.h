@@ -19,6 +19,7 @@ constexpr int MAX_CAND = 16;      // +-pairs of minimum-image candidate offsets
 constexpr int HDR_BYTES = 256;    // per-walker state header
 constexpr int MAX_SPT = 8;        // segments per thread held in registers (MAX_SEGMENTS / BLOCK)
 constexpr int TILE_P = 8;         // particles per phase-table tile when rebuilding rho
+constexpr int RUN_CHUNK = 64;     // proposals staged in LDS per chunk by the fused kernel
 constexpr int WTAB_MAX = 1024;    // largest shell table kept in LDS by the fused kernel
 constexpr int POLY_MAX = 32;      // largest degree of the pair-potential polynomial (FP64)
 constexpr int POLY32_MAX = 22;    // largest degree of its FP32 counterpart
@@ -107,6 +108,7 @@ struct LaunchBatch {
   int poly_deg;             // max pair-polynomial degree over systems (16 or 32)
   int max_wtab;             // largest LDS shell table over systems (0: none in LDS)
   int all_wtab_lds;         // every system's shell table fits in LDS
+  int run_threads;          // fused-kernel workgroup size override (0: default)
 };
 
 // Each returns 0 on success or the hipError_t of the failed launch.

@@ -191,17 +191,18 @@ struct Kahan {
 template <bool MIXED, int PD>
 struct PairAcc;
 
-// Pair terms are evaluated four at a time: the four Horner chains interleave
+// Pair terms are evaluated several at a time (NE = 2 or 4): the four Horner chains interleave
 // (latency hiding) and take their coefficients straight from scalar registers.
 // A term enters iff r2 < r_cut^2; callers pad with r2 = r_cut^2 and q = 0.
 template <int PD>
 struct PairAcc<false, PD> {
   double s = 0.0;
-  __device__ __forceinline__ void add4(const double (&q)[4], const double (&r2)[4], const DevSys* __restrict__ S) {
-    double ir[4], t[4], p[4];
+  template <int NE>
+  __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE], const DevSys* __restrict__ S) {
+    double ir[NE], t[NE], p[NE];
     const double scale = S->poly_scale;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < NE; ++e) {
       ir[e] = rsqrt(r2[e]);
       t[e] = fma(r2[e], scale, -1.0);
       p[e] = S->p64[PD];
@@ -210,11 +211,11 @@ struct PairAcc<false, PD> {
     for (int i = PD - 1; i >= 0; --i) {
       const double c = S->p64[i];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) p[e] = fma(p[e], t[e], c);
+      for (int e = 0; e < NE; ++e) p[e] = fma(p[e], t[e], c);
     }
     const double rc2 = S->rc2, alpha = S->alpha;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < NE; ++e) {
       const double phi = fma(-alpha, p[e], ir[e]);
       s = fma(r2[e] < rc2 ? q[e] : 0.0, phi, s);
     }
@@ -227,12 +228,13 @@ struct PairAcc<true, PD> {
   static constexpr int PF = PD == 16 ? 12 : 22;
   double inv = 0.0;
   Kahan erfpart;
-  __device__ __forceinline__ void add4(const double (&q)[4], const double (&r2)[4], const DevSys* __restrict__ S) {
-    float t[4], p[4];
-    double ir[4];
+  template <int NE>
+  __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE], const DevSys* __restrict__ S) {
+    float t[NE], p[NE];
+    double ir[NE];
     const float scale = float(S->poly_scale);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < NE; ++e) {
       ir[e] = rsqrt(r2[e]);
       t[e] = fmaf(float(r2[e]), scale, -1.0f);
       p[e] = S->p32[PF];
@@ -241,12 +243,12 @@ struct PairAcc<true, PD> {
     for (int i = PF - 1; i >= 0; --i) {
       const float c = S->p32[i];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) p[e] = fmaf(p[e], t[e], c);
+      for (int e = 0; e < NE; ++e) p[e] = fmaf(p[e], t[e], c);
     }
     const double rc2 = S->rc2;
     const float alpha = float(S->alpha);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < NE; ++e) {
       const double qe = r2[e] < rc2 ? q[e] : 0.0;
       inv = fma(qe, ir[e], inv);
       erfpart.add(float(qe) * (alpha * p[e]));
@@ -258,32 +260,53 @@ struct PairAcc<true, PD> {
 // Real-space part of a move of particle k from so to sn, summed over the
 // mobile particles j != k (positions pos, charges q) and the fixed ions:
 // sum_j q_j [phi(sn - s_j) - phi(so - s_j)].  Threads take j = tid, tid + NT, ...
-// two particles (four pair terms) per round.
+// PPR particles (2 PPR pair terms) per round: 2 for workgroups of up to 512
+// threads, 1 for 1024 (one particle per thread at N = 1024).  Indices are
+// clamped rather than branched on, so every load is in bounds and the loop
+// body has no divergent control flow.
 template <int DIM, bool MIXED, int PD, int NT>
 __device__ __forceinline__ double real_move(const double* sn, const double* so, int k, const double* pos,
                                             const double* q, int n, const DevSys* __restrict__ S) {
+  constexpr int PPR = NT >= 1024 ? 1 : 2;
   PairAcc<MIXED, PD> pr;
-  const int n_cand = S->n_cand, nfix = S->n_fixed;
+  const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
-  const int ntot = n + nfix;
-  for (int j0 = threadIdx.x; j0 < ntot; j0 += 2 * NT) {
-    double qq[4], r2[4];
+  for (int j0 = threadIdx.x; j0 < n; j0 += PPR * NT) {
+    double qq[2 * PPR], r2[2 * PPR];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < PPR; ++c) {
       const int j = j0 + c * NT;
-      const bool mob = j < n, fix = !mob && j < ntot;
-      const bool ok = (mob && j != k) || fix;
+      const bool ok = j < n && j != k;
+      const int jj = j < n ? j : n - 1;
       double sj[DIM];
-      const double* src = mob ? pos + j * DIM : S->fixed_s + (fix ? j - n : 0) * DIM;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) sj[d] = ok ? src[d] : 0.0;
-      const double qj = ok ? (mob ? q[j] : S->fixed_q[j - n]) : 0.0;
+      for (int d = 0; d < DIM; ++d) sj[d] = pos[jj * DIM + d];
+      const double qj = ok ? q[jj] : 0.0;
       r2[2 * c] = ok ? min_r2<DIM>(sn, sj, S, n_cand) : rc2;
       r2[2 * c + 1] = ok ? min_r2<DIM>(so, sj, S, n_cand) : rc2;
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
     }
-    pr.add4(qq, r2, S);
+    pr.template add<2 * PPR>(qq, r2, S);
+  }
+  const int nfix = S->n_fixed;
+  for (int j0 = threadIdx.x; j0 < nfix; j0 += PPR * NT) {
+    double qq[2 * PPR], r2[2 * PPR];
+#pragma unroll
+    for (int c = 0; c < PPR; ++c) {
+      const int j = j0 + c * NT;
+      const bool ok = j < nfix;
+      const int jj = ok ? j : nfix - 1;
+      double sj[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sj[d] = S->fixed_s[jj * DIM + d];
+      const double qj = ok ? S->fixed_q[jj] : 0.0;
+      r2[2 * c] = ok ? min_r2<DIM>(sn, sj, S, n_cand) : rc2;
+      r2[2 * c + 1] = ok ? min_r2<DIM>(so, sj, S, n_cand) : rc2;
+      qq[2 * c] = qj;
+      qq[2 * c + 1] = -qj;
+    }
+    pr.template add<2 * PPR>(qq, r2, S);
   }
   return pr.value();
 }
@@ -423,8 +446,8 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
                                                   double* __restrict__ energy, double* __restrict__ jastrow,
                                                   int lds_pos) {
   extern __shared__ double smem[];
-  const int w = blockIdx.x, tid = threadIdx.x;
-  const DevWalker W = walkers[w];
+  const DevWalker W = walkers[blockIdx.x];
+  const int w = W.id, tid = threadIdx.x;
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, nfix = S->n_fixed, n_cand = S->n_cand;
   char* st = state + W.state_off;
@@ -514,7 +537,7 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
         qq[c] = mob ? qi * lq[j] : fix ? qi * S->fixed_q[m - n_mob] : 0.0;
         r2[c] = (mob || fix) ? min_r2<DIM>(si, sj, S, n_cand) : rc2;
       }
-      pr.add4(qq, r2, S);
+      pr.template add<4>(qq, r2, S);
     }
   }
   double v[3] = {pr.value(), er, ej};
@@ -535,8 +558,8 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
                                                  double* __restrict__ delta, double* __restrict__ djas) {
   using R = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double smem[];
-  const int w = blockIdx.x, tid = threadIdx.x;
-  const DevWalker W = walkers[w];
+  const DevWalker W = walkers[blockIdx.x];
+  const int w = W.id, tid = threadIdx.x;
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
   const int tbl = 2 * nm + 1;
@@ -577,10 +600,12 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
   const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
   const double* __restrict__ wt = S->w;
   const double* __restrict__ ja = S->ja;
+  // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)]: q^2 is applied
+  // once to the sums, and a neutral particle's move changes nothing
   double accE64 = 0.0, accJ64 = 0.0;
   Kahan accE32, accJ32;
-  const R q = R(qk), q2 = R(qk * qk);
-  for (int s = tid; s < nseg; s += BLOCK) {
+  const R c2q = qk != 0.0 ? R(2.0 / qk) : R(0);
+  for (int s = tid; s < nseg && qk != 0.0; s += BLOCK) {
     const uint32_t pn = S->seg_n[s];
     cplx<R> eo = anchor<DIM, R>(to, pn, nm);
     cplx<R> en = anchor<DIM, R>(tn, pn, nm);
@@ -588,8 +613,8 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
     for (int j = 0; j < SEG; ++j) {
       const size_t g = size_t(j) * nseg + s;
       const R dx = en.x - eo.x, dy = en.y - eo.y;
-      const R rx = R(rho[2 * g]), ry = R(rho[2 * g + 1]);
-      const R t = R(2) * q * (rx * dx + ry * dy) + q2 * (dx * dx + dy * dy);
+      const R ux = fma(c2q, R(rho[2 * g]), dx), uy = fma(c2q, R(rho[2 * g + 1]), dy);
+      const R t = fma(ux, dx, uy * dy);
       if (MIXED) {
         accE32.add(float(wt[g]) * float(t));
         if (ja) accJ32.add(float(ja[g]) * float(t));
@@ -603,7 +628,8 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
   }
   // real space
   const double er = real_move<DIM, MIXED, PD, BLOCK>(sn, so, k, spos, S->mobile_q, n, S);
-  double v[2] = {(MIXED ? accE32.value() : accE64) + qk * er, MIXED ? accJ32.value() : accJ64};
+  const double q2 = qk * qk;
+  double v[2] = {q2 * (MIXED ? accE32.value() : accE64) + qk * er, q2 * (MIXED ? accJ32.value() : accJ64)};
   block_sum<2>(v, red);
   if (tid == 0) {
     delta[w] = v[0];
@@ -623,8 +649,8 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
                                                   const uint8_t* __restrict__ accept) {
   using R = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double smem[];
-  const int w = blockIdx.x, tid = threadIdx.x;
-  const DevWalker W = walkers[w];
+  const DevWalker W = walkers[blockIdx.x];
+  const int w = W.id, tid = threadIdx.x;
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm, K = S->refresh_every;
   const int tbl = 2 * nm + 1;
@@ -690,8 +716,8 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
                                                    const DevWalker* __restrict__ walkers,
                                                    char* __restrict__ state) {
   extern __shared__ double smem[];
-  const int w = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
-  const DevWalker W = walkers[w];
+  const DevWalker W = walkers[blockIdx.x];
+  const int chunk = blockIdx.y, tid = threadIdx.x;
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, K = S->refresh_every;
   char* st = state + W.state_off;
@@ -747,8 +773,8 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   constexpr int NW = NT / 64;
   constexpr int REDN = (NW + 2 * DIM + 1) & ~1;  // drift scratch + parked old positions
   extern __shared__ double smem[];
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const DevWalker W = walkers[w];
+  const DevWalker W = walkers[blockIdx.x];
+  const int w = W.id, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
   const int K = S->refresh_every, tbl = 2 * nm + 1;
@@ -782,7 +808,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
 
   uint32_t an[SPT];
   cplx<double> rv[SPT][SEG];
-  uint32_t shp[SPT][SEG / 2];  // two 16-bit shell indices per register
+  uint32_t shp[SPT][SEG / 2];  // two 16-bit shell-table byte offsets per register
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
     const int s = tid + i * NT;
@@ -795,7 +821,10 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
 #pragma unroll
     for (int j = 0; j < SEG; j += 2) {
       const size_t g = size_t(j) * nseg + s;
-      shp[i][j / 2] = s < nseg ? uint32_t(S->slot_shell[g]) | (uint32_t(S->slot_shell[g + nseg]) << 16) : 0u;
+      // LDS byte offsets of the (weight, Jastrow) entries
+      shp[i][j / 2] = s < nseg ? uint32_t(S->slot_shell[g]) * uint32_t(sizeof(WT2)) |
+                                     (uint32_t(S->slot_shell[g + nseg]) * uint32_t(sizeof(WT2)) << 16)
+                               : 0u;
     }
   }
 
@@ -894,7 +923,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
       }
     }
     double v0 = 0.0, v1 = 0.0;
-    if (k >= 0) {  // uniform
+    if (k >= 0 && lq[k] != 0.0) {  // uniform; a neutral particle's move changes nothing
       const cplx<R>* to = tabs2 + (m & 1) * 2 * DIM * tbl;
       const cplx<R>* tn = to + DIM * tbl;
       double so[DIM];  // old position of k, parked by the threads that built the tables
@@ -902,7 +931,8 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
       for (int d = 0; d < DIM; ++d) so[d] = so_buf[(m & 1) * DIM + d];
       const double qk = lq[k];
       const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
-      const R q = R(qk), q2 = R(qk * qk);
+      // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)], q^2 applied to the sums
+      const R q = R(qk), c2q = R(2.0 / qk);
       double accE64 = 0.0, accJ64 = 0.0;
       Kahan accE32, accJ32;
 #pragma unroll
@@ -912,9 +942,11 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           cplx<R> en = anchor<DIM, R>(tn, an[i], nm);
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
-            const WT2 wa = ltab[(shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu];
+            const WT2 wa = *reinterpret_cast<const WT2*>(reinterpret_cast<const char*>(ltab) +
+                                                         ((shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu));
             const R dx = en.x - eo.x, dy = en.y - eo.y;
-            const R t = R(2) * q * (R(rv[i][j].x) * dx + R(rv[i][j].y) * dy) + q2 * (dx * dx + dy * dy);
+            const R ux = fma(c2q, R(rv[i][j].x), dx), uy = fma(c2q, R(rv[i][j].y), dy);
+            const R t = fma(ux, dx, uy * dy);
             if (MIXED) {
               accE32.add(float(wa.x) * float(t));
               if (JAS) accJ32.add(float(wa.y) * float(t));
@@ -931,8 +963,9 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           }
         }
       }
-      v0 = (MIXED ? accE32.value() : accE64);
-      v1 = MIXED ? accJ32.value() : accJ64;
+      const double q2 = qk * qk;
+      v0 = q2 * (MIXED ? accE32.value() : accE64);
+      v1 = q2 * (MIXED ? accJ32.value() : accJ64);
       v0 += qk * real_move<DIM, MIXED, PD, NT>(sn, so, k, lpos, lq, n, S);
     }
     v0 = wave_sum_to_lane63(v0);
@@ -1123,8 +1156,8 @@ int run_jp(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, con
   if (b.max_n_seg <= 512)
     return run_inst<DIM, MIXED, 256, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
   if (b.max_n_seg <= 1024)
-    return b.run_threads == 256
-               ? run_inst<DIM, MIXED, 256, 4, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
+    return b.run_threads == 1024
+               ? run_inst<DIM, MIXED, 1024, 1, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
                : run_inst<DIM, MIXED, 512, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
   return run_inst<DIM, MIXED, 512, 4, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
 }

@@ -771,6 +771,8 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
     dw.n_mobile = s->n_mobile;
     dw.state_off = (long long)off;
     dw.pos_off = (long long)B->pos_offsets[w];
+    dw.id = w;
+    dw.pad_ = 0;
     B->walkers.push_back(dw);
     B->pos_offsets[w + 1] = B->pos_offsets[w] + size_t(s->n_mobile);
     off += walker_state_bytes(s->n_mobile, dim, s->n_seg);
@@ -800,8 +802,17 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
   if (rc) return fail(EWALD_E_NOMEM, "device allocation failed");
   rc = dev_alloc(&B->d_walk, B->walkers.size() * sizeof(DevWalker));
   if (rc) return fail(EWALD_E_NOMEM, "device allocation failed");
+  // launch order: per-move work (slots + pair terms) descending, stable
+  std::vector<DevWalker> order = B->walkers;
+  std::stable_sort(order.begin(), order.end(), [&](const DevWalker& a, const DevWalker& b) {
+    auto cost = [&](const DevWalker& x) {
+      const ewald_sys* s = sys[x.sys];
+      return double(s->n_seg) * SEG + 2.0 * (s->n_mobile + s->n_fixed);
+    };
+    return cost(a) > cost(b);
+  });
   rc = dev_upload(B->d_sys, ds.data(), ds.size() * sizeof(DevSys));
-  if (!rc) rc = dev_upload(B->d_walk, B->walkers.data(), B->walkers.size() * sizeof(DevWalker));
+  if (!rc) rc = dev_upload(B->d_walk, order.data(), order.size() * sizeof(DevWalker));
   if (rc) return fail(EWALD_E_HIP, std::string("upload failed: ") + dev_error_string(rc));
   L.d_sys = static_cast<const DevSys*>(B->d_sys);
   L.d_walk = static_cast<const DevWalker*>(B->d_walk);

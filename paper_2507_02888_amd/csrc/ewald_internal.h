@@ -73,11 +73,18 @@ struct DevSys {
   const double* mobile_q;    // [n_mobile]
 };
 
+// Walker descriptors are uploaded in launch order: most expensive first (a
+// longest-processing-time order), so that with one workgroup per walker the
+// hardware dispatcher starts the large walkers of an uneven batch early and
+// the tail is made of small ones.  `id` is the walker's index in the caller's
+// arrays.
 struct DevWalker {
   int sys;
   int n_mobile;
   long long state_off;  // byte offset of the walker's state block
   long long pos_off;    // first row in the packed position input
+  int id;
+  int pad_;
 };
 
 EW_HD inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

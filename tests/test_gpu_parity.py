@@ -342,3 +342,44 @@ def test_full_size_sampled(oracle_lib, precision):
             assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale
         else:
             assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_graph_replay_matches_eager(precision):
+    """move_delta + accept captured once in a HIP graph and replayed move by
+    move (inputs copied in eagerly between replays) give the eager results."""
+    say(f"[graph] cfg=2 precision={precision}")
+    S = 12
+    eager = Case(2, 4, S, precision, refresh_every=3)
+    eager.run_energy()
+    d_ref, dj_ref = eager.per_step()
+
+    c = Case(2, 4, S, precision, refresh_every=3)
+    c.run_energy()
+    k_buf = torch.zeros_like(c.k[0])
+    np_buf = torch.zeros_like(c.new_pos[0])
+    acc_buf = torch.zeros_like(c.accept[0])
+    d_buf = torch.zeros(c.W, dtype=torch.float64, device="cuda")
+    dj_buf = torch.zeros_like(d_buf)
+    k_buf.copy_(c.k[0])
+    np_buf.copy_(c.new_pos[0])
+    acc_buf.copy_(c.accept[0])
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        c.batch.move_delta(k_buf, np_buf, d_buf, dj_buf)
+        c.batch.accept(acc_buf)
+    torch.cuda.synchronize()
+    # capture recorded the kernels without running them: replay every move
+    for m in range(S):
+        k_buf.copy_(c.k[m])
+        np_buf.copy_(c.new_pos[m])
+        acc_buf.copy_(c.accept[m])
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(d_buf.cpu().numpy(), d_ref[m]), m
+        assert np.array_equal(dj_buf.cpu().numpy(), dj_ref[m]), m
+    for w in range(c.W):
+        assert np.array_equal(c.batch.walker_rho(w), eager.batch.walker_rho(w))
+        assert np.array_equal(c.batch.walker_positions(w), eager.batch.walker_positions(w))

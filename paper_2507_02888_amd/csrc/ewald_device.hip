@@ -555,8 +555,9 @@ template <int DIM, bool MIXED, int PD>
 __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ systems,
                                                  const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                                  const int32_t* __restrict__ kk, const double* __restrict__ new_pos,
-                                                 double* __restrict__ delta, double* __restrict__ djas) {
+                                                 double* __restrict__ delta, double* __restrict__ djas, int lds_tab) {
   using R = typename std::conditional<MIXED, float, double>::type;
+  using WT2 = cplx<R>;  // (weight, Jastrow coefficient) in the form's precision
   extern __shared__ double smem[];
   const DevWalker W = walkers[blockIdx.x];
   const int w = W.id, tid = threadIdx.x;
@@ -570,6 +571,8 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
   double* red = smem;
   cplx<R>* to = reinterpret_cast<cplx<R>*>(smem + 16);
   cplx<R>* tn = to + DIM * tbl;
+  WT2* ltab = reinterpret_cast<WT2*>(smem + 16 + lds_tab);  // shell table (when it fits)
+  const double2* __restrict__ rho2 = reinterpret_cast<const double2*>(rho);
 
   const int k = kk[w];
   if (k < 0 || k >= n) {
@@ -580,6 +583,18 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
     }
     return;
   }
+  // start streaming this thread's first segment of rho before the table barrier
+  const bool wlds = S->wtab_lds != 0;
+  double2 rcur[SEG];
+  uint32_t scur[SEG];
+#pragma unroll
+  for (int j = 0; j < SEG; ++j) {
+    const size_t g = size_t(j) * nseg + (tid < nseg ? tid : 0);
+    rcur[j] = rho2[g];
+    scur[j] = S->slot_shell[g];
+  }
+  if (wlds)
+    for (int i = tid; i < S->n_wtab; i += BLOCK) ltab[i] = {R(S->wa_tab[2 * i]), R(S->wa_tab[2 * i + 1])};
   double sn[DIM], so[DIM];
   {
     double r[DIM];
@@ -606,24 +621,48 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
   Kahan accE32, accJ32;
   const R c2q = qk != 0.0 ? R(2.0 / qk) : R(0);
   for (int s = tid; s < nseg && qk != 0.0; s += BLOCK) {
+    // prefetch the next segment while this one is consumed
+    const int s2 = s + BLOCK < nseg ? s + BLOCK : s;
+    double2 rnxt[SEG];
+    uint32_t snxt[SEG];
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const size_t g2 = size_t(j) * nseg + s2;
+      rnxt[j] = rho2[g2];
+      snxt[j] = S->slot_shell[g2];
+    }
     const uint32_t pn = S->seg_n[s];
     cplx<R> eo = anchor<DIM, R>(to, pn, nm);
     cplx<R> en = anchor<DIM, R>(tn, pn, nm);
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
       const size_t g = size_t(j) * nseg + s;
+      R wg, aj;
+      if (wlds) {
+        const WT2 wa = ltab[scur[j]];
+        wg = wa.x;
+        aj = wa.y;
+      } else {
+        wg = R(wt[g]);
+        aj = ja ? R(ja[g]) : R(0);
+      }
       const R dx = en.x - eo.x, dy = en.y - eo.y;
-      const R ux = fma(c2q, R(rho[2 * g]), dx), uy = fma(c2q, R(rho[2 * g + 1]), dy);
+      const R ux = fma(c2q, R(rcur[j].x), dx), uy = fma(c2q, R(rcur[j].y), dy);
       const R t = fma(ux, dx, uy * dy);
       if (MIXED) {
-        accE32.add(float(wt[g]) * float(t));
-        if (ja) accJ32.add(float(ja[g]) * float(t));
+        accE32.add(float(wg) * float(t));
+        if (ja) accJ32.add(float(aj) * float(t));
       } else {
-        accE64 = fma(wt[g], double(t), accE64);
-        if (ja) accJ64 = fma(ja[g], double(t), accJ64);
+        accE64 = fma(double(wg), double(t), accE64);
+        if (ja) accJ64 = fma(double(aj), double(t), accJ64);
       }
       eo = cmul(eo, uo);
       en = cmul(en, un);
+    }
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      rcur[j] = rnxt[j];
+      scur[j] = snxt[j];
     }
   }
   // real space
@@ -680,15 +719,19 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
   if (acc) {
     const R q = R(S->mobile_q[pk]);
     const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
+    double2* rho2 = reinterpret_cast<double2*>(rho);
     for (int s = tid; s < nseg; s += BLOCK) {
+      double2 r[SEG];
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) r[j] = rho2[size_t(j) * nseg + s];
       const uint32_t pn = S->seg_n[s];
       cplx<R> eo = anchor<DIM, R>(to, pn, nm);
       cplx<R> en = anchor<DIM, R>(tn, pn, nm);
 #pragma unroll
       for (int j = 0; j < SEG; ++j) {
-        const size_t g = size_t(j) * nseg + s;
-        rho[2 * g] += double(q * (en.x - eo.x));
-        rho[2 * g + 1] += double(q * (en.y - eo.y));
+        r[j].x += double(q * (en.x - eo.x));
+        r[j].y += double(q * (en.y - eo.y));
+        rho2[size_t(j) * nseg + s] = r[j];
         eo = cmul(eo, uo);
         en = cmul(en, un);
       }
@@ -748,18 +791,25 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
 }
 
 // ---------------------------------------------------------------------------
-// Fused multi-move: n_steps proposals per walker with rho, the shell indices
-// and the segment anchors in registers, and positions, charges, the shell
-// table and the phase tables in LDS for the whole sequence.  NT threads per
-// walker, SPT segments per thread.
+// Fused multi-move: n_steps proposals per walker with rho, the shell-table
+// offsets and the segment anchors in registers, and positions, charges and
+// the shell table in LDS for the whole sequence.  NT threads per walker,
+// SPT segments per thread.
 //
-// One barrier per move.  During move m the last threads also build the phase
-// tables of move m+1 (double buffer): the old position of move m+1 is
-// already known (it is the new position of move m when the same particle was
-// just accepted).  Each wave reduces its partial sums with DPP and parks them
-// in LDS; the cross-wave sums of a chunk of RUN_CHUNK moves are formed once,
-// in a fixed order, at the start of the next chunk.  Proposals are staged
-// per chunk in a two-slot ring.
+// Moves are processed in chunks of up to RUN_CHUNK with no barrier inside a
+// chunk.  Every piece of cross-thread information a move needs is fixed
+// before the chunk starts:
+//   - the proposals are staged in LDS, together with each move's old
+//     position (the latest accepted earlier move of the same particle in the
+//     chunk, else the position at the chunk start);
+//   - thread t owns the slots of its segments (it alone updates them) and the
+//     particles j = t, t + NT, ... (it alone reads and updates their LDS
+//     positions during the chunk);
+//   - each wave builds its own phase tables for every move;
+//   - each wave reduces its partial sums with DPP and parks them in LDS; the
+//     cross-wave sums of the chunk are formed after the chunk, in a fixed order.
+// A chunk ends early after a move that brings the accept counter to K, so the
+// FP64 rebuild of the mixed form runs between chunks.
 template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
 __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
@@ -771,7 +821,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   using WT = R;          // the mixed form multiplies weights with FP32 terms
   using WT2 = cplx<WT>;  // (weight, Jastrow coefficient)
   constexpr int NW = NT / 64;
-  constexpr int REDN = (NW + 2 * DIM + 1) & ~1;  // drift scratch + parked old positions
+  constexpr int CH = RUN_CHUNK;
   extern __shared__ double smem[];
   const DevWalker W = walkers[blockIdx.x];
   const int w = W.id, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -783,19 +833,23 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
   double* spos = reinterpret_cast<double*>(st + HDR_BYTES);
   double* rho = reinterpret_cast<double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
-  // LDS layout (in doubles): positions, charges, reduction scratch, two phase
-  // table buffers, shell table, proposal ring, partial-sum ring, rebuild tiles
+  // LDS layout (in doubles): positions, charges, scratch (NW, even), per-wave
+  // phase tables, shell table, staging (sn, so: [CH][DIM] each; partials
+  // [CH][NW][2]; k, accept, counter: [CH] ints each), rebuild tiles
   double* lpos = smem;
   double* lq = lpos + lds_pos * DIM;
-  double* red = lq + lds_pos;                                     // NW
-  double* so_buf = red + NW;                                      // [2][DIM] old position per table buffer
-  cplx<R>* tabs2 = reinterpret_cast<cplx<R>*>(red + REDN);         // [2][2 * DIM * tbl]
-  WT2* ltab = reinterpret_cast<WT2*>(red + REDN + 2 * lds_tab);
-  double* r_sn = red + REDN + 2 * lds_tab + lds_wtab;              // [2][RUN_CHUNK][DIM]
-  double* r_part = r_sn + 2 * RUN_CHUNK * DIM;                     // [2][RUN_CHUNK][NW][2]
-  int* r_k = reinterpret_cast<int*>(r_part + 2 * RUN_CHUNK * NW * 2);  // [2][RUN_CHUNK]
-  int* r_acc = r_k + 2 * RUN_CHUNK;                                     // [2][RUN_CHUNK]
-  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(r_acc + 2 * RUN_CHUNK);  // rebuild tiles
+  double* red = lq + lds_pos;
+  cplx<R>* wtabs = reinterpret_cast<cplx<R>*>(red + ((NW + 1) & ~1));  // [NW][2 * DIM * tbl]
+  WT2* ltab = reinterpret_cast<WT2*>(red + ((NW + 1) & ~1) + NW * lds_tab);
+  double* st_sn = red + ((NW + 1) & ~1) + NW * lds_tab + lds_wtab;
+  double* st_so = st_sn + CH * DIM;
+  double* st_part = st_so + CH * DIM;
+  int* st_k = reinterpret_cast<int*>(st_part + CH * NW * 2);
+  int* st_acc = st_k + CH;
+  int* st_cnt = st_acc + CH;
+  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(st_cnt + CH + (CH & 1));  // rebuild tiles
+  cplx<R>* to = wtabs + wave * 2 * DIM * tbl;
+  cplx<R>* tn = to + DIM * tbl;
 
   for (int i = tid; i < n * DIM; i += NT) lpos[i] = spos[i];
   for (int i = tid; i < n; i += NT) lq[i] = S->mobile_q[i];
@@ -821,167 +875,152 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
 #pragma unroll
     for (int j = 0; j < SEG; j += 2) {
       const size_t g = size_t(j) * nseg + s;
-      // LDS byte offsets of the (weight, Jastrow) entries
       shp[i][j / 2] = s < nseg ? uint32_t(S->slot_shell[g]) * uint32_t(sizeof(WT2)) |
                                      (uint32_t(S->slot_shell[g + nseg]) * uint32_t(sizeof(WT2)) << 16)
                                : 0u;
     }
   }
+  __syncthreads();
 
-  // stage the proposals of chunk c into ring slot c & 1 (one thread per move)
-  auto stage = [&](int c) {
-    const int m0 = c * RUN_CHUNK, cnt = min(RUN_CHUNK, n_steps - m0), par = c & 1;
+  for (int m0 = 0; m0 < n_steps;) {
+    // ---- stage the chunk ----
+    const int cnt = min(CH, n_steps - m0);
     if (tid < cnt) {
       const size_t idx = size_t(m0 + tid) * n_walkers + w;
       const int kv = kk[idx];
-      r_k[par * RUN_CHUNK + tid] = (kv < 0 || kv >= n) ? -1 : kv;
-      r_acc[par * RUN_CHUNK + tid] = accept[idx] != 0;
+      st_k[tid] = (kv < 0 || kv >= n) ? -1 : kv;
+      st_acc[tid] = accept[idx] != 0;
       double r[DIM], sv[DIM];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) r[d] = new_pos[idx * DIM + d];
       to_frac<DIM>(r, S->Ainv, sv);
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) r_sn[(par * RUN_CHUNK + tid) * DIM + d] = sv[d];
+      for (int d = 0; d < DIM; ++d) st_sn[tid * DIM + d] = sv[d];
     }
-  };
-  // fill the phase tables of move m (buffer m & 1) from its old position so
-  // and its staged new position; run by the last nfill threads
-  auto prepare = [&](int m, const double* so) {
-    const int par = (m / RUN_CHUNK) & 1, mm = m % RUN_CHUNK;
-    cplx<R>* to = tabs2 + (m & 1) * 2 * DIM * tbl;
-    cplx<R>* tn = to + DIM * tbl;
-    if (tid == NT - 1)
+    __syncthreads();
+    if (tid < cnt) {
+      const int k = st_k[tid];
+      int prev = -1, c = counter;
+      for (int q = 0; q < tid; ++q) {
+        const bool a = st_k[q] >= 0 && st_acc[q] != 0;
+        if (a && st_k[q] == k) prev = q;
+        c += a ? 1 : 0;
+      }
+      if (k >= 0) {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) so_buf[(m & 1) * DIM + d] = so[d];
-    for (int e = tid - (NT - nfill); e < nfill; e += NT) {
-      if (e < 0) continue;
-      if (e < DIM * (nm + 1)) {
-        fill_tables<DIM, R>(to, so, nm, e);
-      } else {
-        double sn[DIM];
+        for (int d = 0; d < DIM; ++d) st_so[tid * DIM + d] = prev >= 0 ? st_sn[prev * DIM + d] : lpos[k * DIM + d];
+      }
+      st_cnt[tid] = c + ((k >= 0 && st_acc[tid] != 0) ? 1 : 0);  // accepts since the rebuild, after this move
+    }
+    __syncthreads();
+    int len = cnt;
+    if (MIXED && K > 0)
+      for (int q = 0; q < cnt; ++q)
+        if (st_cnt[q] >= K) {
+          len = q + 1;
+          break;
+        }
+
+    // ---- the chunk's moves, no barrier ----
+    for (int mm = 0; mm < len; ++mm) {
+      const int k = st_k[mm];
+      double v0 = 0.0, v1 = 0.0;
+      if (k >= 0) {  // uniform
+        const bool acc = st_acc[mm] != 0;
+        const double qk = lq[k];
+        double sn[DIM], so[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) sn[d] = r_sn[(par * RUN_CHUNK + mm) * DIM + d];
-        fill_tables<DIM, R>(tn, sn, nm, e - DIM * (nm + 1));
+        for (int d = 0; d < DIM; ++d) {
+          sn[d] = st_sn[mm * DIM + d];
+          so[d] = st_so[mm * DIM + d];
+        }
+        if (qk != 0.0) {  // uniform; a neutral particle's move changes nothing
+          // this wave's phase tables for the move
+          for (int e = lane; e < nfill; e += 64) {
+            if (e < DIM * (nm + 1)) fill_tables<DIM, R>(to, so, nm, e);
+            else fill_tables<DIM, R>(tn, sn, nm, e - DIM * (nm + 1));
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
+          // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)], q^2 applied to the sums
+          const R q = R(qk), c2q = R(2.0 / qk);
+          double accE64 = 0.0, accJ64 = 0.0;
+          Kahan accE32, accJ32;
+#pragma unroll
+          for (int i = 0; i < SPT; ++i) {
+            if (tid + i * NT < nseg) {
+              cplx<R> eo = anchor<DIM, R>(to, an[i], nm);
+              cplx<R> en = anchor<DIM, R>(tn, an[i], nm);
+#pragma unroll
+              for (int j = 0; j < SEG; ++j) {
+                const WT2 wa = *reinterpret_cast<const WT2*>(reinterpret_cast<const char*>(ltab) +
+                                                             ((shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu));
+                const R dx = en.x - eo.x, dy = en.y - eo.y;
+                const R ux = fma(c2q, R(rv[i][j].x), dx), uy = fma(c2q, R(rv[i][j].y), dy);
+                const R t = fma(ux, dx, uy * dy);
+                if (MIXED) {
+                  accE32.add(float(wa.x) * float(t));
+                  if (JAS) accJ32.add(float(wa.y) * float(t));
+                } else {
+                  accE64 = fma(double(wa.x), double(t), accE64);
+                  if (JAS) accJ64 = fma(double(wa.y), double(t), accJ64);
+                }
+                if (acc) {
+                  rv[i][j].x += double(q * dx);
+                  rv[i][j].y += double(q * dy);
+                }
+                eo = cmul(eo, uo);
+                en = cmul(en, un);
+              }
+            }
+          }
+          const double q2 = qk * qk;
+          v0 = q2 * (MIXED ? accE32.value() : accE64);
+          v1 = q2 * (MIXED ? accJ32.value() : accJ64);
+          // real space over this thread's own particles (their LDS positions
+          // are read and written only by this thread during the chunk)
+          v0 += qk * real_move<DIM, MIXED, PD, NT>(sn, so, k, lpos, lq, n, S);
+          // the tables are rewritten by the next move of this wave
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (acc) {
+          if ((k % NT) == tid)  // the owner moves its particle
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) lpos[k * DIM + d] = sn[d];
+          n_acc += 1;
+        }
+      }
+      v0 = wave_sum_to_lane63(v0);
+      v1 = wave_sum_to_lane63(v1);
+      if (lane == 63) {
+        st_part[(mm * NW + wave) * 2] = v0;
+        st_part[(mm * NW + wave) * 2 + 1] = v1;
       }
     }
-  };
-  // sum the wave partials of chunk c (fixed order) and write its outputs
-  auto flush = [&](int c) {
-    const int m0 = c * RUN_CHUNK, cnt = min(RUN_CHUNK, n_steps - m0), par = c & 1;
-    if (tid < cnt) {
+    if (len > 0) counter = st_cnt[len - 1];
+    __syncthreads();  // partials and owner position updates complete
+
+    // ---- outputs of the chunk (cross-wave sums in a fixed order) ----
+    if (tid < len) {
       const size_t idx = size_t(m0 + tid) * n_walkers + w;
       double e = 0.0, j = 0.0;
-      if (r_k[par * RUN_CHUNK + tid] < 0) {
+      if (st_k[tid] < 0) {
         e = j = NAN;
       } else {
-        const double* pp = r_part + (par * RUN_CHUNK + tid) * NW * 2;
 #pragma unroll
         for (int v = 0; v < NW; ++v) {
-          e += pp[2 * v];
-          j += pp[2 * v + 1];
+          e += st_part[(tid * NW + v) * 2];
+          j += st_part[(tid * NW + v) * 2 + 1];
         }
       }
       delta[idx] = e;
       if (djas) djas[idx] = j;
     }
-  };
-
-  if (n_steps > 0) stage(0);
-  __syncthreads();
-  if (n_steps > 0 && r_k[0] >= 0) {
-    double so0[DIM];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) so0[d] = lpos[r_k[0] * DIM + d];
-    prepare(0, so0);
-  }
-  if (n_steps > RUN_CHUNK) stage(1);
-  __syncthreads();
-
-  for (int m = 0; m < n_steps; ++m) {
-    const int c = m / RUN_CHUNK, mm = m % RUN_CHUNK, par = c & 1;
-    if (mm == 0 && c > 0) {
-      flush(c - 1);  // partials of the previous chunk are complete
-      if ((c + 1) * RUN_CHUNK < n_steps) stage(c + 1);  // ring slot of chunk c-1 is free now
-    }
-    const int k = r_k[par * RUN_CHUNK + mm];
-    const bool acc = k >= 0 && r_acc[par * RUN_CHUNK + mm] != 0;
-    double sn[DIM];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) sn[d] = r_sn[(par * RUN_CHUNK + mm) * DIM + d];
-    if (acc && tid == 0)  // nobody reads the old position of k after the last barrier
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) lpos[k * DIM + d] = sn[d];
-    // tables of the next move
-    if (m + 1 < n_steps) {
-      const int c1 = (m + 1) / RUN_CHUNK, mm1 = (m + 1) % RUN_CHUNK;
-      const int k1 = r_k[(c1 & 1) * RUN_CHUNK + mm1];
-      if (k1 >= 0) {
-        double so1[DIM];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) so1[d] = (acc && k1 == k) ? sn[d] : lpos[k1 * DIM + d];
-        prepare(m + 1, so1);
-      }
-    }
-    double v0 = 0.0, v1 = 0.0;
-    if (k >= 0 && lq[k] != 0.0) {  // uniform; a neutral particle's move changes nothing
-      const cplx<R>* to = tabs2 + (m & 1) * 2 * DIM * tbl;
-      const cplx<R>* tn = to + DIM * tbl;
-      double so[DIM];  // old position of k, parked by the threads that built the tables
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) so[d] = so_buf[(m & 1) * DIM + d];
-      const double qk = lq[k];
-      const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
-      // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)], q^2 applied to the sums
-      const R q = R(qk), c2q = R(2.0 / qk);
-      double accE64 = 0.0, accJ64 = 0.0;
-      Kahan accE32, accJ32;
-#pragma unroll
-      for (int i = 0; i < SPT; ++i) {
-        if (tid + i * NT < nseg) {
-          cplx<R> eo = anchor<DIM, R>(to, an[i], nm);
-          cplx<R> en = anchor<DIM, R>(tn, an[i], nm);
-#pragma unroll
-          for (int j = 0; j < SEG; ++j) {
-            const WT2 wa = *reinterpret_cast<const WT2*>(reinterpret_cast<const char*>(ltab) +
-                                                         ((shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu));
-            const R dx = en.x - eo.x, dy = en.y - eo.y;
-            const R ux = fma(c2q, R(rv[i][j].x), dx), uy = fma(c2q, R(rv[i][j].y), dy);
-            const R t = fma(ux, dx, uy * dy);
-            if (MIXED) {
-              accE32.add(float(wa.x) * float(t));
-              if (JAS) accJ32.add(float(wa.y) * float(t));
-            } else {
-              accE64 = fma(double(wa.x), double(t), accE64);
-              if (JAS) accJ64 = fma(double(wa.y), double(t), accJ64);
-            }
-            if (acc) {
-              rv[i][j].x += double(q * dx);
-              rv[i][j].y += double(q * dy);
-            }
-            eo = cmul(eo, uo);
-            en = cmul(en, un);
-          }
-        }
-      }
-      const double q2 = qk * qk;
-      v0 = q2 * (MIXED ? accE32.value() : accE64);
-      v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-      v0 += qk * real_move<DIM, MIXED, PD, NT>(sn, so, k, lpos, lq, n, S);
-    }
-    v0 = wave_sum_to_lane63(v0);
-    v1 = wave_sum_to_lane63(v1);
-    if (lane == 63) {
-      double* pp = r_part + ((par * RUN_CHUNK + mm) * NW + wave) * 2;
-      pp[0] = v0;
-      pp[1] = v1;
-    }
-    if (acc) {
-      counter += 1;
-      n_acc += 1;
-    }
-    __syncthreads();  // the one barrier of the move
-    if (MIXED && K > 0 && counter >= K) {  // uniform
-      // park the running rho in the state, rebuild in registers, compare
+    if (MIXED && K > 0 && counter >= K) {  // uniform: rebuild rho in FP64 between chunks
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
         const int s = tid + i * NT;
@@ -1009,14 +1048,14 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
       if (lane == 0) red[wave] = dm;
       __syncthreads();
       for (int k2 = 0; k2 < NW; ++k2) drift = fmax(drift, red[k2]);
-      __syncthreads();
       counter = 0;
       n_ref += 1;
     }
+    __syncthreads();  // staging buffers are reused by the next chunk
+    m0 += len;
   }
-  if (n_steps > 0) flush((n_steps - 1) / RUN_CHUNK);
 
-  // write back
+  // write back (n_acc counted by every thread alike)
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
     const int s = tid + i * NT;
@@ -1101,13 +1140,15 @@ template <int DIM, bool MIXED>
 int delta_dim(const LaunchBatch& b, char* state, const int32_t* k, const double* new_pos, double* delta,
               double* djas, void* stream) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  const size_t lds = 16 * 8 + size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
+  const size_t mtab = size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
+  const int lds_tab = even(int((mtab + 7) / 8));  // in doubles
+  const size_t lds = 16 * 8 + size_t(lds_tab) * 8 + size_t(b.max_wtab) * sizeof(cplx<R>);
   if (b.poly_deg <= 16)
     hipLaunchKernelGGL((k_delta<DIM, MIXED, 16>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
-                       b.d_sys, b.d_walk, state, k, new_pos, delta, djas);
+                       b.d_sys, b.d_walk, state, k, new_pos, delta, djas, lds_tab);
   else
     hipLaunchKernelGGL((k_delta<DIM, MIXED, 32>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
-                       b.d_sys, b.d_walk, state, k, new_pos, delta, djas);
+                       b.d_sys, b.d_walk, state, k, new_pos, delta, djas, lds_tab);
   return last_launch();
 }
 
@@ -1130,15 +1171,15 @@ template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
 int run_inst(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
              const uint8_t* accept, double* delta, double* djas, void* stream) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  const int redn = (NT / 64 + 2 * DIM + 1) & ~1;
+  constexpr int NW = NT / 64, CH = RUN_CHUNK;
   const int lds_pos = even(b.max_particles);
   const size_t mtab = size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
-  const int lds_tab = even(int((mtab + 7) / 8));  // one table buffer, in doubles
+  const int lds_tab = even(int((mtab + 7) / 8));  // one wave's tables, in doubles
   const size_t rtab = MIXED ? size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>) : 0;
   const int lds_wtab = even(int((size_t(b.max_wtab) * sizeof(cplx<R>) + 7) / 8));  // in doubles
-  const size_t ring = size_t(2) * RUN_CHUNK * (DIM + 2 * (NT / 64)) * 8 + size_t(2) * RUN_CHUNK * 2 * 4;
-  const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + size_t(redn) * 8 + size_t(2 * lds_tab) * 8 +
-                     size_t(lds_wtab) * 8 + ring + rtab;
+  const size_t stage = (size_t(2) * CH * DIM + size_t(CH) * NW * 2) * 8 + size_t(3 * CH + (CH & 1)) * 4;
+  const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + size_t(even(NW)) * 8 + size_t(NW) * lds_tab * 8 +
+                     size_t(lds_wtab) * 8 + stage + rtab;
   if (int rc = allow_lds(k_run<DIM, MIXED, NT, SPT, JAS, PD>, lds)) return rc;
   hipLaunchKernelGGL((k_run<DIM, MIXED, NT, SPT, JAS, PD>), dim3(b.n_walkers), dim3(NT), lds, as_stream(stream),
                      b.d_sys, b.d_walk, state, n_steps, b.n_walkers, k, new_pos, accept, delta, djas, lds_pos,

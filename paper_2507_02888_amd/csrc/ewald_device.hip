@@ -20,6 +20,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -191,6 +192,17 @@ struct Kahan {
 template <bool MIXED, int PD>
 struct PairAcc;
 
+// 1/sqrt(x) for x in (0, r_cut^2]: the hardware estimate refined by one
+// Newton step carried to second order, y (1 + e/2 + 3e^2/8) with
+// e = 1 - x y^2 (remaining relative error ~5e^3/16).  Unlike the library
+// rsqrt it has no zero/infinity/denormal handling, which the pair terms never
+// need (coincident particles are documented as giving non-finite results).
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // Pair terms are evaluated several at a time (NE = 2 or 4): the four Horner chains interleave
 // (latency hiding) and take their coefficients straight from scalar registers.
 // A term enters iff r2 < r_cut^2; callers pad with r2 = r_cut^2 and q = 0.
@@ -203,7 +215,7 @@ struct PairAcc<false, PD> {
     const double scale = S->poly_scale;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      ir[e] = rsqrt(r2[e]);
+      ir[e] = rsqrt_pos(r2[e]);
       t[e] = fma(r2[e], scale, -1.0);
       p[e] = S->p64[PD];
     }
@@ -235,7 +247,7 @@ struct PairAcc<true, PD> {
     const float scale = float(S->poly_scale);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      ir[e] = rsqrt(r2[e]);
+      ir[e] = rsqrt_pos(r2[e]);
       t[e] = fmaf(float(r2[e]), scale, -1.0f);
       p[e] = S->p32[PF];
     }
@@ -311,6 +323,63 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
   return pr.value();
 }
 
+// Real-space part of a move inside the fused sweep.  Thread t owns the
+// particles j = t + c NT (c < PPR) and keeps their positions and charges in
+// registers (ps, pq); it alone updates them when they move.  Particles beyond
+// PPR NT (larger systems than the launch shape covers) are read from the LDS
+// copy, again only by their owner t = j mod NT.
+template <int DIM, bool MIXED, int PD, int NT, int PPR>
+__device__ __forceinline__ double real_move_own(const double* sn, const double* so, int k,
+                                                const double (&ps)[PPR][DIM], const double (&pq)[PPR],
+                                                const double* lpos, const double* lq, int n,
+                                                const DevSys* __restrict__ S) {
+  PairAcc<MIXED, PD> pr;
+  const int n_cand = S->n_cand;
+  const double rc2 = S->rc2;
+  {
+    double qq[2 * PPR], r2[2 * PPR];
+#pragma unroll
+    for (int c = 0; c < PPR; ++c) {
+      const int j = threadIdx.x + c * NT;
+      const bool ok = j < n && j != k;
+      r2[2 * c] = ok ? min_r2<DIM>(sn, ps[c], S, n_cand) : rc2;
+      r2[2 * c + 1] = ok ? min_r2<DIM>(so, ps[c], S, n_cand) : rc2;
+      qq[2 * c] = pq[c];
+      qq[2 * c + 1] = -pq[c];
+    }
+    pr.template add<2 * PPR>(qq, r2, S);
+  }
+  for (int j = threadIdx.x + PPR * NT; j < n; j += NT) {
+    double qq[2], r2[2];
+    const bool ok = j != k;
+    r2[0] = ok ? min_r2<DIM>(sn, lpos + j * DIM, S, n_cand) : rc2;
+    r2[1] = ok ? min_r2<DIM>(so, lpos + j * DIM, S, n_cand) : rc2;
+    qq[0] = lq[j];
+    qq[1] = -lq[j];
+    pr.template add<2>(qq, r2, S);
+  }
+  const int nfix = S->n_fixed;
+  for (int j0 = threadIdx.x; j0 < nfix; j0 += 2 * NT) {
+    double qq[4], r2[4];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int j = j0 + c * NT;
+      const bool ok = j < nfix;
+      const int jj = ok ? j : nfix - 1;
+      double sj[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sj[d] = S->fixed_s[jj * DIM + d];
+      const double qj = ok ? S->fixed_q[jj] : 0.0;
+      r2[2 * c] = ok ? min_r2<DIM>(sn, sj, S, n_cand) : rc2;
+      r2[2 * c + 1] = ok ? min_r2<DIM>(so, sj, S, n_cand) : rc2;
+      qq[2 * c] = qj;
+      qq[2 * c + 1] = -qj;
+    }
+    pr.template add<4>(qq, r2, S);
+  }
+  return pr.value();
+}
+
 // Sum NV values over a workgroup of NT threads; the result is valid in
 // thread 0.  red must hold NV * NT / 64 doubles.
 template <int NV, int NT = BLOCK>
@@ -343,6 +412,23 @@ __device__ __forceinline__ double dpp_take(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
   return __hiloint2double(hi, lo);
+}
+
+// Sum over each row of 16 lanes with DPP moves whose every lane has a source
+// (no previous value to preserve); every lane of a row ends with the row sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_all(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_all<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_all<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_all<0x141>(v);  // row_half_mirror
+  v += dpp_all<0x140>(v);  // row_mirror
+  return v;
 }
 
 __device__ __forceinline__ double wave_sum_to_lane63(double v) {
@@ -381,12 +467,12 @@ __device__ __forceinline__ cplx<R> anchor(const cplx<R>* tab, uint32_t pn, int n
 
 // Rebuild rho over the segments segs[i] = seg0 + i * NT (i < NS) of one
 // walker in FP64: rho = rho_fix + sum_p q_p exp(i G.r_p), particles taken
-// TILE_P at a time through LDS phase tables (tabs: TILE_P * DIM * (2nm+1)).
+// `tile` at a time through LDS phase tables (tabs: tile * DIM * (2nm+1)).
 // `pos` may point to global or LDS memory.  All NT threads must call it.
 template <int DIM, int NS, int NT = BLOCK>
 __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[NS], int seg0,
                             const DevSys* __restrict__ S, const double* pos, const double* q, int n,
-                            cplx<double>* tabs) {
+                            cplx<double>* tabs, int tile = TILE_P) {
   const int nseg = S->n_seg, nm = S->nm, tbl = 2 * nm + 1;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
@@ -401,8 +487,8 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
       }
     }
   }
-  for (int p0 = 0; p0 < n; p0 += TILE_P) {
-    const int np = min(TILE_P, n - p0);
+  for (int p0 = 0; p0 < n; p0 += tile) {
+    const int np = min(tile, n - p0);
     for (int e = threadIdx.x; e < np * DIM * (nm + 1); e += NT) {
       const int p = e / (DIM * (nm + 1));
       double sp[DIM];
@@ -792,64 +878,69 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
 
 // ---------------------------------------------------------------------------
 // Fused multi-move: n_steps proposals per walker with rho, the shell-table
-// offsets and the segment anchors in registers, and positions, charges and
-// the shell table in LDS for the whole sequence.  NT threads per walker,
-// SPT segments per thread.
+// offsets, the segment anchors and the thread's own particles in registers,
+// and positions, charges, the shell table and the chunk's phase tables in LDS
+// for the whole sequence.  NT threads per walker, SPT segments per thread.
 //
-// Moves are processed in chunks of up to RUN_CHUNK with no barrier inside a
-// chunk.  Every piece of cross-thread information a move needs is fixed
-// before the chunk starts:
+// Moves are processed in chunks of up to `ch` with no barrier inside a chunk.
+// Every piece of cross-thread information a move needs is fixed before the
+// chunk starts:
 //   - the proposals are staged in LDS, together with each move's old
 //     position (the latest accepted earlier move of the same particle in the
 //     chunk, else the position at the chunk start);
+//   - the per-dimension phase tables of every move's old and new position
+//     are built by the whole workgroup, once per chunk;
 //   - thread t owns the slots of its segments (it alone updates them) and the
-//     particles j = t, t + NT, ... (it alone reads and updates their LDS
-//     positions during the chunk);
-//   - each wave builds its own phase tables for every move;
-//   - each wave reduces its partial sums with DPP and parks them in LDS; the
-//     cross-wave sums of the chunk are formed after the chunk, in a fixed order.
+//     particles j = t, t + NT, ... (it alone reads and updates them during
+//     the chunk);
+//   - each wave reduces its partial sums per row of 16 lanes with DPP and
+//     parks the four row sums in LDS; the cross-row sums of the chunk are
+//     formed after the chunk, in a fixed order.
 // A chunk ends early after a move that brings the accept counter to K, so the
 // FP64 rebuild of the mixed form runs between chunks.
+struct RunLds {
+  // byte offsets into dynamic LDS; positions start at 0
+  uint32_t q, red, wtab, ctab, sn, so, part, k, acc, cnt;
+  int ch;     // moves per chunk
+  int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
+};
+
 template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
 __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
                                             const double* __restrict__ new_pos, const uint8_t* __restrict__ accept,
-                                            double* __restrict__ delta, double* __restrict__ djas, int lds_pos,
-                                            int lds_tab, int lds_wtab) {
+                                            double* __restrict__ delta, double* __restrict__ djas, RunLds L) {
   using R = typename std::conditional<MIXED, float, double>::type;
   using WT = R;          // the mixed form multiplies weights with FP32 terms
   using WT2 = cplx<WT>;  // (weight, Jastrow coefficient)
   constexpr int NW = NT / 64;
-  constexpr int CH = RUN_CHUNK;
-  extern __shared__ double smem[];
+  constexpr int PPR = NT >= 1024 ? 1 : 2;  // own particles per thread held in registers
+  extern __shared__ __align__(16) char lds[];
   const DevWalker W = walkers[blockIdx.x];
   const int w = W.id, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
   const int K = S->refresh_every, tbl = 2 * nm + 1;
-  const int nfill = 2 * DIM * (nm + 1);  // table entries per move
+  const int per = DIM * (nm + 1);    // table entries computed per position (n >= 0)
+  const int mstride = 2 * DIM * tbl;  // one move's tables (old, new), in entries
+  const int CH = L.ch;
   char* st = state + W.state_off;
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
   double* spos = reinterpret_cast<double*>(st + HDR_BYTES);
   double* rho = reinterpret_cast<double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
-  // LDS layout (in doubles): positions, charges, scratch (NW, even), per-wave
-  // phase tables, shell table, staging (sn, so: [CH][DIM] each; partials
-  // [CH][NW][2]; k, accept, counter: [CH] ints each), rebuild tiles
-  double* lpos = smem;
-  double* lq = lpos + lds_pos * DIM;
-  double* red = lq + lds_pos;
-  cplx<R>* wtabs = reinterpret_cast<cplx<R>*>(red + ((NW + 1) & ~1));  // [NW][2 * DIM * tbl]
-  WT2* ltab = reinterpret_cast<WT2*>(red + ((NW + 1) & ~1) + NW * lds_tab);
-  double* st_sn = red + ((NW + 1) & ~1) + NW * lds_tab + lds_wtab;
-  double* st_so = st_sn + CH * DIM;
-  double* st_part = st_so + CH * DIM;
-  int* st_k = reinterpret_cast<int*>(st_part + CH * NW * 2);
-  int* st_acc = st_k + CH;
-  int* st_cnt = st_acc + CH;
-  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(st_cnt + CH + (CH & 1));  // rebuild tiles
-  cplx<R>* to = wtabs + wave * 2 * DIM * tbl;
-  cplx<R>* tn = to + DIM * tbl;
+  double* lpos = reinterpret_cast<double*>(lds);
+  double* lq = reinterpret_cast<double*>(lds + L.q);
+  double* red = reinterpret_cast<double*>(lds + L.red);
+  WT2* ltab = reinterpret_cast<WT2*>(lds + L.wtab);
+  cplx<R>* ctab = reinterpret_cast<cplx<R>*>(lds + L.ctab);
+  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(lds + L.ctab);  // rebuild tiles, between chunks
+  double* st_sn = reinterpret_cast<double*>(lds + L.sn);
+  double* st_so = reinterpret_cast<double*>(lds + L.so);
+  double* st_part = reinterpret_cast<double*>(lds + L.part);  // [CH][NW][4 rows][2]
+  int* st_k = reinterpret_cast<int*>(lds + L.k);
+  int* st_acc = reinterpret_cast<int*>(lds + L.acc);
+  int* st_cnt = reinterpret_cast<int*>(lds + L.cnt);
 
   for (int i = tid; i < n * DIM; i += NT) lpos[i] = spos[i];
   for (int i = tid; i < n; i += NT) lq[i] = S->mobile_q[i];
@@ -860,6 +951,14 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   double drift = hdr->drift_max;
   if (K > 0 && counter >= K) counter = 0;
 
+  double ps[PPR][DIM], pq[PPR];
+#pragma unroll
+  for (int c = 0; c < PPR; ++c) {
+    const int j = tid + c * NT;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ps[c][d] = j < n ? spos[j * DIM + d] : 0.0;
+    pq[c] = j < n ? S->mobile_q[j] : 0.0;
+  }
   uint32_t an[SPT];
   cplx<double> rv[SPT][SEG];
   uint32_t shp[SPT][SEG / 2];  // two 16-bit shell-table byte offsets per register
@@ -883,7 +982,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   __syncthreads();
 
   for (int m0 = 0; m0 < n_steps;) {
-    // ---- stage the chunk ----
+    // ---- stage the chunk: proposals, old positions, accept counts ----
     const int cnt = min(CH, n_steps - m0);
     if (tid < cnt) {
       const size_t idx = size_t(m0 + tid) * n_walkers + w;
@@ -920,6 +1019,16 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           len = q + 1;
           break;
         }
+    // ---- phase tables of every move of the chunk (old, then new position) ----
+    for (int e = tid; e < len * 2 * per; e += NT) {
+      const int q = e / (2 * per), r = e - q * (2 * per);
+      if (st_k[q] >= 0) {
+        const bool nw = r >= per;
+        fill_tables<DIM, R>(ctab + q * mstride + (nw ? DIM * tbl : 0), (nw ? st_sn : st_so) + q * DIM, nm,
+                            nw ? r - per : r);
+      }
+    }
+    __syncthreads();
 
     // ---- the chunk's moves, no barrier ----
     for (int mm = 0; mm < len; ++mm) {
@@ -935,14 +1044,8 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           so[d] = st_so[mm * DIM + d];
         }
         if (qk != 0.0) {  // uniform; a neutral particle's move changes nothing
-          // this wave's phase tables for the move
-          for (int e = lane; e < nfill; e += 64) {
-            if (e < DIM * (nm + 1)) fill_tables<DIM, R>(to, so, nm, e);
-            else fill_tables<DIM, R>(tn, sn, nm, e - DIM * (nm + 1));
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const cplx<R>* to = ctab + mm * mstride;
+          const cplx<R>* tn = to + DIM * tbl;
           const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
           // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)], q^2 applied to the sums
           const R q = R(qk), c2q = R(2.0 / qk);
@@ -978,43 +1081,45 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           }
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
-          v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-          // real space over this thread's own particles (their LDS positions
-          // are read and written only by this thread during the chunk)
-          v0 += qk * real_move<DIM, MIXED, PD, NT>(sn, so, k, lpos, lq, n, S);
-          // the tables are rewritten by the next move of this wave
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
+          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR>(sn, so, k, ps, pq, lpos, lq, n, S);
         }
         if (acc) {
-          if ((k % NT) == tid)  // the owner moves its particle
+          if ((k % NT) == tid) {  // the owner moves its particle
 #pragma unroll
             for (int d = 0; d < DIM; ++d) lpos[k * DIM + d] = sn[d];
+#pragma unroll
+            for (int c = 0; c < PPR; ++c)
+              if (k == tid + c * NT)
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) ps[c][d] = sn[d];
+          }
           n_acc += 1;
         }
       }
-      v0 = wave_sum_to_lane63(v0);
-      v1 = wave_sum_to_lane63(v1);
-      if (lane == 63) {
-        st_part[(mm * NW + wave) * 2] = v0;
-        st_part[(mm * NW + wave) * 2 + 1] = v1;
+      v0 = row_sum16(v0);
+      if (JAS) v1 = row_sum16(v1);
+      if ((lane & 15) == 0) {
+        double* p = st_part + ((mm * NW + wave) * 4 + (lane >> 4)) * 2;
+        p[0] = v0;
+        p[1] = v1;
       }
     }
     if (len > 0) counter = st_cnt[len - 1];
     __syncthreads();  // partials and owner position updates complete
 
-    // ---- outputs of the chunk (cross-wave sums in a fixed order) ----
+    // ---- outputs of the chunk (cross-row sums in a fixed order) ----
     if (tid < len) {
       const size_t idx = size_t(m0 + tid) * n_walkers + w;
       double e = 0.0, j = 0.0;
       if (st_k[tid] < 0) {
         e = j = NAN;
       } else {
+        const double* p = st_part + tid * NW * 8;
 #pragma unroll
-        for (int v = 0; v < NW; ++v) {
-          e += st_part[(tid * NW + v) * 2];
-          j += st_part[(tid * NW + v) * 2 + 1];
+        for (int v = 0; v < NW * 4; ++v) {
+          e += p[2 * v];
+          j += p[2 * v + 1];
         }
       }
       delta[idx] = e;
@@ -1032,7 +1137,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
             rho[2 * g + 1] = rv[i][j].y;
           }
       }
-      rebuild_rho<DIM, SPT, NT>(rv, an, tid, S, lpos, lq, n, tabs);
+      rebuild_rho<DIM, SPT, NT>(rv, an, tid, S, lpos, lq, n, tabs, L.rtile);
       double dm = 0.0;
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
@@ -1051,7 +1156,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
       counter = 0;
       n_ref += 1;
     }
-    __syncthreads();  // staging buffers are reused by the next chunk
+    __syncthreads();  // staging buffers and tables are reused by the next chunk
     m0 += len;
   }
 
@@ -1167,23 +1272,57 @@ int accept_dim(const LaunchBatch& b, char* state, const uint8_t* accept, void* s
   return last_launch();
 }
 
+constexpr size_t RUN_LDS_BUDGET = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int RUN_NO_FIT = -1;                 // the fused kernel's LDS does not fit: use the per-step kernels
+
+size_t up16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// LDS layout of the fused kernel for a chunk of ch moves; returns the total bytes.
+template <int DIM, bool MIXED, int NT>
+size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
+  using R = typename std::conditional<MIXED, float, double>::type;
+  constexpr int NW = NT / 64;
+  const size_t tbl = size_t(2 * b.max_nm + 1);
+  const size_t mtab = 2 * DIM * tbl * sizeof(cplx<R>);                 // one move's tables
+  const size_t rpart = DIM * tbl * sizeof(cplx<double>);               // one rebuild particle
+  size_t o = up16(size_t(b.max_particles) * DIM * 8);
+  L.q = uint32_t(o);
+  o = up16(o + size_t(b.max_particles) * 8);
+  L.red = uint32_t(o);
+  o = up16(o + size_t(NW) * 8);
+  L.wtab = uint32_t(o);
+  o = up16(o + size_t(b.max_wtab) * sizeof(cplx<R>));
+  L.ctab = uint32_t(o);
+  const size_t ctab = std::max(size_t(ch) * mtab, size_t(TILE_P) * rpart);
+  o = up16(o + ctab);
+  L.sn = uint32_t(o);
+  o = up16(o + size_t(ch) * DIM * 8);
+  L.so = uint32_t(o);
+  o = up16(o + size_t(ch) * DIM * 8);
+  L.part = uint32_t(o);
+  o = up16(o + size_t(ch) * NW * 8 * 8);
+  L.k = uint32_t(o);
+  o = up16(o + size_t(ch) * 4);
+  L.acc = uint32_t(o);
+  o = up16(o + size_t(ch) * 4);
+  L.cnt = uint32_t(o);
+  o = up16(o + size_t(ch) * 4);
+  L.ch = ch;
+  L.rtile = int(std::min<size_t>(ctab / rpart, 64));
+  return o;
+}
+
 template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
 int run_inst(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
              const uint8_t* accept, double* delta, double* djas, void* stream) {
-  using R = typename std::conditional<MIXED, float, double>::type;
-  constexpr int NW = NT / 64, CH = RUN_CHUNK;
-  const int lds_pos = even(b.max_particles);
-  const size_t mtab = size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
-  const int lds_tab = even(int((mtab + 7) / 8));  // one wave's tables, in doubles
-  const size_t rtab = MIXED ? size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>) : 0;
-  const int lds_wtab = even(int((size_t(b.max_wtab) * sizeof(cplx<R>) + 7) / 8));  // in doubles
-  const size_t stage = (size_t(2) * CH * DIM + size_t(CH) * NW * 2) * 8 + size_t(3 * CH + (CH & 1)) * 4;
-  const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + size_t(even(NW)) * 8 + size_t(NW) * lds_tab * 8 +
-                     size_t(lds_wtab) * 8 + stage + rtab;
+  RunLds L{};
+  int ch = RUN_CHUNK;
+  size_t lds = run_layout<DIM, MIXED, NT>(b, ch, L);
+  while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT>(b, --ch, L);
+  if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
   if (int rc = allow_lds(k_run<DIM, MIXED, NT, SPT, JAS, PD>, lds)) return rc;
   hipLaunchKernelGGL((k_run<DIM, MIXED, NT, SPT, JAS, PD>), dim3(b.n_walkers), dim3(NT), lds, as_stream(stream),
-                     b.d_sys, b.d_walk, state, n_steps, b.n_walkers, k, new_pos, accept, delta, djas, lds_pos,
-                     lds_tab, lds_wtab);
+                     b.d_sys, b.d_walk, state, n_steps, b.n_walkers, k, new_pos, accept, delta, djas, L);
   return last_launch();
 }
 
@@ -1238,21 +1377,23 @@ int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void
 
 int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
                const uint8_t* accept, double* delta, double* djas, void* stream) {
-  if (!b.all_wtab_lds) {
-    // a shell table too large for LDS: the same sequence through the per-step kernels
-    const size_t W = size_t(b.n_walkers);
-    for (int m = 0; m < n_steps; ++m) {
-      int rc = launch_delta(b, state, k + m * W, new_pos + m * W * b.dim, delta + m * W, djas ? djas + m * W : nullptr,
-                            stream);
-      if (!rc) rc = launch_accept(b, state, accept + m * W, stream);
-      if (rc) return rc;
-    }
-    return 0;
-  }
-  if (b.dim == 3) return b.mixed ? run_dim<3, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
+  int rc = RUN_NO_FIT;
+  if (b.all_wtab_lds) {
+    if (b.dim == 3) rc = b.mixed ? run_dim<3, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
                                  : run_dim<3, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-  return b.mixed ? run_dim<2, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-                 : run_dim<2, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+    else rc = b.mixed ? run_dim<2, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
+                      : run_dim<2, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+  }
+  if (rc != RUN_NO_FIT) return rc;
+  // a shell table or walker too large for LDS: the same sequence through the per-step kernels
+  const size_t W = size_t(b.n_walkers);
+  for (int m = 0; m < n_steps; ++m) {
+    rc = launch_delta(b, state, k + m * W, new_pos + m * W * b.dim, delta + m * W, djas ? djas + m * W : nullptr,
+                      stream);
+    if (!rc) rc = launch_accept(b, state, accept + m * W, stream);
+    if (rc) return rc;
+  }
+  return 0;
 }
 
 int dev_alloc(void** p, size_t bytes) {

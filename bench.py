@@ -70,7 +70,8 @@ def traffic_from_profiles(form: str):
     return None if f is None else f.get("hbm_bytes_per_launch")
 
 
-def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int):
+def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_step: bool = True,
+             threads: int = 0):
     import torch
     from paper_2507_02888_amd import ewald as ew
     cfg, b = batch_inputs["cfg"], batch_inputs["b"]
@@ -80,6 +81,14 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int):
                   jastrow_a=b.jastrow_a)
     batch = ew.Batch([s], b.walker_sys, device=dev)
     t = batch_inputs["tensors"]
+    # launch shape: the autotuner's choice (probe sweep of rejected moves,
+    # outside the timed region), or a fixed workgroup size
+    batch.energy(t["pos"], torch.zeros(b.walkers, dtype=torch.float64, device=dev))
+    if threads:
+        batch.set_tuning(threads=threads)
+    else:
+        batch.autotune(n_moves=32)
+    tuning = batch.tuning()
     W, S = b.walkers, b.steps
     energy = torch.zeros(W, dtype=torch.float64, device=dev)
     jas = torch.zeros(W, dtype=torch.float64, device=dev)
@@ -122,8 +131,12 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int):
     d = delta.cpu().numpy()
     assert np.all(np.isfinite(d))
     out = dict(elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, energy_ms=float(np.mean(e_ms)),
-               run_ms=float(np.mean(r_ms)), n_refresh=n_refresh_total, sample_delta=d[:4, 0].tolist(),
+               run_ms=float(np.mean(r_ms)), n_refresh=n_refresh_total, sample_delta=d[:4, 0].tolist(), tuning=tuning,
                drift_max=max(h["drift_max"] for h in hdr))
+    if not per_step:
+        batch.close()
+        s.close()
+        return out
     # per-step path (move_delta + accept per call), a short sweep for its rate
     n_ps = 16
     batch.energy(t["pos"], energy, jas)
@@ -169,7 +182,22 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--threads", type=int, default=0,
+                    help="fixed fused-kernel workgroup size instead of the autotuner's choice")
+    ap.add_argument("--k-sweep", default="128,256,512,0",
+                    help="further refresh intervals K timed for the mixed form (0 = no rebuild); empty to skip")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b_ = torch.empty_like(a)
+        for _ in range(3):
+            b_.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": a.numel() * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (walkers shard "
               "trivially across GPUs, but this build measures the one-GPU path)", file=sys.stderr)
@@ -199,7 +227,7 @@ def main():
     results = {}
     for form in args.forms.split(","):
         prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
-        r = run_form(prec, inputs, args.steps, args.warmup, K)
+        r = run_form(prec, inputs, args.steps, args.warmup, K, threads=args.threads)
         flops_run = deltas_per_step * algorithmic_flops_per_delta(n_g, n_part) + \
             r["n_refresh"] * algorithmic_flops_per_rebuild(n_g, n_part)
         achieved = flops_run / (r["run_ms"] * 1e-3) / 1e12
@@ -208,6 +236,7 @@ def main():
         r["roofline"] = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
                              frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=traffic,
                              kernel=f"k_run ({form}), fused {S}-move sweep of {W} walkers",
+                             launch_shape=r["tuning"],
                              flop_per_launch=flops_run, launch_ms=round(r["run_ms"], 4),
                              frac_of_packed_fp32_peak=round(achieved / PEAK_FP32_PACKED_TFLOPS, 4)
                              if form == "mixed" else None)
@@ -216,6 +245,18 @@ def main():
         r["energy_kernel"] = dict(ms=round(r["energy_ms"], 4), achieved_tflops=round(e_flops / (r["energy_ms"] * 1e-3) / 1e12, 3))
         r["per_step_deltas_per_s"] = W / (r["per_step_ms_per_move"] * 1e-3)
         results[form] = r
+
+    sweep = []
+    if "mixed" in results and args.k_sweep:
+        for k_alt in [int(x) for x in args.k_sweep.split(",")]:
+            r = run_form(ew.EWALD_FP32_MIXED, inputs, max(1, min(args.steps, 2)), 1, k_alt, per_step=False,
+                         threads=args.threads)
+            flops_run = deltas_per_step * algorithmic_flops_per_delta(n_g, n_part) + \
+                r["n_refresh"] * algorithmic_flops_per_rebuild(n_g, n_part)
+            sweep.append(dict(refresh_every=k_alt, run_deltas_per_s=round(deltas_per_step / (r["run_ms"] * 1e-3), 1),
+                              launch_ms=round(r["run_ms"], 4), rebuilds=r["n_refresh"],
+                              frac=round(flops_run / (r["run_ms"] * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4),
+                              drift_max=r["drift_max"] if k_alt > 0 else None))
 
     cpu = None
     if not args.no_cpu:
@@ -245,6 +286,11 @@ def main():
         "energies_per_s": round(head["energies_per_s"], 1),
         "per_step_path_deltas_per_s": round(head["per_step_deltas_per_s"], 1),
     }
+    if sweep:
+        k_main = results["mixed"]
+        line["mixed_refresh_sweep"] = [dict(refresh_every=K, run_deltas_per_s=round(deltas_per_step / (k_main["run_ms"] * 1e-3), 1),
+                                            launch_ms=round(k_main["run_ms"], 4), rebuilds=k_main["n_refresh"],
+                                            frac=k_main["roofline"]["frac"], drift_max=k_main["drift_max"])] + sweep
     if "fp64" in results and "mixed" in results:
         f = results["fp64"]
         line["fp64"] = {"value": round(f["value"], 1), "unit": "deltas/s", "ms_per_step": round(f["ms_per_step"], 3),

@@ -138,6 +138,16 @@ ewald_status ewald_sys_tables(const ewald_sys *sys, int32_t *n, double *weight, 
  * [n][3]; `cand` may be NULL to query the count. */
 ewald_status ewald_sys_candidates(const ewald_sys *sys, int *n_cand, double *cand);
 
+/* The minimum-image geometry the fused kernel uses for this cell.  If the
+ * lattice contains mutually orthogonal vectors spanning a sublattice of index
+ * m <= 4 whose cosets are offset by half box sides (simple-cubic, bcc, fcc and
+ * hexagonal cells), *index = m and box[0..dim) receives their lengths
+ * (bohr): pair distances are then reduced per axis in that box with one
+ * extra image check per coset.  Otherwise *index = 0 and the general
+ * reduction (fractional rint plus the candidate offsets above) is used.
+ * Either pointer may be NULL; box must hold 3 doubles.  Status: E_ARG. */
+ewald_status ewald_sys_geometry(const ewald_sys *sys, int *index, double *box);
+
 void ewald_sys_destroy(ewald_sys *sys);
 
 /* A batch of n_walkers walkers; walker w belongs to sys[walker_sys[w]]
@@ -201,6 +211,41 @@ ewald_status ewald_accept_batch(ewald_batch *b, void *state, const uint8_t *acce
 ewald_status ewald_run_moves_batch(ewald_batch *b, void *state, int n_steps, const int32_t *k,
                                    const double *new_pos, const uint8_t *accept, double *delta,
                                    double *djastrow, void *stream);
+
+/* Launch shape of ewald_run_moves_batch (the batching of Sec. 5.1, where the
+ * paper hand-tunes gang and vector sizes).  One workgroup serves one walker;
+ *   threads        workgroup size, which fixes segments of 4 G per thread and
+ *                  particles per thread: 0 = default for the largest segment
+ *                  count s of the batch (s <= 512: 256; s <= 1024: 1024 or
+ *                  512; s <= 2048: 512); other values give E_ARG
+ *   chunk          at most this many moves staged per chunk, 1..64 (fewer
+ *                  when LDS does not hold them), or 0 = as many as LDS allows
+ *                  without lowering the workgroups per CU
+ *   general_frame  1 = the general minimum-image reduction even when the
+ *                  cell has an orthogonal-sublattice frame (ewald_sys_geometry);
+ *                  applies to ewald_energy_batch as well
+ * Results do not depend on the choice beyond rounding order.  Not to be
+ * called concurrently with launches on the same batch. */
+ewald_status ewald_batch_set_tuning(ewald_batch *b, int threads, int chunk, int general_frame);
+
+/* The launch shape ewald_run_moves_batch will use: workgroup size, moves per
+ * chunk, frame (1 = general), and fused = 0 when the walkers do not fit the
+ * fused kernel's LDS layout (then it runs the per-step kernels in turn).
+ * Any output pointer may be NULL. */
+ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, int *general_frame,
+                                    int *fused);
+
+/* Time every launch shape of ewald_run_moves_batch on this batch and keep
+ * the fastest (ewald_batch_set_tuning).  The probe runs n_moves (1..4096)
+ * proposals per walker, all rejected, on `state`, which must be ready (after
+ * ewald_energy_batch, no pending move) and is left unchanged.  With a
+ * cache_path, a tuning stored there for the same device architecture and
+ * batch shape is applied without timing, and a new one is appended (one text
+ * line per shape).  Allocates temporary device buffers and synchronises
+ * `stream`: a set-up call, not for graph capture.  Status: E_ARG, E_STATE,
+ * E_HIP. */
+ewald_status ewald_autotune(ewald_batch *b, void *state, int n_moves, const char *cache_path,
+                            void *stream);
 
 /* Thread-local message for the last non-OK status of this thread. */
 const char *ewald_last_error(void);

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <type_traits>
 
 #include "ewald_internal.h"
@@ -63,8 +64,9 @@ __device__ __forceinline__ void to_frac(const double* r, const double* Ainv, dou
 // exp(2 pi i x) in turns: reduce x to the nearest quarter turn q and a
 // remainder of at most half a quarter turn (exact in FP64), evaluate the
 // Taylor series of cos and sin at theta = remainder * pi/2 (|theta| <= pi/4;
-// the first omitted terms are below 1e-19 in FP64 and 1e-11 in FP32), and
-// rotate by i^q.  Small and register-light, unlike a general sincos.
+// the first omitted terms are below 1e-19), and rotate by i^q.  Small and
+// register-light, unlike a general sincos.  Both precision forms build their
+// phase tables from it in FP64 (the mixed form rounds the entries to FP32).
 __device__ __forceinline__ void quarter_turns(double x, double& r, int& q) {
   x -= rint(x);
   const double y = 4.0 * x;
@@ -79,7 +81,7 @@ __device__ __forceinline__ cplx<R> rotate_quarter(R c, R s, int q) {
   return (q & 2) ? cplx<R>{-x, -y} : cplx<R>{x, y};
 }
 
-__device__ __forceinline__ cplx<double> turn(double x, double) {
+__device__ __forceinline__ cplx<double> turn(double x) {
   double r;
   int q;
   quarter_turns(x, r, q);
@@ -104,33 +106,6 @@ __device__ __forceinline__ cplx<double> turn(double x, double) {
   cp = fma(cp, t2, -0.5);
   cp = fma(cp, t2, 1.0);
   return rotate_quarter<double>(cp, sp, q);
-}
-
-__device__ __forceinline__ cplx<float> turn(double x, float) {
-  double r;
-  int q;
-  quarter_turns(x, r, q);
-  const float th = float(r * 1.5707963267948966), t2 = th * th;
-  float sp = -2.5052108e-08f;
-  sp = fmaf(sp, t2, 2.7557319e-06f);
-  sp = fmaf(sp, t2, -1.9841270e-04f);
-  sp = fmaf(sp, t2, 8.3333333e-03f);
-  sp = fmaf(sp, t2, -1.6666667e-01f);
-  sp = fmaf(sp, t2 * th, th);
-  float cp = 2.0876757e-09f;
-  cp = fmaf(cp, t2, -2.7557319e-07f);
-  cp = fmaf(cp, t2, 2.4801587e-05f);
-  cp = fmaf(cp, t2, -1.3888889e-03f);
-  cp = fmaf(cp, t2, 4.1666667e-02f);
-  cp = fmaf(cp, t2, -0.5f);
-  cp = fmaf(cp, t2, 1.0f);
-  return rotate_quarter<float>(cp, sp, q);
-}
-
-// exp(2 pi i n s) for a fractional coordinate s.
-template <typename R>
-__device__ __forceinline__ cplx<R> phase(double s, int n, R) {
-  return turn(double(n) * s, R(0));
 }
 
 // Squared minimum-image distance between fractional positions a and b:
@@ -168,6 +143,62 @@ __device__ __forceinline__ double min_r2(const double* a, const double* b, const
     r2 = fmin(r2, fma(-2.0, fabs(dot), r0sq + S->cand[c][3]));
   }
   return r2;
+}
+
+// Squared minimum-image distance in the orthogonal-sublattice frame: wrap
+// each axis into the box (|x_d| <= box_d / 2), then for each coset offset by
+// half box sides along the axes in its mask the nearest image is at
+// sum_mask (box_d/2 - |x_d|)^2 + sum_other x_d^2 = |x|^2 + cc - sum_mask box_d |x_d|.
+template <int DIM>
+__device__ __forceinline__ double min_r2_ortho(const double* a, const double* b, const DevSys* __restrict__ S) {
+  double x[DIM], r0sq = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    x[d] = a[d] - b[d];
+    x[d] = fma(-S->box[d], rint(x[d] * S->ibox[d]), x[d]);
+    r0sq = fma(x[d], x[d], r0sq);
+  }
+  double r2 = r0sq;
+  const int nc = S->n_coset;
+  for (int c = 0; c < nc; ++c) {
+    double t = r0sq + S->cc[c];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) t = fma(-S->cw[c][d], fabs(x[d]), t);
+    r2 = fmin(r2, t);
+  }
+  return r2;
+}
+
+// Coordinates of a fractional position in the orthogonal-sublattice frame.
+template <int DIM>
+__device__ __forceinline__ void frame_coords(const double* s, const DevSys* __restrict__ S, double* x) {
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) v = fma(s[i], S->F[i * 3 + d], v);
+    x[d] = v;
+  }
+}
+
+// Minimum-image r^2 between two positions given in the kernel's geometry:
+// frame coordinates (ORTHO) or fractional coordinates (general cells).
+template <int DIM, bool ORTHO>
+__device__ __forceinline__ double image_r2(const double* a, const double* b, const DevSys* __restrict__ S,
+                                           int n_cand) {
+  if (ORTHO) return min_r2_ortho<DIM>(a, b, S);
+  return min_r2<DIM>(a, b, S, n_cand);
+}
+
+// A stored (fractional) position in the kernel's geometry.
+template <int DIM, bool ORTHO>
+__device__ __forceinline__ void geo_pos(const double* s, const DevSys* __restrict__ S, double* x) {
+  if (ORTHO) {
+    frame_coords<DIM>(s, S, x);
+  } else {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) x[d] = s[d];
+  }
 }
 
 // Kahan-compensated FP32 accumulator.
@@ -324,11 +355,12 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
 }
 
 // Real-space part of a move inside the fused sweep.  Thread t owns the
-// particles j = t + c NT (c < PPR) and keeps their positions and charges in
-// registers (ps, pq); it alone updates them when they move.  Particles beyond
+// particles j = t + c NT (c < PPR) and keeps their positions (in the
+// kernel's geometry: frame or fractional coordinates, as sn and so) and
+// charges in registers (ps, pq); it alone updates them when they move.  Particles beyond
 // PPR NT (larger systems than the launch shape covers) are read from the LDS
 // copy, again only by their owner t = j mod NT.
-template <int DIM, bool MIXED, int PD, int NT, int PPR>
+template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO>
 __device__ __forceinline__ double real_move_own(const double* sn, const double* so, int k,
                                                 const double (&ps)[PPR][DIM], const double (&pq)[PPR],
                                                 const double* lpos, const double* lq, int n,
@@ -342,8 +374,8 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
     for (int c = 0; c < PPR; ++c) {
       const int j = threadIdx.x + c * NT;
       const bool ok = j < n && j != k;
-      r2[2 * c] = ok ? min_r2<DIM>(sn, ps[c], S, n_cand) : rc2;
-      r2[2 * c + 1] = ok ? min_r2<DIM>(so, ps[c], S, n_cand) : rc2;
+      r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, ps[c], S, n_cand) : rc2;
+      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, ps[c], S, n_cand) : rc2;
       qq[2 * c] = pq[c];
       qq[2 * c + 1] = -pq[c];
     }
@@ -352,8 +384,10 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
   for (int j = threadIdx.x + PPR * NT; j < n; j += NT) {
     double qq[2], r2[2];
     const bool ok = j != k;
-    r2[0] = ok ? min_r2<DIM>(sn, lpos + j * DIM, S, n_cand) : rc2;
-    r2[1] = ok ? min_r2<DIM>(so, lpos + j * DIM, S, n_cand) : rc2;
+    double xj[DIM];
+    geo_pos<DIM, ORTHO>(lpos + j * DIM, S, xj);
+    r2[0] = ok ? image_r2<DIM, ORTHO>(sn, xj, S, n_cand) : rc2;
+    r2[1] = ok ? image_r2<DIM, ORTHO>(so, xj, S, n_cand) : rc2;
     qq[0] = lq[j];
     qq[1] = -lq[j];
     pr.template add<2>(qq, r2, S);
@@ -367,11 +401,10 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
       const bool ok = j < nfix;
       const int jj = ok ? j : nfix - 1;
       double sj[DIM];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) sj[d] = S->fixed_s[jj * DIM + d];
+      geo_pos<DIM, ORTHO>(S->fixed_s + jj * DIM, S, sj);
       const double qj = ok ? S->fixed_q[jj] : 0.0;
-      r2[2 * c] = ok ? min_r2<DIM>(sn, sj, S, n_cand) : rc2;
-      r2[2 * c + 1] = ok ? min_r2<DIM>(so, sj, S, n_cand) : rc2;
+      r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, sj, S, n_cand) : rc2;
+      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, sj, S, n_cand) : rc2;
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
     }
@@ -441,18 +474,20 @@ __device__ __forceinline__ double wave_sum_to_lane63(double v) {
   return v;
 }
 
-// Per-dimension phase tables of one position, n in [-nm, nm]:
-// tab[d * (2 nm + 1) + nm + n] = exp(2 pi i n s_d).  Entries are written by
-// threads [t0, t0 + DIM (nm + 1)) of the calling group.
-template <int DIM, typename R>
-__device__ __forceinline__ void fill_tables(cplx<R>* tab, const double* s, int nm, int e) {
-  const int per = nm + 1;
-  if (e >= 0 && e < DIM * per) {
-    const int d = e / per, m = e - d * per;
-    cplx<R> c = phase(s[d], m, R(0));
-    const int tbl = 2 * nm + 1;
-    tab[d * tbl + nm + m] = c;
-    tab[d * tbl + nm - m] = {c.x, -c.y};
+// One row of a phase table, tab_d[nm + m] = exp(2 pi i m s) and its conjugate
+// at nm - m for m = 0..nm, by one thread: powers of exp(2 pi i s) formed by
+// repeated FP64 multiplication (the paper's buffered powers, Sec. 5.2), with an
+// exact restart every 8 powers so the rounding error stays below ~8 ulp;
+// stored in R.
+template <typename R>
+__device__ __forceinline__ void fill_row(cplx<R>* row, double s, int nm) {
+  const cplx<double> u = turn(s);
+  cplx<double> c = {1.0, 0.0};
+  row[nm] = {R(1), R(0)};
+  for (int m = 1; m <= nm; ++m) {
+    c = (m & 7) == 0 ? turn(double(m) * s) : cmul(c, u);
+    row[nm + m] = {R(c.x), R(c.y)};
+    row[nm - m] = {R(c.x), R(-c.y)};
   }
 }
 
@@ -489,27 +524,28 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
   }
   for (int p0 = 0; p0 < n; p0 += tile) {
     const int np = min(tile, n - p0);
-    for (int e = threadIdx.x; e < np * DIM * (nm + 1); e += NT) {
-      const int p = e / (DIM * (nm + 1));
-      double sp[DIM];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) sp[d] = pos[(p0 + p) * DIM + d];
-      fill_tables<DIM, double>(tabs + p * DIM * tbl, sp, nm, e - p * DIM * (nm + 1));
-    }
+    for (int e = threadIdx.x; e < np * DIM; e += NT)  // row e: particle e / DIM, dimension e % DIM
+      fill_row<double>(tabs + e * tbl, pos[p0 * DIM + e], nm);
     __syncthreads();
-    for (int p = 0; p < np; ++p) {
-      const cplx<double>* tp = tabs + p * DIM * tbl;
-      const double qp = q[p0 + p];
-      const cplx<double> u = tp[(DIM - 1) * tbl + nm + 1];
+    // two particles per pass: independent chains for latency hiding (an odd
+    // tile's last pass pairs the particle with itself at zero charge)
+    for (int p = 0; p < np; p += 2) {
+      const bool two = p + 1 < np;
+      const cplx<double>* t0 = tabs + p * DIM * tbl;
+      const cplx<double>* t1 = two ? t0 + DIM * tbl : t0;
+      const double q0 = q[p0 + p], q1 = two ? q[p0 + p + 1] : 0.0;
+      const cplx<double> u0 = t0[(DIM - 1) * tbl + nm + 1], u1 = t1[(DIM - 1) * tbl + nm + 1];
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
         if (seg0 + i * NT < nseg) {
-          cplx<double> e = anchor<DIM, double>(tp, an[i], nm);
+          cplx<double> e0 = anchor<DIM, double>(t0, an[i], nm);
+          cplx<double> e1 = anchor<DIM, double>(t1, an[i], nm);
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
-            acc[i][j].x = fma(qp, e.x, acc[i][j].x);
-            acc[i][j].y = fma(qp, e.y, acc[i][j].y);
-            e = cmul(e, u);
+            acc[i][j].x = fma(q1, e1.x, fma(q0, e0.x, acc[i][j].x));
+            acc[i][j].y = fma(q1, e1.y, fma(q0, e0.y, acc[i][j].y));
+            e0 = cmul(e0, u0);
+            e1 = cmul(e1, u1);
           }
         }
       }
@@ -521,11 +557,13 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
 // ---------------------------------------------------------------------------
 // Energy: wrap positions, rho in FP64, reciprocal and Jastrow sums, real-space
 // pairs, constants.  SPT = segments per thread held in registers.  Both
-// precision forms sum the pair terms in FP64: the energy adds ~N^2/4 terms of
-// one sign (like charges), so any FP32 rounding bias of the pair function
+// precision forms compute the energy alike, in FP64: it adds ~N^2/4 pair terms
+// of one sign (like charges), so any FP32 rounding bias of the pair function
 // would add up coherently, while in a move delta it cancels between the old
-// and new terms.
-template <int DIM, bool MIXED, int SPT, int PD>
+// and new terms.  The pair loop works in the orthogonal-sublattice frame when
+// the cell has one (ORTHO); rho is built from the fractional positions just
+// stored in the walker state.
+template <int DIM, int SPT, int PD, bool ORTHO>
 __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ systems,
                                                   const DevWalker* __restrict__ walkers,
                                                   const double* __restrict__ pos, char* __restrict__ state,
@@ -540,20 +578,21 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
   double* spos = reinterpret_cast<double*>(st + HDR_BYTES);
   double* rho = reinterpret_cast<double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
-  double* lpos = smem;                       // [n][DIM]
+  double* lpos = smem;                       // [n][DIM] in the pair loop's geometry
   double* lq = smem + lds_pos * DIM;         // [n]
   double* red = lq + lds_pos;                // [4 * 4]
   cplx<double>* tabs = reinterpret_cast<cplx<double>*>(red + 16);
 
   const double* pw = pos + size_t(W.pos_off) * DIM;
   for (int i = tid; i < n; i += BLOCK) {
-    double r[DIM], s[DIM];
+    double r[DIM], s[DIM], x[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) r[d] = pw[i * DIM + d];
     to_frac<DIM>(r, S->Ainv, s);
+    geo_pos<DIM, ORTHO>(s, S, x);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      lpos[i * DIM + d] = s[d];
+      lpos[i * DIM + d] = x[d];
       spos[i * DIM + d] = s[d];
     }
     lq[i] = S->mobile_q[i];
@@ -576,7 +615,7 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
     an[i] = s < nseg ? S->seg_n[s] : 0u;
   }
   cplx<double> acc[SPT][SEG];
-  rebuild_rho<DIM, SPT>(acc, an, tid, S, lpos, lq, n, tabs);
+  rebuild_rho<DIM, SPT>(acc, an, tid, S, spos, lq, n, tabs);
   double er = 0.0, ej = 0.0;
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
@@ -595,11 +634,9 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
   }
 
   // real space: each unordered mobile pair once (pair i with i+1..i+(n-1)/2
-  // cyclically, plus i+n/2 for i < n/2 when n is even), then mobile-ion pairs
+  // cyclically, plus i+n/2 for i < n/2 when n is even), then every fixed ion
   PairAcc<false, PD> pr;
   const double rc2 = S->rc2;
-  // partners of particle i: i+1 .. i+half cyclically, i + n/2 when n is even
-  // and i < n/2 (each unordered mobile pair once), then every fixed ion
   const int half = (n - 1) / 2;
   for (int i = tid; i < n; i += BLOCK) {
     double si[DIM];
@@ -616,12 +653,15 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
         const bool mob = m < n_mob, fix = !mob && m < n_part;
         int j = i + m + 1;
         if (j >= n) j -= n;
-        const double* src = mob ? lpos + j * DIM : S->fixed_s + (fix ? m - n_mob : 0) * DIM;
         double sj[DIM];
+        if (mob) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) sj[d] = (mob || fix) ? src[d] : 0.0;
+          for (int d = 0; d < DIM; ++d) sj[d] = lpos[j * DIM + d];
+        } else {
+          geo_pos<DIM, ORTHO>(S->fixed_s + (fix ? m - n_mob : 0) * DIM, S, sj);
+        }
         qq[c] = mob ? qi * lq[j] : fix ? qi * S->fixed_q[m - n_mob] : 0.0;
-        r2[c] = (mob || fix) ? min_r2<DIM>(si, sj, S, n_cand) : rc2;
+        r2[c] = (mob || fix) ? image_r2<DIM, ORTHO>(si, sj, S, n_cand) : rc2;
       }
       pr.template add<4>(qq, r2, S);
     }
@@ -691,10 +731,7 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
     for (int d = 0; d < DIM; ++d) so[d] = spos[k * DIM + d];
   }
   const double qk = S->mobile_q[k];
-  for (int e = tid; e < 2 * DIM * (nm + 1); e += BLOCK) {
-    if (e < DIM * (nm + 1)) fill_tables<DIM, R>(to, so, nm, e);
-    else fill_tables<DIM, R>(tn, sn, nm, e - DIM * (nm + 1));
-  }
+  if (tid < 2 * DIM) fill_row<R>(to + tid * tbl, tid < DIM ? so[tid] : sn[tid - DIM], nm);  // to, then tn
   __syncthreads();
 
   // reciprocal space: t(G) = 2 q Re(conj(rho) d) + q^2 |d|^2, d = e_new - e_old
@@ -796,10 +833,7 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
       so[d] = spos[pk * DIM + d];
       sn[d] = hdr->pending_s[d];
     }
-    for (int e = tid; e < 2 * DIM * (nm + 1); e += BLOCK) {
-      if (e < DIM * (nm + 1)) fill_tables<DIM, R>(to, so, nm, e);
-      else fill_tables<DIM, R>(tn, sn, nm, e - DIM * (nm + 1));
-    }
+    if (tid < 2 * DIM) fill_row<R>(to + tid * tbl, tid < DIM ? so[tid] : sn[tid - DIM], nm);  // to, then tn
   }
   __syncthreads();  // every thread has read the header and pending position
   if (acc) {
@@ -900,12 +934,12 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
 // FP64 rebuild of the mixed form runs between chunks.
 struct RunLds {
   // byte offsets into dynamic LDS; positions start at 0
-  uint32_t q, red, wtab, ctab, sn, so, part, k, acc, cnt;
+  uint32_t q, red, wtab, ctab, sn, so, xn, xo, part, k, acc, cnt;
   int ch;     // moves per chunk
   int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
 };
 
-template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
+template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD, bool ORTHO>
 __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
@@ -922,7 +956,6 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
   const int K = S->refresh_every, tbl = 2 * nm + 1;
-  const int per = DIM * (nm + 1);    // table entries computed per position (n >= 0)
   const int mstride = 2 * DIM * tbl;  // one move's tables (old, new), in entries
   const int CH = L.ch;
   char* st = state + W.state_off;
@@ -937,6 +970,8 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   cplx<double>* tabs = reinterpret_cast<cplx<double>*>(lds + L.ctab);  // rebuild tiles, between chunks
   double* st_sn = reinterpret_cast<double*>(lds + L.sn);
   double* st_so = reinterpret_cast<double*>(lds + L.so);
+  double* st_xn = reinterpret_cast<double*>(lds + L.xn);  // sn, so in the real-space geometry (ORTHO)
+  double* st_xo = reinterpret_cast<double*>(lds + L.xo);
   double* st_part = reinterpret_cast<double*>(lds + L.part);  // [CH][NW][4 rows][2]
   int* st_k = reinterpret_cast<int*>(lds + L.k);
   int* st_acc = reinterpret_cast<int*>(lds + L.acc);
@@ -955,8 +990,10 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
 #pragma unroll
   for (int c = 0; c < PPR; ++c) {
     const int j = tid + c * NT;
+    double sj[DIM];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) ps[c][d] = j < n ? spos[j * DIM + d] : 0.0;
+    for (int d = 0; d < DIM; ++d) sj[d] = j < n ? spos[j * DIM + d] : 0.0;
+    geo_pos<DIM, ORTHO>(sj, S, ps[c]);
     pq[c] = j < n ? S->mobile_q[j] : 0.0;
   }
   uint32_t an[SPT];
@@ -1006,8 +1043,16 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
         c += a ? 1 : 0;
       }
       if (k >= 0) {
+        double so[DIM];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) st_so[tid * DIM + d] = prev >= 0 ? st_sn[prev * DIM + d] : lpos[k * DIM + d];
+        for (int d = 0; d < DIM; ++d) {
+          so[d] = prev >= 0 ? st_sn[prev * DIM + d] : lpos[k * DIM + d];
+          st_so[tid * DIM + d] = so[d];
+        }
+        if (ORTHO) {
+          frame_coords<DIM>(so, S, st_xo + tid * DIM);
+          frame_coords<DIM>(st_sn + tid * DIM, S, st_xn + tid * DIM);
+        }
       }
       st_cnt[tid] = c + ((k >= 0 && st_acc[tid] != 0) ? 1 : 0);  // accepts since the rebuild, after this move
     }
@@ -1020,13 +1065,12 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           break;
         }
     // ---- phase tables of every move of the chunk (old, then new position) ----
-    for (int e = tid; e < len * 2 * per; e += NT) {
-      const int q = e / (2 * per), r = e - q * (2 * per);
-      if (st_k[q] >= 0) {
-        const bool nw = r >= per;
-        fill_tables<DIM, R>(ctab + q * mstride + (nw ? DIM * tbl : 0), (nw ? st_sn : st_so) + q * DIM, nm,
-                            nw ? r - per : r);
-      }
+    // row e: move e / (2 DIM), old (0) or new (1) position, dimension; the
+    // tables of a move are [old: DIM rows][new: DIM rows]
+    for (int e = tid; e < len * 2 * DIM; e += NT) {
+      const int q = e / (2 * DIM), r = e - q * (2 * DIM);
+      if (st_k[q] >= 0)
+        fill_row<R>(ctab + e * tbl, r < DIM ? st_so[q * DIM + r] : st_sn[q * DIM + r - DIM], nm);
     }
     __syncthreads();
 
@@ -1037,11 +1081,12 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
       if (k >= 0) {  // uniform
         const bool acc = st_acc[mm] != 0;
         const double qk = lq[k];
-        double sn[DIM], so[DIM];
+        double sn[DIM], xn[DIM], xo[DIM];  // new (fractional), new and old in the real-space geometry
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
           sn[d] = st_sn[mm * DIM + d];
-          so[d] = st_so[mm * DIM + d];
+          xn[d] = ORTHO ? st_xn[mm * DIM + d] : sn[d];
+          xo[d] = ORTHO ? st_xo[mm * DIM + d] : st_so[mm * DIM + d];
         }
         if (qk != 0.0) {  // uniform; a neutral particle's move changes nothing
           const cplx<R>* to = ctab + mm * mstride;
@@ -1082,7 +1127,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
           if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR>(sn, so, k, ps, pq, lpos, lq, n, S);
+          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO>(xn, xo, k, ps, pq, lpos, lq, n, S);
         }
         if (acc) {
           if ((k % NT) == tid) {  // the owner moves its particle
@@ -1092,7 +1137,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
             for (int c = 0; c < PPR; ++c)
               if (k == tid + c * NT)
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) ps[c][d] = sn[d];
+                for (int d = 0; d < DIM; ++d) ps[c][d] = xn[d];
           }
           n_acc += 1;
         }
@@ -1211,34 +1256,39 @@ int allow_lds(F* kernel, size_t bytes) {
 
 int even(int x) { return (x + 1) & ~1; }
 
-template <int DIM, bool MIXED, int SPT, int PD>
+template <int DIM, int SPT, int PD, bool ORTHO>
 int energy_inst(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
                 void* stream) {
   const int lds_pos = even(b.max_particles);
   const size_t tab = size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>);
   const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + 16 * 8 + tab;
-  if (int rc = allow_lds(k_energy<DIM, MIXED, SPT, PD>, lds)) return rc;
-  hipLaunchKernelGGL((k_energy<DIM, MIXED, SPT, PD>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
-                     b.d_sys, b.d_walk, pos, state, energy, jastrow, lds_pos);
+  auto* kern = k_energy<DIM, SPT, PD, ORTHO>;
+  if (int rc = allow_lds(kern, lds)) return rc;
+  hipLaunchKernelGGL(kern, dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), b.d_sys, b.d_walk, pos, state,
+                     energy, jastrow, lds_pos);
   return last_launch();
 }
 
-template <int DIM, bool MIXED, int PD>
+template <int DIM, int PD, bool ORTHO>
 int energy_pd(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
               void* stream) {
   switch (spt_for(b.max_n_seg)) {
-    case 1: return energy_inst<DIM, MIXED, 1, PD>(b, pos, state, energy, jastrow, stream);
-    case 2: return energy_inst<DIM, MIXED, 2, PD>(b, pos, state, energy, jastrow, stream);
-    case 4: return energy_inst<DIM, MIXED, 4, PD>(b, pos, state, energy, jastrow, stream);
-    default: return energy_inst<DIM, MIXED, 8, PD>(b, pos, state, energy, jastrow, stream);
+    case 1: return energy_inst<DIM, 1, PD, ORTHO>(b, pos, state, energy, jastrow, stream);
+    case 2: return energy_inst<DIM, 2, PD, ORTHO>(b, pos, state, energy, jastrow, stream);
+    case 4: return energy_inst<DIM, 4, PD, ORTHO>(b, pos, state, energy, jastrow, stream);
+    default: return energy_inst<DIM, 8, PD, ORTHO>(b, pos, state, energy, jastrow, stream);
   }
 }
 
-template <int DIM, bool MIXED>
+template <int DIM>
 int energy_dim(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
                void* stream) {
-  return b.poly_deg <= 16 ? energy_pd<DIM, MIXED, 16>(b, pos, state, energy, jastrow, stream)
-                          : energy_pd<DIM, MIXED, 32>(b, pos, state, energy, jastrow, stream);
+  const bool o = b.all_ortho && !b.general_frame;
+  if (b.poly_deg <= 16)
+    return o ? energy_pd<DIM, 16, true>(b, pos, state, energy, jastrow, stream)
+             : energy_pd<DIM, 16, false>(b, pos, state, energy, jastrow, stream);
+  return o ? energy_pd<DIM, 32, true>(b, pos, state, energy, jastrow, stream)
+           : energy_pd<DIM, 32, false>(b, pos, state, energy, jastrow, stream);
 }
 
 template <int DIM, bool MIXED>
@@ -1299,6 +1349,10 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   o = up16(o + size_t(ch) * DIM * 8);
   L.so = uint32_t(o);
   o = up16(o + size_t(ch) * DIM * 8);
+  L.xn = uint32_t(o);
+  o = up16(o + size_t(ch) * DIM * 8);
+  L.xo = uint32_t(o);
+  o = up16(o + size_t(ch) * DIM * 8);
   L.part = uint32_t(o);
   o = up16(o + size_t(ch) * NW * 8 * 8);
   L.k = uint32_t(o);
@@ -1312,54 +1366,114 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   return o;
 }
 
-template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD>
-int run_inst(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
-             const uint8_t* accept, double* delta, double* djas, void* stream) {
+// Workgroups of this kernel that fit on one CU by registers (4 SIMDs, 512
+// VGPRs per lane each); the fused kernel sizes its LDS so as not to lower it.
+template <typename F>
+int blocks_per_cu(F* kernel, int nt) {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)) != hipSuccess || a.numRegs <= 0) return 1;
+  const int vgpr = (a.numRegs + 7) & ~7;
+  const int waves_per_simd = std::min(8, 512 / vgpr);
+  return std::max(1, 4 * waves_per_simd / (nt / 64));
+}
+
+struct RunArgs {
+  char* state;
+  int n_steps;
+  const int32_t* k;
+  const double* new_pos;
+  const uint8_t* accept;
+  double* delta;
+  double* djas;
+  void* stream;
+  RunPlan* plan;  // non-null: resolve the launch shape only, launch nothing
+};
+
+template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD, bool ORTHO>
+int run_inst(const LaunchBatch& b, const RunArgs& a) {
+  auto* kern = k_run<DIM, MIXED, NT, SPT, JAS, PD, ORTHO>;
+  static const int per_cu = blocks_per_cu(kern, NT);
+  const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
   RunLds L{};
-  int ch = RUN_CHUNK;
+  int ch = b.run_chunk > 0 ? std::min(b.run_chunk, RUN_CHUNK) : RUN_CHUNK;
   size_t lds = run_layout<DIM, MIXED, NT>(b, ch, L);
+  if (b.run_chunk <= 0)
+    while (lds > budget && ch > 8) lds = run_layout<DIM, MIXED, NT>(b, --ch, L);
   while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT>(b, --ch, L);
   if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
-  if (int rc = allow_lds(k_run<DIM, MIXED, NT, SPT, JAS, PD>, lds)) return rc;
-  hipLaunchKernelGGL((k_run<DIM, MIXED, NT, SPT, JAS, PD>), dim3(b.n_walkers), dim3(NT), lds, as_stream(stream),
-                     b.d_sys, b.d_walk, state, n_steps, b.n_walkers, k, new_pos, accept, delta, djas, L);
+  if (a.plan) {
+    *a.plan = RunPlan{1, NT, SPT, ch, ORTHO ? 0 : 1, int(lds), per_cu};
+    return 0;
+  }
+  if (int rc = allow_lds(kern, lds)) return rc;
+  hipLaunchKernelGGL(kern, dim3(b.n_walkers), dim3(NT), lds, as_stream(a.stream), b.d_sys, b.d_walk, a.state,
+                     a.n_steps, b.n_walkers, a.k, a.new_pos, a.accept, a.delta, a.djas, L);
   return last_launch();
 }
 
-template <int DIM, bool MIXED, bool JAS, int PD>
-int run_jp(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
-           const uint8_t* accept, double* delta, double* djas, void* stream) {
-  // threads per walker and segments per thread from the largest G set
+// Workgroup shapes of the fused kernel (threads NT, segments per thread SPT)
+// by the largest segment count of the batch; `threads` picks among the
+// shapes available for that count (0: the default, the first listed).
+//   <= 256 segments: (256, 1)      <= 512: (256, 2)
+//   <= 1024: (1024, 1) or (512, 2)  <= 2048: (512, 4)
+int run_shape(int max_n_seg, int threads, int* nt, int* spt) {
+  struct Shape { int lim, nt, spt; };
+  static const Shape shapes[] = {{256, 256, 1}, {512, 256, 2}, {1024, 1024, 1}, {1024, 512, 2}, {2048, 512, 4}};
+  int lim = 0;
+  for (const Shape& sh : shapes) {
+    if (max_n_seg > sh.lim) continue;
+    if (lim == 0) lim = sh.lim;
+    if (sh.lim != lim) break;
+    if (threads == 0 || threads == sh.nt) {
+      *nt = sh.nt;
+      *spt = sh.spt;
+      return 1;
+    }
+  }
+  return 0;
+}
+
+template <int DIM, bool MIXED, bool JAS, int PD, bool ORTHO>
+int run_jp(const LaunchBatch& b, const RunArgs& a) {
   static_assert(RUN_CHUNK <= 256, "staging uses one thread per move");
-  if (b.max_n_seg <= 256)
-    return run_inst<DIM, MIXED, 256, 1, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-  if (b.max_n_seg <= 512)
-    return run_inst<DIM, MIXED, 256, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-  if (b.max_n_seg <= 1024)
-    return b.run_threads == 1024
-               ? run_inst<DIM, MIXED, 1024, 1, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-               : run_inst<DIM, MIXED, 512, 2, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-  return run_inst<DIM, MIXED, 512, 4, JAS, PD>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+  int nt = 0, spt = 0;
+  if (!run_shape(b.max_n_seg, b.run_threads, &nt, &spt)) return RUN_NO_FIT;
+#define EW_RUN(NT, SPT) \
+  if (nt == NT && spt == SPT) return run_inst<DIM, MIXED, NT, SPT, JAS, PD, ORTHO>(b, a)
+  EW_RUN(256, 1);
+  EW_RUN(256, 2);
+  EW_RUN(1024, 1);
+  EW_RUN(512, 2);
+  EW_RUN(512, 4);
+#undef EW_RUN
+  return RUN_NO_FIT;
+}
+
+template <int DIM, bool MIXED, bool JAS, int PD>
+int run_jpo(const LaunchBatch& b, const RunArgs& a) {
+  return b.all_ortho && !b.general_frame ? run_jp<DIM, MIXED, JAS, PD, true>(b, a)
+                                         : run_jp<DIM, MIXED, JAS, PD, false>(b, a);
 }
 
 template <int DIM, bool MIXED>
-int run_dim(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
-            const uint8_t* accept, double* delta, double* djas, void* stream) {
+int run_dim(const LaunchBatch& b, const RunArgs& a) {
   const bool jas = b.has_jastrow != 0, p16 = b.poly_deg <= 16;
-  if (jas) return p16 ? run_jp<DIM, MIXED, true, 16>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-                      : run_jp<DIM, MIXED, true, 32>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-  return p16 ? run_jp<DIM, MIXED, false, 16>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-             : run_jp<DIM, MIXED, false, 32>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
+  if (jas) return p16 ? run_jpo<DIM, MIXED, true, 16>(b, a) : run_jpo<DIM, MIXED, true, 32>(b, a);
+  return p16 ? run_jpo<DIM, MIXED, false, 16>(b, a) : run_jpo<DIM, MIXED, false, 32>(b, a);
+}
+
+int run_any(const LaunchBatch& b, const RunArgs& a) {
+  if (!b.all_wtab_lds) return RUN_NO_FIT;
+  if (b.dim == 3) return b.mixed ? run_dim<3, true>(b, a) : run_dim<3, false>(b, a);
+  return b.mixed ? run_dim<2, true>(b, a) : run_dim<2, false>(b, a);
 }
 
 }  // namespace
 
 int launch_energy(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
                   void* stream) {
-  if (b.dim == 3) return b.mixed ? energy_dim<3, true>(b, pos, state, energy, jastrow, stream)
-                                 : energy_dim<3, false>(b, pos, state, energy, jastrow, stream);
-  return b.mixed ? energy_dim<2, true>(b, pos, state, energy, jastrow, stream)
-                 : energy_dim<2, false>(b, pos, state, energy, jastrow, stream);
+  return b.dim == 3 ? energy_dim<3>(b, pos, state, energy, jastrow, stream)
+                   : energy_dim<2>(b, pos, state, energy, jastrow, stream);
 }
 
 int launch_delta(const LaunchBatch& b, char* state, const int32_t* k, const double* new_pos, double* delta,
@@ -1377,13 +1491,7 @@ int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void
 
 int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
                const uint8_t* accept, double* delta, double* djas, void* stream) {
-  int rc = RUN_NO_FIT;
-  if (b.all_wtab_lds) {
-    if (b.dim == 3) rc = b.mixed ? run_dim<3, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-                                 : run_dim<3, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-    else rc = b.mixed ? run_dim<2, true>(b, state, n_steps, k, new_pos, accept, delta, djas, stream)
-                      : run_dim<2, false>(b, state, n_steps, k, new_pos, accept, delta, djas, stream);
-  }
+  int rc = run_any(b, RunArgs{state, n_steps, k, new_pos, accept, delta, djas, stream, nullptr});
   if (rc != RUN_NO_FIT) return rc;
   // a shell table or walker too large for LDS: the same sequence through the per-step kernels
   const size_t W = size_t(b.n_walkers);
@@ -1394,6 +1502,57 @@ int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k,
     if (rc) return rc;
   }
   return 0;
+}
+
+void plan_run(const LaunchBatch& b, RunPlan* plan) {
+  *plan = RunPlan{};
+  if (run_any(b, RunArgs{nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, plan}) != 0) *plan = RunPlan{};
+}
+
+bool run_threads_valid(int max_n_seg, int threads) {
+  int nt, spt;
+  return threads == 0 || run_shape(max_n_seg, threads, &nt, &spt);
+}
+
+int time_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
+             const uint8_t* accept, double* delta, void* stream, int reps, float* best_ms) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return int(hipErrorOutOfMemory);
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return int(hipErrorOutOfMemory);
+  }
+  int rc = launch_run(b, state, n_steps, k, new_pos, accept, delta, nullptr, stream);  // warm-up
+  float best = 0.f;
+  for (int r = 0; r < reps && !rc; ++r) {
+    hipEventRecord(e0, as_stream(stream));
+    rc = launch_run(b, state, n_steps, k, new_pos, accept, delta, nullptr, stream);
+    hipEventRecord(e1, as_stream(stream));
+    if (!rc) rc = int(hipEventSynchronize(e1));
+    float ms = 0.f;
+    if (!rc) rc = int(hipEventElapsedTime(&ms, e0, e1));
+    if (!rc && (r == 0 || ms < best)) best = ms;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *best_ms = best;
+  return rc;
+}
+
+int dev_arch(char* buf, int len) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return int(e);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return int(e);
+  std::snprintf(buf, size_t(len), "%s", prop.gcnArchName);
+  return 0;
+}
+
+int dev_memset(void* p, int value, size_t bytes) {
+  hipError_t e = hipMemset(p, value, bytes);
+  return e == hipSuccess ? 0 : int(e);
 }
 
 int dev_alloc(void** p, size_t bytes) {

@@ -7,7 +7,9 @@
 // one.
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -67,6 +69,125 @@ void inverse_n(const double* a, int dim, double* inv) {
 double wrap01(double x) {
   double f = x - std::floor(x);
   return f >= 1.0 ? 0.0 : f;
+}
+
+// Orthogonal sublattice of small index whose cosets sit at half box sides
+// (simple-cubic, bcc, fcc and hexagonal cells have one).  Integer vectors
+// with coefficients in [-2, 2] are searched for dim mutually orthogonal
+// lattice vectors v_d = n_d A of the smallest index |det n| <= 4; the cosets of
+// the sublattice they span are found by reducing lattice points into the box
+// spanned by them, and accepted only if every component of every coset offset
+// is 0 or half the box side.  Returns false if no such frame exists (the
+// kernels then use the general reduction with candidate images).
+struct OrthoFrame {
+  double F[9] = {0};    // x = s F (frame coordinates from fractional ones)
+  double box[3] = {0};
+  int n_coset = 0;
+  double cw[MAX_COSET][3] = {{0}};
+  double cc[MAX_COSET] = {0};
+};
+
+bool ortho_frame(const double* A, int dim, OrthoFrame& out) {
+  std::vector<std::array<int, 3>> ns;
+  std::vector<std::array<double, 3>> vs;
+  const int R = 2;
+  for (int a = -R; a <= R; ++a)
+    for (int b = -R; b <= R; ++b)
+      for (int c = (dim == 3 ? -R : 0); c <= (dim == 3 ? R : 0); ++c) {
+        const int n[3] = {a, b, c};
+        int first = 0;
+        for (int d = 0; d < dim && first == 0; ++d) first = n[d];
+        if (first <= 0) continue;  // one of each +-pair, no zero vector
+        std::array<double, 3> v = {0, 0, 0};
+        for (int i = 0; i < dim; ++i)
+          for (int x = 0; x < 3; ++x) v[x] += n[i] * A[i * 3 + x];
+        ns.push_back({a, b, c});
+        vs.push_back(v);
+      }
+  auto dot = [](const std::array<double, 3>& u, const std::array<double, 3>& v) {
+    return u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+  };
+  auto orth = [&](size_t i, size_t j) {
+    return std::fabs(dot(vs[i], vs[j])) <= 1e-12 * std::sqrt(dot(vs[i], vs[i]) * dot(vs[j], vs[j]));
+  };
+  int best_index = 5;
+  double best_len = INFINITY;
+  size_t pick[3] = {0, 0, 0};
+  const size_t nv = vs.size();
+  for (size_t i = 0; i < nv; ++i)
+    for (size_t j = i + 1; j < nv; ++j) {
+      if (!orth(i, j)) continue;
+      for (size_t k = (dim == 3 ? j + 1 : 0); k < (dim == 3 ? nv : 1); ++k) {
+        if (dim == 3 && (!orth(i, k) || !orth(j, k))) continue;
+        const auto &p = ns[i], &q = ns[j];
+        int det;
+        double len = std::sqrt(dot(vs[i], vs[i])) + std::sqrt(dot(vs[j], vs[j]));
+        if (dim == 3) {
+          const auto& r = ns[k];
+          det = p[0] * (q[1] * r[2] - q[2] * r[1]) - p[1] * (q[0] * r[2] - q[2] * r[0]) +
+                p[2] * (q[0] * r[1] - q[1] * r[0]);
+          len += std::sqrt(dot(vs[k], vs[k]));
+        } else {
+          det = p[0] * q[1] - p[1] * q[0];
+        }
+        det = std::abs(det);
+        if (det == 0 || det > best_index || (det == best_index && len >= best_len)) continue;
+        best_index = det;
+        best_len = len;
+        pick[0] = i;
+        pick[1] = j;
+        pick[2] = k;
+      }
+    }
+  if (best_index > 4) return false;
+  double e[3][3] = {{0}};
+  for (int d = 0; d < dim; ++d) {
+    const auto& v = vs[pick[d]];
+    out.box[d] = std::sqrt(dot(v, v));
+    for (int x = 0; x < 3; ++x) e[d][x] = v[x] / out.box[d];
+  }
+  for (int i = 0; i < dim; ++i)
+    for (int d = 0; d < dim; ++d)
+      out.F[i * 3 + d] = A[i * 3] * e[d][0] + A[i * 3 + 1] * e[d][1] + A[i * 3 + 2] * e[d][2];
+  // cosets: lattice points k A, k in [0, index)^dim, reduced into the box
+  std::vector<std::array<double, 3>> reps;
+  const int m = best_index;
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b)
+      for (int c = 0; c < (dim == 3 ? m : 1); ++c) {
+        const int k[3] = {a, b, c};
+        std::array<double, 3> x = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) {
+          for (int i = 0; i < dim; ++i) x[d] += k[i] * out.F[i * 3 + d];
+          x[d] -= out.box[d] * std::nearbyint(x[d] / out.box[d]);
+          if (std::fabs(std::fabs(x[d]) - 0.5 * out.box[d]) <= 1e-9 * out.box[d]) x[d] = 0.5 * out.box[d];
+          if (std::fabs(x[d]) <= 1e-9 * out.box[d]) x[d] = 0.0;
+        }
+        bool seen = false;
+        for (const auto& r : reps) {
+          bool same = true;
+          for (int d = 0; d < dim; ++d) same = same && std::fabs(r[d] - x[d]) <= 1e-9 * out.box[d];
+          seen = seen || same;
+        }
+        if (!seen) reps.push_back(x);
+      }
+  if (int(reps.size()) != m) return false;
+  out.n_coset = 0;
+  for (const auto& r : reps) {
+    bool zero = true;
+    for (int d = 0; d < dim; ++d) zero = zero && r[d] == 0.0;
+    if (zero) continue;
+    for (int d = 0; d < dim; ++d)
+      if (r[d] != 0.0 && r[d] != 0.5 * out.box[d]) return false;  // not a half-box offset
+    if (out.n_coset >= MAX_COSET) return false;
+    double cc = 0;
+    for (int d = 0; d < dim; ++d) {
+      out.cw[out.n_coset][d] = r[d] != 0.0 ? out.box[d] : 0.0;
+      cc += r[d] != 0.0 ? 0.25 * out.box[d] * out.box[d] : 0.0;
+    }
+    out.cc[out.n_coset++] = cc;
+  }
+  return true;
 }
 
 // Minimum over f in the box [c - 1/2, c + 1/2]^dim of f^T M f, M = A A^T the
@@ -597,6 +718,20 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
     }
     D.cand[c][3] = v2;
   }
+  OrthoFrame of;
+  D.ortho = ortho_frame(A, dim, of) ? 1 : 0;
+  if (D.ortho) {
+    std::copy(of.F, of.F + 9, D.F);
+    for (int d = 0; d < 3; ++d) {
+      D.box[d] = of.box[d];
+      D.ibox[d] = of.box[d] > 0 ? 1.0 / of.box[d] : 0.0;
+    }
+    D.n_coset = of.n_coset;
+    for (int c = 0; c < MAX_COSET; ++c) {
+      for (int d = 0; d < 3; ++d) D.cw[c][d] = of.cw[c][d];
+      D.cc[c] = of.cc[c];
+    }
+  }
   *out = S.release();
   return EWALD_OK;
 } catch (const std::bad_alloc&) {
@@ -633,6 +768,14 @@ ewald_status ewald_sys_candidates(const ewald_sys* s, int* n_cand, double* cand)
   if (cand)
     for (int c = 0; c < s->dev.n_cand; ++c)
       for (int e = 0; e < 3; ++e) cand[c * 3 + e] = s->cand_cart[c * 3 + e];
+  return EWALD_OK;
+}
+
+ewald_status ewald_sys_geometry(const ewald_sys* s, int* index, double* box) {
+  if (!s) return fail(EWALD_E_ARG, "sys is NULL");
+  if (index) *index = s->dev.ortho ? s->dev.n_coset + 1 : 0;
+  if (box)
+    for (int d = 0; d < 3; ++d) box[d] = s->dev.ortho ? s->dev.box[d] : 0.0;
   return EWALD_OK;
 }
 
@@ -781,6 +924,7 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
   std::vector<DevSys> ds;
   LaunchBatch& L = B->lb;
   L.all_wtab_lds = 1;
+  L.all_ortho = 1;
   L.n_walkers = n_walkers;
   L.dim = dim;
   L.mixed = sys[0]->precision == EWALD_FP32_MIXED ? 1 : 0;
@@ -795,9 +939,8 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
     L.poly_deg = std::max(L.poly_deg, sys[i]->dev.poly_deg);
     L.max_wtab = std::max(L.max_wtab, sys[i]->dev_uploaded.wtab_lds ? sys[i]->dev_uploaded.n_wtab : 0);
     L.all_wtab_lds &= sys[i]->dev_uploaded.wtab_lds;
+    L.all_ortho &= sys[i]->dev.ortho;
   }
-  // tuning override of the fused kernel's workgroup size (256 or 512)
-  if (const char* env = std::getenv("EWALD_RUN_THREADS")) L.run_threads = std::atoi(env);
   rc = dev_alloc(&B->d_sys, ds.size() * sizeof(DevSys));
   if (rc) return fail(EWALD_E_NOMEM, "device allocation failed");
   rc = dev_alloc(&B->d_walk, B->walkers.size() * sizeof(DevWalker));
@@ -889,6 +1032,151 @@ ewald_status ewald_run_moves_batch(ewald_batch* b, void* state, int n_steps, con
     return fail(EWALD_E_ARG, "k, new_pos, accept and delta must be non-NULL");
   int rc = launch_run(b->lb, static_cast<char*>(state), n_steps, k, new_pos, accept, delta, djastrow, stream);
   if (rc) return launch_status(rc, "run_moves");
+  return EWALD_OK;
+}
+
+ewald_status ewald_batch_set_tuning(ewald_batch* b, int threads, int chunk, int general_frame) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (!run_threads_valid(b->lb.max_n_seg, threads))
+    return fail(EWALD_E_ARG, "threads is not a fused-kernel workgroup size for this batch's segment count");
+  if (chunk < 0 || chunk > RUN_CHUNK) return fail(EWALD_E_ARG, "chunk must be in [0, 64]");
+  if (general_frame != 0 && general_frame != 1) return fail(EWALD_E_ARG, "general_frame must be 0 or 1");
+  std::lock_guard<std::mutex> lk(b->mu);
+  b->lb.run_threads = threads;
+  b->lb.run_chunk = chunk;
+  b->lb.general_frame = general_frame;
+  return EWALD_OK;
+}
+
+ewald_status ewald_batch_get_tuning(ewald_batch* b, int* threads, int* chunk, int* general_frame,
+                                    int* fused) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  RunPlan p{};
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    plan_run(b->lb, &p);
+  }
+  if (threads) *threads = p.threads;
+  if (chunk) *chunk = p.chunk;
+  if (general_frame) *general_frame = p.fused ? p.general_frame : 1;
+  if (fused) *fused = p.fused;
+  return EWALD_OK;
+}
+
+namespace {
+
+// Cache key of a tuning: everything the fused kernel's shape depends on.
+std::string tune_key(const ewald_batch* b) {
+  char arch[128] = "unknown";
+  dev_arch(arch, sizeof(arch));
+  const LaunchBatch& L = b->lb;
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "arch=%s dim=%d mixed=%d jastrow=%d segs=%d nm=%d particles=%d fixed=%d "
+                "poly=%d wtab=%d ortho=%d walkers=%d", arch, L.dim, L.mixed, L.has_jastrow, L.max_n_seg, L.max_nm,
+                L.max_particles, L.max_fixed, L.poly_deg, L.max_wtab, L.all_ortho, L.n_walkers);
+  return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* t, int* c, int* g) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    std::string l(line);
+    const size_t bar = l.find('|');
+    if (bar == std::string::npos || l.substr(0, bar) != key) continue;
+    found = std::sscanf(l.c_str() + bar + 1, "threads=%d chunk=%d general_frame=%d", t, c, g) == 3;
+  }
+  std::fclose(f);
+  return found;
+}
+
+}  // namespace
+
+ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char* cache_path, void* stream) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (!state) return fail(EWALD_E_ARG, "state must be non-NULL");
+  if (n_moves < 1 || n_moves > 4096) return fail(EWALD_E_ARG, "n_moves must be in [1, 4096]");
+  ewald_status st = check_state(b, state, 3, -1);
+  if (st != EWALD_OK) return st;
+  const std::string key = tune_key(b);
+  int t = 0, c = 0, g = 0;
+  if (cache_path && cache_lookup(cache_path, key, &t, &c, &g)) return ewald_batch_set_tuning(b, t, c, g);
+  // probe proposals: every move rejected, so the walkers' state is left as it was
+  const int W = b->lb.n_walkers, dim = b->lb.dim;
+  std::vector<int32_t> hk(size_t(n_moves) * W);
+  std::vector<double> hp(size_t(n_moves) * W * dim);
+  for (int m = 0; m < n_moves; ++m)
+    for (int w = 0; w < W; ++w) {
+      const ewald_sys* s = b->sys[size_t(b->walker_sys[w])];
+      const size_t i = size_t(m) * W + w;
+      hk[i] = int32_t((size_t(m) * 7919u + size_t(w) * 104729u) % size_t(s->n_mobile));
+      double f[3];  // fractional coordinates spread over the cell
+      for (int e = 0; e < dim; ++e)
+        f[e] = std::fmod(0.6180339887 * double(m + 1) + 0.4142135624 * double(e + 1) + 0.7320508076 * double(w % 97),
+                         1.0);
+      for (int d = 0; d < dim; ++d) {
+        double x = 0;
+        for (int e = 0; e < dim; ++e) x += f[e] * s->dev.A[e * 3 + d];
+        hp[i * dim + d] = x;
+      }
+    }
+  void *dk = nullptr, *dp = nullptr, *da = nullptr, *dd = nullptr;
+  auto release = [&]() {
+    for (void* p : {dk, dp, da, dd})
+      if (p) dev_free(p);
+  };
+  int rc = dev_alloc(&dk, hk.size() * 4);
+  if (!rc) rc = dev_alloc(&dp, hp.size() * 8);
+  if (!rc) rc = dev_alloc(&da, size_t(n_moves) * W);
+  if (!rc) rc = dev_alloc(&dd, size_t(n_moves) * W * 8);
+  if (!rc) rc = dev_upload(dk, hk.data(), hk.size() * 4);
+  if (!rc) rc = dev_upload(dp, hp.data(), hp.size() * 8);
+  if (!rc) rc = dev_memset(da, 0, size_t(n_moves) * W);
+  if (rc) {
+    release();
+    return launch_status(rc, "autotune set-up");
+  }
+  // candidates: every workgroup shape for the segment count, chunk sizes, both frames
+  const LaunchBatch saved = b->lb;
+  float best = -1.f;
+  int bt = 0, bc = 0, bg = 0;
+  for (int threads : {256, 512, 1024}) {
+    if (!run_threads_valid(b->lb.max_n_seg, threads)) continue;
+    for (int chunk : {0, 32, 16})
+      for (int general : {0, 1}) {
+        if (general == 0 && !b->lb.all_ortho) continue;
+        LaunchBatch L = saved;
+        L.run_threads = threads;
+        L.run_chunk = chunk;
+        L.general_frame = general;
+        RunPlan p{};
+        plan_run(L, &p);
+        if (!p.fused) continue;
+        float ms = 0.f;
+        rc = time_run(L, static_cast<char*>(state), n_moves, static_cast<int32_t*>(dk), static_cast<double*>(dp),
+                      static_cast<uint8_t*>(da), static_cast<double*>(dd), stream, 2, &ms);
+        if (rc) {
+          release();
+          return launch_status(rc, "autotune");
+        }
+        if (best < 0.f || ms < best) {
+          best = ms;
+          bt = threads;
+          bc = chunk;
+          bg = general;
+        }
+      }
+  }
+  release();
+  if (best < 0.f) return EWALD_OK;  // the fused kernel does not fit: nothing to tune
+  st = ewald_batch_set_tuning(b, bt, bc, bg);
+  if (st != EWALD_OK || !cache_path) return st;
+  if (FILE* f = std::fopen(cache_path, "a")) {
+    std::fprintf(f, "%s|threads=%d chunk=%d general_frame=%d ms=%.4f\n", key.c_str(), bt, bc, bg, double(best));
+    std::fclose(f);
+  }
   return EWALD_OK;
 }
 

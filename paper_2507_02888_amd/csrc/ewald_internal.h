@@ -16,6 +16,7 @@ namespace ewald {
 constexpr int SEG = 4;            // G slots per segment: consecutive n along the last reduced index
 constexpr int BLOCK = 256;        // threads per workgroup of every kernel
 constexpr int MAX_CAND = 16;      // +-pairs of minimum-image candidate offsets
+constexpr int MAX_COSET = 3;      // nonzero cosets of an orthogonal sublattice (index <= 4)
 constexpr int HDR_BYTES = 256;    // per-walker state header
 constexpr int MAX_SPT = 8;        // segments per thread held in registers (MAX_SEGMENTS / BLOCK)
 constexpr int TILE_P = 8;         // particles per phase-table tile when rebuilding rho
@@ -56,6 +57,18 @@ struct DevSys {
   double poly_scale;    // 2 / r_cut^2: t = r^2 poly_scale - 1 maps [0, r_cut^2] to [-1, 1]
   double e_const;       // E_self + E_background + fixed-ion real-space energy
   double cand[MAX_CAND][4];  // (v_x, v_y, v_z, |v|^2) of one of each +-pair, rotated frame
+  // Orthogonal-sublattice frame (ortho = 1): the lattice contains mutually
+  // orthogonal vectors of lengths box[d] spanning a sublattice of index
+  // n_coset + 1 whose nonzero cosets are offset by half box sides.  Positions
+  // in this frame are x = s F; the minimum image is a per-axis wrap into the
+  // box plus, per coset c, |x|^2 + cc[c] - sum_d cw[c][d] |x_d|.
+  int ortho;
+  int n_coset;
+  double F[9];
+  double box[3];
+  double ibox[3];
+  double cw[MAX_COSET][3];  // box[d] where coset c has a half-box offset along d, else 0
+  double cc[MAX_COSET];     // sum over those d of box[d]^2 / 4
   // erf(alpha r)/(alpha r) = sum_i p64[i] t^i for r < r_cut (p32: FP32 copy of lower accuracy)
   double p64[POLY_MAX + 1];
   float p32[POLY32_MAX + 1];
@@ -115,7 +128,22 @@ struct LaunchBatch {
   int poly_deg;             // max pair-polynomial degree over systems (16 or 32)
   int max_wtab;             // largest LDS shell table over systems (0: none in LDS)
   int all_wtab_lds;         // every system's shell table fits in LDS
-  int run_threads;          // fused-kernel workgroup size override (0: default)
+  int all_ortho;            // every system has an orthogonal-sublattice frame (DevSys::ortho)
+  int run_threads;          // fused kernel: workgroup size (0: default for the segment count)
+  int run_chunk;            // fused kernel: moves per chunk (0: as many as LDS allows, <= RUN_CHUNK)
+  int general_frame;        // fused kernel: 1 = general minimum-image reduction even if all_ortho
+};
+
+// The fused kernel's launch shape for a batch (all zero: it does not fit and
+// the per-step kernels run instead).
+struct RunPlan {
+  int fused;          // 1 if the fused kernel runs
+  int threads;        // workgroup size
+  int spt;            // segments per thread
+  int chunk;          // moves per chunk
+  int general_frame;  // 1 = general minimum-image reduction
+  int lds_bytes;
+  int blocks_per_cu;  // workgroups per CU allowed by registers
 };
 
 // Each returns 0 on success or the hipError_t of the failed launch.
@@ -128,11 +156,19 @@ int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k,
                const double* new_pos, const uint8_t* accept, double* delta, double* djastrow,
                void* stream);
 
+void plan_run(const LaunchBatch& b, RunPlan* plan);
+bool run_threads_valid(int max_n_seg, int threads);
+// Warm-up plus `reps` timed fused launches on `stream` (synchronises); best time in ms.
+int time_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
+             const uint8_t* accept, double* delta, void* stream, int reps, float* best_ms);
+
 // Device memory helpers (ewald_device.hip); return 0 on success.
 int dev_alloc(void** p, size_t bytes);
 int dev_free(void* p);
 int dev_upload(void* dst, const void* src, size_t bytes);
 int dev_current(int* device);
 const char* dev_error_string(int code);
+int dev_arch(char* buf, int len);  // the current device's architecture name
+int dev_memset(void* p, int value, size_t bytes);
 
 }  // namespace ewald

@@ -27,9 +27,10 @@ STATUS_NAMES = {0: "EWALD_OK", 1: "EWALD_E_ARG", 2: "EWALD_E_RCUT", 3: "EWALD_E_
 
 # every symbol include/ewald.h declares
 EXPORTS = ("ewald_setup", "ewald_sys_query", "ewald_sys_tables", "ewald_sys_candidates",
-           "ewald_sys_destroy", "ewald_batch_create", "ewald_batch_layout", "ewald_state_offsets",
+           "ewald_sys_geometry", "ewald_sys_destroy", "ewald_batch_create", "ewald_batch_layout", "ewald_state_offsets",
            "ewald_batch_destroy", "ewald_energy_batch", "ewald_move_delta_batch",
-           "ewald_accept_batch", "ewald_run_moves_batch", "ewald_last_error")
+           "ewald_accept_batch", "ewald_run_moves_batch", "ewald_batch_set_tuning",
+           "ewald_batch_get_tuning", "ewald_autotune", "ewald_last_error")
 
 
 class EwaldError(RuntimeError):
@@ -65,6 +66,7 @@ def load() -> ctypes.CDLL:
     lib.ewald_sys_query.argtypes = [vp, P(c_int), P(c_int), P(c_int), P(ctypes.c_double), P(ctypes.c_double)]
     lib.ewald_sys_tables.argtypes = [vp, vp, vp, vp, vp]
     lib.ewald_sys_candidates.argtypes = [vp, P(c_int), vp]
+    lib.ewald_sys_geometry.argtypes = [vp, P(c_int), vp]
     lib.ewald_sys_destroy.argtypes = [vp]
     lib.ewald_sys_destroy.restype = None
     lib.ewald_batch_create.argtypes = [P(vp), c_int, P(c_int), c_int, P(vp)]
@@ -76,6 +78,9 @@ def load() -> ctypes.CDLL:
     lib.ewald_move_delta_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.ewald_accept_batch.argtypes = [vp, vp, vp, vp]
     lib.ewald_run_moves_batch.argtypes = [vp, vp, c_int, vp, vp, vp, vp, vp, vp]
+    lib.ewald_batch_set_tuning.argtypes = [vp, c_int, c_int, c_int]
+    lib.ewald_batch_get_tuning.argtypes = [vp, P(c_int), P(c_int), P(c_int), P(c_int)]
+    lib.ewald_autotune.argtypes = [vp, vp, c_int, ctypes.c_char_p, vp]
     lib.ewald_last_error.argtypes = []
     lib.ewald_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -165,6 +170,14 @@ def ewald_sys_candidates(sys_h: int) -> np.ndarray:
     return out
 
 
+def ewald_sys_geometry(sys_h: int):
+    """(sublattice index or 0 for the general reduction, box lengths [3])."""
+    idx = ctypes.c_int()
+    box = np.zeros(3)
+    _check(load().ewald_sys_geometry(ctypes.c_void_p(sys_h), ctypes.byref(idx), box.ctypes.data))
+    return idx.value, box
+
+
 def ewald_sys_destroy(sys_h: int) -> None:
     load().ewald_sys_destroy(ctypes.c_void_p(sys_h))
 
@@ -221,6 +234,22 @@ def ewald_run_moves_batch(batch_h, state_ptr, n_steps, k_ptr, new_pos_ptr, accep
                                         ctypes.c_void_p(k_ptr), ctypes.c_void_p(new_pos_ptr),
                                         ctypes.c_void_p(accept_ptr), ctypes.c_void_p(delta_ptr),
                                         ctypes.c_void_p(djastrow_ptr or None), ctypes.c_void_p(stream or None)))
+
+
+def ewald_batch_set_tuning(batch_h, threads=0, chunk=0, general_frame=0) -> None:
+    _check(load().ewald_batch_set_tuning(ctypes.c_void_p(batch_h), int(threads), int(chunk), int(general_frame)))
+
+
+def ewald_batch_get_tuning(batch_h) -> dict:
+    v = [ctypes.c_int() for _ in range(4)]
+    _check(load().ewald_batch_get_tuning(ctypes.c_void_p(batch_h), *[ctypes.byref(x) for x in v]))
+    return dict(threads=v[0].value, chunk=v[1].value, general_frame=v[2].value, fused=v[3].value)
+
+
+def ewald_autotune(batch_h, state_ptr, n_moves=32, cache_path=None, stream=0) -> None:
+    _check(load().ewald_autotune(ctypes.c_void_p(batch_h), ctypes.c_void_p(state_ptr), int(n_moves),
+                                 None if cache_path is None else str(cache_path).encode(),
+                                 ctypes.c_void_p(stream or None)))
 
 
 def ewald_last_error() -> str:
@@ -290,6 +319,15 @@ class Batch:
         ewald_run_moves_batch(self.handle, self.state.data_ptr(), int(k.shape[0]), k.data_ptr(),
                               new_pos.data_ptr(), accept.data_ptr(), delta.data_ptr(),
                               0 if djastrow is None else djastrow.data_ptr(), self.stream())
+
+    def set_tuning(self, threads=0, chunk=0, general_frame=0):
+        ewald_batch_set_tuning(self.handle, threads, chunk, general_frame)
+
+    def tuning(self) -> dict:
+        return ewald_batch_get_tuning(self.handle)
+
+    def autotune(self, n_moves=32, cache_path=None):
+        ewald_autotune(self.handle, self.state.data_ptr(), n_moves, cache_path, self.stream())
 
     def walker_rho(self, w: int) -> np.ndarray:
         """rho of walker w (valid and padding slots) as complex numpy, after a sync."""

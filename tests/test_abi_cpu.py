@@ -99,6 +99,10 @@ def test_validation_errors(lib):
     assert lib.ewald_run_moves_batch(None, None, 1, None, None, None, None, None, None) == ew.EWALD_E_ARG
     assert lib.ewald_sys_query(None, None, None, None, None, None) == ew.EWALD_E_ARG
     assert lib.ewald_batch_layout(None, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_batch_set_tuning(None, 0, 0, 0) == ew.EWALD_E_ARG
+    assert lib.ewald_batch_get_tuning(None, None, None, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_autotune(None, None, 8, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_sys_geometry(None, None, None) == ew.EWALD_E_ARG
 
 
 def test_batch_create_validation(lib):
@@ -213,3 +217,50 @@ def test_batch_create_without_device(lib):
     with pytest.raises(ew.EwaldError) as e:
         ew.ewald_batch_create([s.handle], np.zeros(2, dtype=np.int32))
     assert e.value.status == ew.EWALD_E_HIP
+
+
+@pytest.mark.parametrize("cfg_id,index", [(1, 1), (2, 2), (3, 2), (4, 2), (5, 2)])
+def test_orthogonal_frame(lib, cfg_id, index):
+    """Orthogonal sublattices found at set-up: the sc cell itself (index 1);
+    for bcc the conventional cube (index 2, one coset at the body centre); for
+    fcc the tetragonal cell spanned by a1, a2 - a3 and a2 + a3 - a1 (index 2,
+    box c/sqrt2 x c/sqrt2 x c); for the hexagonal cell the a x a sqrt3 rectangle
+    (index 2).  Box volume = index x cell volume.  For the cubic-axis frames
+    (sc, bcc) the per-axis wrap plus the half-box coset check reproduces the
+    brute-force minimum image."""
+    import itertools
+    system = wl.config(cfg_id).systems[0]
+    s = ew.System(system)
+    idx, box = ew.ewald_sys_geometry(s.handle)
+    assert idx == index
+    d = system.dim
+    A = system.lattice[:d, :d]
+    vol = abs(np.linalg.det(A))
+    assert abs(np.prod(box[:d]) - index * vol) <= 1e-9 * vol
+    if cfg_id in (2, 4):
+        c = abs(A[0, 1]) * 2.0  # conventional cube edge (rows are (0,1,1) c/2 ...)
+        assert np.allclose(sorted(box), [c / math.sqrt(2), c / math.sqrt(2), c], rtol=1e-12)
+    if cfg_id == 3:
+        a = np.linalg.norm(A[0])
+        assert np.allclose(sorted(box[:2]), [a, a * math.sqrt(3)], rtol=1e-12)
+    if cfg_id in (1, 5):  # frame axes along the Cartesian axes
+        L = box[0]
+        assert np.allclose(box, L, rtol=1e-12)
+        g = np.random.default_rng(5)
+        r0 = (g.random((20000, d)) - 0.5) @ A
+        brute = np.full(r0.shape[0], np.inf)
+        for cc in itertools.product(range(-2, 3), repeat=d):
+            brute = np.minimum(brute, np.sum((r0 + np.array(cc) @ A) ** 2, axis=1))
+        x = r0 - L * np.rint(r0 / L)
+        best = np.sum(x * x, axis=1)
+        if index == 2:  # body-centre coset
+            best = np.minimum(best, best + 0.75 * L * L - L * np.abs(x).sum(axis=1))
+        assert np.allclose(best, brute, rtol=1e-12, atol=1e-12)
+
+
+def test_general_cell_has_no_frame(lib):
+    lat = np.array([[6.0, 0.3, 0.0], [0.5, 5.5, 0.2], [0.1, -0.4, 6.2]])
+    sysm = wl.System("tri", 3, lat, 2, np.array([-1.0, -2.0]), np.zeros((0, 3)), np.zeros(0),
+                     1.1, 2.6, 8 * 2 * math.pi / 6.0)
+    idx, box = ew.ewald_sys_geometry(ew.System(sysm).handle)
+    assert idx == 0 and np.all(box == 0)

@@ -320,6 +320,37 @@ def test_two_particles_and_ions(oracle_lib):
         tol = 1e-10 * scale if prec == FP64 else 1e-5
         assert abs(e.item() - r["energy0"]) <= (1e-10 if prec == FP64 else 1e-6) * scale
         assert np.max(np.abs(d.cpu().numpy() - r["delta"])) <= tol
+        # the fused sweep on this triclinic cell (general minimum-image reduction)
+        assert ew.ewald_sys_geometry(sysh.handle)[0] == 0
+        batch.energy(pos, e)
+        df = torch.zeros((4, 1), dtype=torch.float64, device="cuda")
+        batch.run_moves(torch.tensor(ks.reshape(4, 1), device="cuda"), torch.tensor(newp.reshape(4, 1, 3), device="cuda"),
+                        torch.tensor(acc.reshape(4, 1), device="cuda"), df)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(df.cpu().numpy()[:, 0] - r["delta"])) <= tol
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [2, 3, 5])
+def test_general_frame_matches_ortho(cfg_id, precision):
+    """The fused sweep with the general minimum-image reduction (forced)
+    equals the one in the orthogonal-sublattice frame on the same cell."""
+    W, S, w0 = SUBSETS[cfg_id]
+    say(f"[general vs ortho frame] cfg={cfg_id} precision={precision}")
+    a = Case(cfg_id, W, S, precision, walker_start=w0)
+    assert ew.ewald_sys_geometry(a.systems[0].handle)[0] > 0
+    assert a.batch.tuning()["general_frame"] == 0
+    a.run_energy()
+    d1, j1 = a.fused()
+    b = Case(cfg_id, W, S, precision, walker_start=w0)
+    b.batch.set_tuning(general_frame=1)
+    assert b.batch.tuning()["general_frame"] == 1
+    b.run_energy()
+    d2, j2 = b.fused()
+    tol = 1e-12 if precision == FP64 else 1e-9
+    scale = max(abs(x) for x in a.energy.cpu().numpy())
+    assert np.max(np.abs(d1 - d2)) <= tol * max(1.0, scale)
+    assert np.max(np.abs(j1 - j2)) <= tol * max(1.0, scale)
 
 
 @pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
@@ -383,3 +414,68 @@ def test_graph_replay_matches_eager(precision):
     for w in range(c.W):
         assert np.array_equal(c.batch.walker_rho(w), eager.batch.walker_rho(w))
         assert np.array_equal(c.batch.walker_positions(w), eager.batch.walker_positions(w))
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_tuning_shapes_agree(precision):
+    """Every fused-kernel launch shape (workgroup size, chunk length, frame)
+    gives the same sweep up to rounding order."""
+    W, S, w0 = SUBSETS[5]
+    say(f"[tuning shapes] precision={precision}")
+    ref = Case(5, W, S, precision, walker_start=w0, refresh_every=3)
+    t = ref.batch.tuning()
+    assert t["fused"] == 1 and t["threads"] == 1024 and 1 <= t["chunk"] <= 64
+    ref.run_energy()
+    d0, j0 = ref.fused()
+    tol = 1e-12 if precision == FP64 else 1e-9
+    scale = max(1.0, max(abs(x) for x in ref.energy.cpu().numpy()))
+    for threads, chunk, general in ((512, 0, 0), (1024, 5, 0), (512, 1, 1), (0, 64, 1)):
+        c = Case(5, W, S, precision, walker_start=w0, refresh_every=3)
+        c.batch.set_tuning(threads, chunk, general)
+        t = c.batch.tuning()
+        assert t["threads"] == (threads or 1024) and t["general_frame"] == general
+        if chunk:  # an upper bound: fewer moves per chunk when LDS does not hold them
+            assert t["chunk"] == chunk if chunk <= 8 else 8 <= t["chunk"] <= chunk
+        c.run_energy()
+        d, j = c.fused()
+        assert np.max(np.abs(d - d0)) <= tol * scale, (threads, chunk, general)
+        assert np.max(np.abs(j - j0)) <= tol * scale
+        for w in range(W):
+            assert np.max(np.abs(c.batch.walker_rho(w) - ref.batch.walker_rho(w))) <= 1e-9
+    with pytest.raises(ew.EwaldError):
+        ref.batch.set_tuning(threads=256)  # not a shape for 990 segments
+    with pytest.raises(ew.EwaldError):
+        ref.batch.set_tuning(chunk=65)
+
+
+def test_autotune_keeps_state_and_caches(tmp_path, oracle_lib):
+    """The autotuner probes with rejected moves (state unchanged), stores its
+    choice in the cache file and re-applies it from there; the tuned sweep
+    still matches the oracle."""
+    W, S, w0 = SUBSETS[2]
+    say("[autotune] cfg=2")
+    c = Case(2, W, S, FP64, walker_start=w0)
+    c.run_energy()
+    before = [c.batch.walker_rho(w) for w in range(W)]
+    pos_before = [c.batch.walker_positions(w) for w in range(W)]
+    cache = tmp_path / "tune.txt"
+    c.batch.autotune(n_moves=8, cache_path=str(cache))
+    t1 = c.batch.tuning()
+    assert t1["fused"] == 1
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1 and "threads=" in lines[0]
+    for w in range(W):
+        assert np.array_equal(c.batch.walker_rho(w), before[w])
+        assert np.array_equal(c.batch.walker_positions(w), pos_before[w])
+        assert c.batch.walker_header(w)["n_accepts"] == 0
+    c2 = Case(2, W, S, FP64, walker_start=w0)
+    c2.run_energy()
+    c2.batch.set_tuning(256, 7, 1)
+    c2.batch.autotune(n_moves=8, cache_path=str(cache))  # from the cache: no new line
+    assert c2.batch.tuning() == t1
+    assert len(cache.read_text().strip().splitlines()) == 1
+    d, _ = c.fused()
+    for w in range(W):
+        r = c.oracle(oracle_lib, w)
+        scale = max(abs(r["energy0"]), e_scale(c.system(w)))
+        assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale

@@ -81,13 +81,13 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_
                   jastrow_a=b.jastrow_a)
     batch = ew.Batch([s], b.walker_sys, device=dev)
     t = batch_inputs["tensors"]
-    # launch shape: the autotuner's choice (probe sweep of rejected moves,
-    # outside the timed region), or a fixed workgroup size
+    # launch shape: the autotuner's choice (probe sweeps on a copy of the
+    # state, outside the timed region), or a fixed workgroup size
     batch.energy(t["pos"], torch.zeros(b.walkers, dtype=torch.float64, device=dev))
     if threads:
         batch.set_tuning(threads=threads)
     else:
-        batch.autotune(n_moves=32)
+        batch.autotune(n_moves=max(32, 2 * K) if precision == ew.EWALD_FP32_MIXED and K > 0 else 32)
     tuning = batch.tuning()
     W, S = b.walkers, b.steps
     energy = torch.zeros(W, dtype=torch.float64, device=dev)

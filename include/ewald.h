@@ -237,8 +237,10 @@ ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, in
 
 /* Time every launch shape of ewald_run_moves_batch on this batch and keep
  * the fastest (ewald_batch_set_tuning).  The probe runs n_moves (1..4096)
- * proposals per walker, all rejected, on `state`, which must be ready (after
- * ewald_energy_batch, no pending move) and is left unchanged.  With a
+ * proposals per walker, every other one accepted, on a device copy of
+ * `state`, which must be ready (after ewald_energy_batch, no pending move)
+ * and is left unchanged; in the FP32-mixed form n_moves >= 2 refresh_every
+ * makes the probe include rho rebuilds.  With a
  * cache_path, a tuning stored there for the same device architecture and
  * batch shape is applied without timing, and a new one is appended (one text
  * line per shape).  Allocates temporary device buffers and synchronises

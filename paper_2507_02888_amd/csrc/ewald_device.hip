@@ -240,6 +240,8 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
 template <int PD>
 struct PairAcc<false, PD> {
   double s = 0.0;
+  const double* __restrict__ c;  // the polynomial coefficients (system tables, or an LDS copy)
+  __device__ __forceinline__ PairAcc(const DevSys* __restrict__ S, const double* c64, const float*) : c(c64) {}
   template <int NE>
   __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE], const DevSys* __restrict__ S) {
     double ir[NE], t[NE], p[NE];
@@ -248,13 +250,13 @@ struct PairAcc<false, PD> {
     for (int e = 0; e < NE; ++e) {
       ir[e] = rsqrt_pos(r2[e]);
       t[e] = fma(r2[e], scale, -1.0);
-      p[e] = S->p64[PD];
+      p[e] = c[PD];
     }
 #pragma unroll
     for (int i = PD - 1; i >= 0; --i) {
-      const double c = S->p64[i];
+      const double ci = c[i];
 #pragma unroll
-      for (int e = 0; e < NE; ++e) p[e] = fma(p[e], t[e], c);
+      for (int e = 0; e < NE; ++e) p[e] = fma(p[e], t[e], ci);
     }
     const double rc2 = S->rc2, alpha = S->alpha;
 #pragma unroll
@@ -271,6 +273,8 @@ struct PairAcc<true, PD> {
   static constexpr int PF = PD == 16 ? 12 : 22;
   double inv = 0.0;
   Kahan erfpart;
+  const float* __restrict__ c;  // the FP32 polynomial coefficients (system tables, or an LDS copy)
+  __device__ __forceinline__ PairAcc(const DevSys* __restrict__ S, const double*, const float* c32) : c(c32) {}
   template <int NE>
   __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE], const DevSys* __restrict__ S) {
     float t[NE], p[NE];
@@ -280,13 +284,13 @@ struct PairAcc<true, PD> {
     for (int e = 0; e < NE; ++e) {
       ir[e] = rsqrt_pos(r2[e]);
       t[e] = fmaf(float(r2[e]), scale, -1.0f);
-      p[e] = S->p32[PF];
+      p[e] = c[PF];
     }
 #pragma unroll
     for (int i = PF - 1; i >= 0; --i) {
-      const float c = S->p32[i];
+      const float ci = c[i];
 #pragma unroll
-      for (int e = 0; e < NE; ++e) p[e] = fmaf(p[e], t[e], c);
+      for (int e = 0; e < NE; ++e) p[e] = fmaf(p[e], t[e], ci);
     }
     const double rc2 = S->rc2;
     const float alpha = float(S->alpha);
@@ -311,7 +315,7 @@ template <int DIM, bool MIXED, int PD, int NT>
 __device__ __forceinline__ double real_move(const double* sn, const double* so, int k, const double* pos,
                                             const double* q, int n, const DevSys* __restrict__ S) {
   constexpr int PPR = NT >= 1024 ? 1 : 2;
-  PairAcc<MIXED, PD> pr;
+  PairAcc<MIXED, PD> pr(S, S->p64, S->p32);
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
   for (int j0 = threadIdx.x; j0 < n; j0 += PPR * NT) {
@@ -364,8 +368,9 @@ template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO>
 __device__ __forceinline__ double real_move_own(const double* sn, const double* so, int k,
                                                 const double (&ps)[PPR][DIM], const double (&pq)[PPR],
                                                 const double* lpos, const double* lq, int n,
-                                                const DevSys* __restrict__ S) {
-  PairAcc<MIXED, PD> pr;
+                                                const DevSys* __restrict__ S, const double* c64,
+                                                const float* c32) {
+  PairAcc<MIXED, PD> pr(S, c64, c32);
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
   {
@@ -474,11 +479,24 @@ __device__ __forceinline__ double wave_sum_to_lane63(double v) {
   return v;
 }
 
-// One row of a phase table, tab_d[nm + m] = exp(2 pi i m s) and its conjugate
-// at nm - m for m = 0..nm, by one thread: powers of exp(2 pi i s) formed by
-// repeated FP64 multiplication (the paper's buffered powers, Sec. 5.2), with an
-// exact restart every 8 powers so the rounding error stays below ~8 ulp;
-// stored in R.
+// The value lane l of the wave holds, in scalar registers (l uniform).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Phase tables: per dimension d one row of tbl = 2 nm + 1 complex entries,
+// exp(2 pi i n s_d) at [nm + n] for n = -nm..nm; a table of one position is
+// DIM rows.
+template <typename R>
+__device__ __forceinline__ cplx<R> tab_at(const cplx<R>* tab, int row, int idx, int tbl) {
+  return tab[row * tbl + idx];
+}
+
+// One row, by one thread: powers of exp(2 pi i s) formed by repeated FP64
+// multiplication (the paper's buffered powers, Sec. 5.2), with an exact
+// restart every 8 powers so the rounding error stays below ~8 ulp; stored in R.
 template <typename R>
 __device__ __forceinline__ void fill_row(cplx<R>* row, double s, int nm) {
   const cplx<double> u = turn(s);
@@ -495,8 +513,8 @@ __device__ __forceinline__ void fill_row(cplx<R>* row, double s, int nm) {
 template <int DIM, typename R>
 __device__ __forceinline__ cplx<R> anchor(const cplx<R>* tab, uint32_t pn, int nm) {
   const int tbl = 2 * nm + 1;
-  cplx<R> e = cmul(tab[nm + unpack_n(pn, 0)], tab[tbl + nm + unpack_n(pn, 1)]);
-  if (DIM == 3) e = cmul(e, tab[2 * tbl + nm + unpack_n(pn, 2)]);
+  cplx<R> e = cmul(tab_at(tab, 0, nm + unpack_n(pn, 0), tbl), tab_at(tab, 1, nm + unpack_n(pn, 1), tbl));
+  if (DIM == 3) e = cmul(e, tab_at(tab, 2, nm + unpack_n(pn, 2), tbl));
   return e;
 }
 
@@ -527,14 +545,24 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
     for (int e = threadIdx.x; e < np * DIM; e += NT)  // row e: particle e / DIM, dimension e % DIM
       fill_row<double>(tabs + e * tbl, pos[p0 * DIM + e], nm);
     __syncthreads();
+    // the charge and step phase exp(2 pi i s_last) of particle p0 + l sit in
+    // lane l of every wave (tiles hold at most 64 particles); the passes
+    // below take them from there into scalar registers, so that the LDS
+    // serves only the per-lane table entries
+    const int lane = threadIdx.x & 63;
+    const double lq_ = lane < np ? q[p0 + lane] : 0.0;
+    const cplx<double> lu_ =
+        lane < np ? tab_at(tabs + lane * DIM * tbl, DIM - 1, nm + 1, tbl) : cplx<double>{1.0, 0.0};
     // two particles per pass: independent chains for latency hiding (an odd
     // tile's last pass pairs the particle with itself at zero charge)
     for (int p = 0; p < np; p += 2) {
       const bool two = p + 1 < np;
+      const int p1 = two ? p + 1 : p;
       const cplx<double>* t0 = tabs + p * DIM * tbl;
-      const cplx<double>* t1 = two ? t0 + DIM * tbl : t0;
-      const double q0 = q[p0 + p], q1 = two ? q[p0 + p + 1] : 0.0;
-      const cplx<double> u0 = t0[(DIM - 1) * tbl + nm + 1], u1 = t1[(DIM - 1) * tbl + nm + 1];
+      const cplx<double>* t1 = tabs + p1 * DIM * tbl;
+      const double q0 = lane_value(lq_, p), q1 = two ? lane_value(lq_, p1) : 0.0;
+      const cplx<double> u0 = {lane_value(lu_.x, p), lane_value(lu_.y, p)};
+      const cplx<double> u1 = {lane_value(lu_.x, p1), lane_value(lu_.y, p1)};
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
         if (seg0 + i * NT < nseg) {
@@ -635,7 +663,7 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
 
   // real space: each unordered mobile pair once (pair i with i+1..i+(n-1)/2
   // cyclically, plus i+n/2 for i < n/2 when n is even), then every fixed ion
-  PairAcc<false, PD> pr;
+  PairAcc<false, PD> pr(S, S->p64, S->p32);
   const double rc2 = S->rc2;
   const int half = (n - 1) / 2;
   for (int i = tid; i < n; i += BLOCK) {
@@ -735,7 +763,7 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
   __syncthreads();
 
   // reciprocal space: t(G) = 2 q Re(conj(rho) d) + q^2 |d|^2, d = e_new - e_old
-  const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
+  const cplx<R> uo = tab_at(to, DIM - 1, nm + 1, tbl), un = tab_at(tn, DIM - 1, nm + 1, tbl);
   const double* __restrict__ wt = S->w;
   const double* __restrict__ ja = S->ja;
   // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)]: q^2 is applied
@@ -757,6 +785,7 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
     const uint32_t pn = S->seg_n[s];
     cplx<R> eo = anchor<DIM, R>(to, pn, nm);
     cplx<R> en = anchor<DIM, R>(tn, pn, nm);
+    float segE = 0.f, segJ = 0.f;  // mixed form: FP32 sums per segment, compensated across segments
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
       const size_t g = size_t(j) * nseg + s;
@@ -773,14 +802,18 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
       const R ux = fma(c2q, R(rcur[j].x), dx), uy = fma(c2q, R(rcur[j].y), dy);
       const R t = fma(ux, dx, uy * dy);
       if (MIXED) {
-        accE32.add(float(wg) * float(t));
-        if (ja) accJ32.add(float(aj) * float(t));
+        segE = fmaf(float(wg), float(t), segE);
+        if (ja) segJ = fmaf(float(aj), float(t), segJ);
       } else {
         accE64 = fma(double(wg), double(t), accE64);
         if (ja) accJ64 = fma(double(aj), double(t), accJ64);
       }
       eo = cmul(eo, uo);
       en = cmul(en, un);
+    }
+    if (MIXED) {
+      accE32.add(segE);
+      if (ja) accJ32.add(segJ);
     }
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
@@ -838,7 +871,7 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
   __syncthreads();  // every thread has read the header and pending position
   if (acc) {
     const R q = R(S->mobile_q[pk]);
-    const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
+    const cplx<R> uo = tab_at(to, DIM - 1, nm + 1, tbl), un = tab_at(tn, DIM - 1, nm + 1, tbl);
     double2* rho2 = reinterpret_cast<double2*>(rho);
     for (int s = tid; s < nseg; s += BLOCK) {
       double2 r[SEG];
@@ -934,7 +967,7 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
 // FP64 rebuild of the mixed form runs between chunks.
 struct RunLds {
   // byte offsets into dynamic LDS; positions start at 0
-  uint32_t q, red, wtab, ctab, sn, so, xn, xo, part, k, acc, cnt;
+  uint32_t q, red, wtab, ctab, sn, so, xn, xo, c2q, part, k, acc, cnt;
   int ch;     // moves per chunk
   int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
 };
@@ -972,6 +1005,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   double* st_so = reinterpret_cast<double*>(lds + L.so);
   double* st_xn = reinterpret_cast<double*>(lds + L.xn);  // sn, so in the real-space geometry (ORTHO)
   double* st_xo = reinterpret_cast<double*>(lds + L.xo);
+  double* st_c2q = reinterpret_cast<double*>(lds + L.c2q);  // 2 / q_k of each move (0 for q_k = 0)
   double* st_part = reinterpret_cast<double*>(lds + L.part);  // [CH][NW][4 rows][2]
   int* st_k = reinterpret_cast<int*>(lds + L.k);
   int* st_acc = reinterpret_cast<int*>(lds + L.acc);
@@ -1053,6 +1087,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           frame_coords<DIM>(so, S, st_xo + tid * DIM);
           frame_coords<DIM>(st_sn + tid * DIM, S, st_xn + tid * DIM);
         }
+        st_c2q[tid] = lq[k] != 0.0 ? 2.0 / lq[k] : 0.0;
       }
       st_cnt[tid] = c + ((k >= 0 && st_acc[tid] != 0) ? 1 : 0);  // accepts since the rebuild, after this move
     }
@@ -1091,16 +1126,17 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
         if (qk != 0.0) {  // uniform; a neutral particle's move changes nothing
           const cplx<R>* to = ctab + mm * mstride;
           const cplx<R>* tn = to + DIM * tbl;
-          const cplx<R> uo = to[(DIM - 1) * tbl + nm + 1], un = tn[(DIM - 1) * tbl + nm + 1];
+          const cplx<R> uo = tab_at(to, DIM - 1, nm + 1, tbl), un = tab_at(tn, DIM - 1, nm + 1, tbl);
           // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)], q^2 applied to the sums
-          const R q = R(qk), c2q = R(2.0 / qk);
+          const R q = R(qk), c2q = R(st_c2q[mm]);
           double accE64 = 0.0, accJ64 = 0.0;
-          Kahan accE32, accJ32;
+          Kahan accE32, accJ32;  // mixed form: FP32 sums per segment, compensated across segments
 #pragma unroll
           for (int i = 0; i < SPT; ++i) {
             if (tid + i * NT < nseg) {
               cplx<R> eo = anchor<DIM, R>(to, an[i], nm);
               cplx<R> en = anchor<DIM, R>(tn, an[i], nm);
+              float segE = 0.f, segJ = 0.f;
 #pragma unroll
               for (int j = 0; j < SEG; ++j) {
                 const WT2 wa = *reinterpret_cast<const WT2*>(reinterpret_cast<const char*>(ltab) +
@@ -1109,8 +1145,8 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                 const R ux = fma(c2q, R(rv[i][j].x), dx), uy = fma(c2q, R(rv[i][j].y), dy);
                 const R t = fma(ux, dx, uy * dy);
                 if (MIXED) {
-                  accE32.add(float(wa.x) * float(t));
-                  if (JAS) accJ32.add(float(wa.y) * float(t));
+                  segE = fmaf(float(wa.x), float(t), segE);
+                  if (JAS) segJ = fmaf(float(wa.y), float(t), segJ);
                 } else {
                   accE64 = fma(double(wa.x), double(t), accE64);
                   if (JAS) accJ64 = fma(double(wa.y), double(t), accJ64);
@@ -1122,12 +1158,16 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                 eo = cmul(eo, uo);
                 en = cmul(en, un);
               }
+              if (MIXED) {
+                accE32.add(segE);
+                if (JAS) accJ32.add(segJ);
+              }
             }
           }
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
           if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO>(xn, xo, k, ps, pq, lpos, lq, n, S);
+          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO>(xn, xo, k, ps, pq, lpos, lq, n, S, S->p64, S->p32);
         }
         if (acc) {
           if ((k % NT) == tid) {  // the owner moves its particle
@@ -1353,6 +1393,8 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   o = up16(o + size_t(ch) * DIM * 8);
   L.xo = uint32_t(o);
   o = up16(o + size_t(ch) * DIM * 8);
+  L.c2q = uint32_t(o);
+  o = up16(o + size_t(ch) * 8);
   L.part = uint32_t(o);
   o = up16(o + size_t(ch) * NW * 8 * 8);
   L.k = uint32_t(o);
@@ -1548,6 +1590,11 @@ int dev_arch(char* buf, int len) {
   if (e != hipSuccess) return int(e);
   std::snprintf(buf, size_t(len), "%s", prop.gcnArchName);
   return 0;
+}
+
+int dev_copy(void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToDevice);
+  return e == hipSuccess ? 0 : int(e);
 }
 
 int dev_memset(void* p, int value, size_t bytes) {

@@ -1103,8 +1103,12 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   const std::string key = tune_key(b);
   int t = 0, c = 0, g = 0;
   if (cache_path && cache_lookup(cache_path, key, &t, &c, &g)) return ewald_batch_set_tuning(b, t, c, g);
-  // probe proposals: every move rejected, so the walkers' state is left as it was
+  // probe: proposals spread over each cell, every other move accepted, run on
+  // a copy of the walkers' state (which is left as it was)
   const int W = b->lb.n_walkers, dim = b->lb.dim;
+  std::vector<uint8_t> ha(size_t(n_moves) * W);
+  for (int m = 0; m < n_moves; ++m)
+    for (int w = 0; w < W; ++w) ha[size_t(m) * W + w] = uint8_t(m & 1);
   std::vector<int32_t> hk(size_t(n_moves) * W);
   std::vector<double> hp(size_t(n_moves) * W * dim);
   for (int m = 0; m < n_moves; ++m)
@@ -1122,18 +1126,20 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
         hp[i * dim + d] = x;
       }
     }
-  void *dk = nullptr, *dp = nullptr, *da = nullptr, *dd = nullptr;
+  void *dk = nullptr, *dp = nullptr, *da = nullptr, *dd = nullptr, *ds = nullptr;
   auto release = [&]() {
-    for (void* p : {dk, dp, da, dd})
+    for (void* p : {dk, dp, da, dd, ds})
       if (p) dev_free(p);
   };
-  int rc = dev_alloc(&dk, hk.size() * 4);
+  int rc = dev_alloc(&ds, b->state_bytes);
+  if (!rc) rc = dev_copy(ds, state, b->state_bytes);
+  if (!rc) rc = dev_alloc(&dk, hk.size() * 4);
   if (!rc) rc = dev_alloc(&dp, hp.size() * 8);
   if (!rc) rc = dev_alloc(&da, size_t(n_moves) * W);
   if (!rc) rc = dev_alloc(&dd, size_t(n_moves) * W * 8);
   if (!rc) rc = dev_upload(dk, hk.data(), hk.size() * 4);
   if (!rc) rc = dev_upload(dp, hp.data(), hp.size() * 8);
-  if (!rc) rc = dev_memset(da, 0, size_t(n_moves) * W);
+  if (!rc) rc = dev_upload(da, ha.data(), ha.size());
   if (rc) {
     release();
     return launch_status(rc, "autotune set-up");
@@ -1155,7 +1161,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
         plan_run(L, &p);
         if (!p.fused) continue;
         float ms = 0.f;
-        rc = time_run(L, static_cast<char*>(state), n_moves, static_cast<int32_t*>(dk), static_cast<double*>(dp),
+        rc = time_run(L, static_cast<char*>(ds), n_moves, static_cast<int32_t*>(dk), static_cast<double*>(dp),
                       static_cast<uint8_t*>(da), static_cast<double*>(dd), stream, 2, &ms);
         if (rc) {
           release();

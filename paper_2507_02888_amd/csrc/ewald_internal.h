@@ -170,5 +170,6 @@ int dev_current(int* device);
 const char* dev_error_string(int code);
 int dev_arch(char* buf, int len);  // the current device's architecture name
 int dev_memset(void* p, int value, size_t bytes);
+int dev_copy(void* dst, const void* src, size_t bytes);  // device to device, synchronous
 
 }  // namespace ewald

@@ -427,8 +427,10 @@ def test_tuning_shapes_agree(precision):
     assert t["fused"] == 1 and t["threads"] == 1024 and 1 <= t["chunk"] <= 64
     ref.run_energy()
     d0, j0 = ref.fused()
-    tol = 1e-12 if precision == FP64 else 1e-9
+    # FP64: rounding order only; FP32-mixed: per-thread FP32 partial sums
+    # differ with the shape, so the form's own per-delta bound applies
     scale = max(1.0, max(abs(x) for x in ref.energy.cpu().numpy()))
+    tol = 1e-12 * scale if precision == FP64 else 1e-5
     for threads, chunk, general in ((512, 0, 0), (1024, 5, 0), (512, 1, 1), (0, 64, 1)):
         c = Case(5, W, S, precision, walker_start=w0, refresh_every=3)
         c.batch.set_tuning(threads, chunk, general)
@@ -438,8 +440,8 @@ def test_tuning_shapes_agree(precision):
             assert t["chunk"] == chunk if chunk <= 8 else 8 <= t["chunk"] <= chunk
         c.run_energy()
         d, j = c.fused()
-        assert np.max(np.abs(d - d0)) <= tol * scale, (threads, chunk, general)
-        assert np.max(np.abs(j - j0)) <= tol * scale
+        assert np.max(np.abs(d - d0)) <= tol, (threads, chunk, general)
+        assert np.max(np.abs(j - j0)) <= tol
         for w in range(W):
             assert np.max(np.abs(c.batch.walker_rho(w) - ref.batch.walker_rho(w))) <= 1e-9
     with pytest.raises(ew.EwaldError):
@@ -449,8 +451,8 @@ def test_tuning_shapes_agree(precision):
 
 
 def test_autotune_keeps_state_and_caches(tmp_path, oracle_lib):
-    """The autotuner probes with rejected moves (state unchanged), stores its
-    choice in the cache file and re-applies it from there; the tuned sweep
+    """The autotuner probes on a copy of the state (the walkers' state is
+    unchanged), stores its choice in the cache file and re-applies it from there; the tuned sweep
     still matches the oracle."""
     W, S, w0 = SUBSETS[2]
     say("[autotune] cfg=2")

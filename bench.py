@@ -54,9 +54,10 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(form: str):
+def traffic_from_profiles(form: str, shape: dict):
     """Measured HBM bytes per fused launch from the committed counter summary,
-    or None when it is missing or was taken on another kernel source."""
+    or None when it is missing, was taken on another kernel source, or on
+    another launch shape (workgroup size, frame)."""
     p = os.path.join(ROOT, "profiles", "k_run_n1024_counters.json")
     if not os.path.exists(p):
         return None
@@ -65,6 +66,8 @@ def traffic_from_profiles(form: str):
     except Exception:
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if d.get("threads") != shape.get("threads") or d.get("general_frame", 0) != shape.get("general_frame"):
         return None
     f = d.get("forms", {}).get(form)
     return None if f is None else f.get("hbm_bytes_per_launch")
@@ -231,7 +234,7 @@ def main():
         flops_run = deltas_per_step * algorithmic_flops_per_delta(n_g, n_part) + \
             r["n_refresh"] * algorithmic_flops_per_rebuild(n_g, n_part)
         achieved = flops_run / (r["run_ms"] * 1e-3) / 1e12
-        traffic = traffic_from_profiles(form)
+        traffic = traffic_from_profiles(form, r["tuning"])
         r["value"] = deltas_per_step / (r["ms_per_step"] * 1e-3)
         r["roofline"] = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
                              frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=traffic,

@@ -35,9 +35,12 @@ struct cplx {
   R x, y;
 };
 
+// Complex product with the FMAs written out, so that every kernel and launch
+// shape rounds it the same way (left to itself the compiler may contract
+// either product of each component).
 template <typename R>
 __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  return {fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
 }
 
 __device__ __forceinline__ int unpack_n(uint32_t p, int d) {
@@ -509,6 +512,20 @@ __device__ __forceinline__ void fill_row(cplx<R>* row, double s, int nm) {
   }
 }
 
+// Coordinate r of (a, b) read as one array of 2 DIM values, with the index
+// resolved by selects (a runtime index into register arrays would place
+// them in scratch memory).
+template <int DIM>
+__device__ __forceinline__ double pick_coord(const double (&a)[DIM], const double (&b)[DIM], int r) {
+  double v = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    v = r == d ? a[d] : v;
+    v = r == DIM + d ? b[d] : v;
+  }
+  return v;
+}
+
 // First phase of segment `pn` from the tables.
 template <int DIM, typename R>
 __device__ __forceinline__ cplx<R> anchor(const cplx<R>* tab, uint32_t pn, int nm) {
@@ -517,6 +534,29 @@ __device__ __forceinline__ cplx<R> anchor(const cplx<R>* tab, uint32_t pn, int n
   if (DIM == 3) e = cmul(e, tab_at(tab, 2, nm + unpack_n(pn, 2), tbl));
   return e;
 }
+
+// Phases along a segment: e_0 = the anchor, e_1 = e_0 u, then the three-term
+// recurrence e_{j+1} = 2 Re(u) e_j - e_{j-1} for u = exp(2 pi i s_last)
+// (|u| = 1): two FMAs per slot instead of a complex multiply.  Rounding errors
+// grow at most linearly along the segment (they propagate through Chebyshev
+// polynomials of the second kind, |U_j(cos phi)| <= j + 1).
+template <typename R>
+struct SegWalk {
+  cplx<R> cur, prev;
+  R c2;
+  cplx<R> u;
+  __device__ __forceinline__ SegWalk(cplx<R> a, cplx<R> u_) : cur(a), prev(a), c2(R(2) * u_.x), u(u_) {}
+  __device__ __forceinline__ void step(int j) {  // e_j -> e_{j+1}; j is a compile-time index in unrolled loops
+    if (j == 0) {
+      prev = cur;
+      cur = cmul(cur, u);
+    } else {
+      const cplx<R> nx = {fma(c2, cur.x, -prev.x), fma(c2, cur.y, -prev.y)};
+      prev = cur;
+      cur = nx;
+    }
+  }
+};
 
 // Rebuild rho over the segments segs[i] = seg0 + i * NT (i < NS) of one
 // walker in FP64: rho = rho_fix + sum_p q_p exp(i G.r_p), particles taken
@@ -566,14 +606,16 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
         if (seg0 + i * NT < nseg) {
-          cplx<double> e0 = anchor<DIM, double>(t0, an[i], nm);
-          cplx<double> e1 = anchor<DIM, double>(t1, an[i], nm);
+          SegWalk<double> w0(anchor<DIM, double>(t0, an[i], nm), u0);
+          SegWalk<double> w1(anchor<DIM, double>(t1, an[i], nm), u1);
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
-            acc[i][j].x = fma(q1, e1.x, fma(q0, e0.x, acc[i][j].x));
-            acc[i][j].y = fma(q1, e1.y, fma(q0, e0.y, acc[i][j].y));
-            e0 = cmul(e0, u0);
-            e1 = cmul(e1, u1);
+            acc[i][j].x = fma(q1, w1.cur.x, fma(q0, w0.cur.x, acc[i][j].x));
+            acc[i][j].y = fma(q1, w1.cur.y, fma(q0, w0.cur.y, acc[i][j].y));
+            if (j + 1 < SEG) {
+              w0.step(j);
+              w1.step(j);
+            }
           }
         }
       }
@@ -592,7 +634,7 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
 // the cell has one (ORTHO); rho is built from the fractional positions just
 // stored in the walker state.
 template <int DIM, int SPT, int PD, bool ORTHO>
-__global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ systems,
+__global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys* __restrict__ systems,
                                                   const DevWalker* __restrict__ walkers,
                                                   const double* __restrict__ pos, char* __restrict__ state,
                                                   double* __restrict__ energy, double* __restrict__ jastrow,
@@ -706,7 +748,7 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
 // Move delta: dE and dJ of moving particle k to new_pos; records the pending
 // move.  rho is streamed from the state once (slot-planar, coalesced).
 template <int DIM, bool MIXED, int PD>
-__global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ systems,
+__global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ systems,
                                                  const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                                  const int32_t* __restrict__ kk, const double* __restrict__ new_pos,
                                                  double* __restrict__ delta, double* __restrict__ djas, int lds_tab) {
@@ -759,7 +801,7 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
     for (int d = 0; d < DIM; ++d) so[d] = spos[k * DIM + d];
   }
   const double qk = S->mobile_q[k];
-  if (tid < 2 * DIM) fill_row<R>(to + tid * tbl, tid < DIM ? so[tid] : sn[tid - DIM], nm);  // to, then tn
+  if (tid < 2 * DIM) fill_row<R>(to + tid * tbl, pick_coord<DIM>(so, sn, tid), nm);  // to, then tn
   __syncthreads();
 
   // reciprocal space: t(G) = 2 q Re(conj(rho) d) + q^2 |d|^2, d = e_new - e_old
@@ -783,11 +825,11 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
       snxt[j] = S->slot_shell[g2];
     }
     const uint32_t pn = S->seg_n[s];
-    cplx<R> eo = anchor<DIM, R>(to, pn, nm);
-    cplx<R> en = anchor<DIM, R>(tn, pn, nm);
+    SegWalk<R> wo(anchor<DIM, R>(to, pn, nm), uo), wn(anchor<DIM, R>(tn, pn, nm), un);
     float segE = 0.f, segJ = 0.f;  // mixed form: FP32 sums per segment, compensated across segments
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
+      const cplx<R> eo = wo.cur, en = wn.cur;
       const size_t g = size_t(j) * nseg + s;
       R wg, aj;
       if (wlds) {
@@ -808,8 +850,10 @@ __global__ __launch_bounds__(BLOCK) void k_delta(const DevSys* __restrict__ syst
         accE64 = fma(double(wg), double(t), accE64);
         if (ja) accJ64 = fma(double(aj), double(t), accJ64);
       }
-      eo = cmul(eo, uo);
-      en = cmul(en, un);
+      if (j + 1 < SEG) {
+        wo.step(j);
+        wn.step(j);
+      }
     }
     if (MIXED) {
       accE32.add(segE);
@@ -866,7 +910,7 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
       so[d] = spos[pk * DIM + d];
       sn[d] = hdr->pending_s[d];
     }
-    if (tid < 2 * DIM) fill_row<R>(to + tid * tbl, tid < DIM ? so[tid] : sn[tid - DIM], nm);  // to, then tn
+    if (tid < 2 * DIM) fill_row<R>(to + tid * tbl, pick_coord<DIM>(so, sn, tid), nm);  // to, then tn
   }
   __syncthreads();  // every thread has read the header and pending position
   if (acc) {
@@ -878,15 +922,16 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
 #pragma unroll
       for (int j = 0; j < SEG; ++j) r[j] = rho2[size_t(j) * nseg + s];
       const uint32_t pn = S->seg_n[s];
-      cplx<R> eo = anchor<DIM, R>(to, pn, nm);
-      cplx<R> en = anchor<DIM, R>(tn, pn, nm);
+      SegWalk<R> wo(anchor<DIM, R>(to, pn, nm), uo), wn(anchor<DIM, R>(tn, pn, nm), un);
 #pragma unroll
       for (int j = 0; j < SEG; ++j) {
-        r[j].x += double(q * (en.x - eo.x));
-        r[j].y += double(q * (en.y - eo.y));
+        r[j].x += double(q * (wn.cur.x - wo.cur.x));
+        r[j].y += double(q * (wn.cur.y - wo.cur.y));
         rho2[size_t(j) * nseg + s] = r[j];
-        eo = cmul(eo, uo);
-        en = cmul(en, un);
+        if (j + 1 < SEG) {
+          wo.step(j);
+          wn.step(j);
+        }
       }
     }
   }
@@ -1134,11 +1179,11 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
 #pragma unroll
           for (int i = 0; i < SPT; ++i) {
             if (tid + i * NT < nseg) {
-              cplx<R> eo = anchor<DIM, R>(to, an[i], nm);
-              cplx<R> en = anchor<DIM, R>(tn, an[i], nm);
+              SegWalk<R> wo(anchor<DIM, R>(to, an[i], nm), uo), wn(anchor<DIM, R>(tn, an[i], nm), un);
               float segE = 0.f, segJ = 0.f;
 #pragma unroll
               for (int j = 0; j < SEG; ++j) {
+                const cplx<R> eo = wo.cur, en = wn.cur;
                 const WT2 wa = *reinterpret_cast<const WT2*>(reinterpret_cast<const char*>(ltab) +
                                                              ((shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu));
                 const R dx = en.x - eo.x, dy = en.y - eo.y;
@@ -1155,8 +1200,10 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                   rv[i][j].x += double(q * dx);
                   rv[i][j].y += double(q * dy);
                 }
-                eo = cmul(eo, uo);
-                en = cmul(en, un);
+                if (j + 1 < SEG) {
+                  wo.step(j);
+                  wn.step(j);
+                }
               }
               if (MIXED) {
                 accE32.add(segE);

@@ -158,6 +158,63 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_
     return out
 
 
+def other_workload(cfg_id: int, precision: int, steps: int = 2):
+    """A whole-workload sweep of one of the smaller configurations (energy plus
+    the fused sweep, autotuned launch shape): deltas/s and the fused kernel's
+    VALU fraction by the same algorithmic count."""
+    import torch
+    from paper_2507_02888_amd import ewald as ew
+    from paper_2507_02888_amd import workloads as wl
+    cfg = wl.config(cfg_id)
+    b = wl.make_batch(cfg)
+    mixed = precision == ew.EWALD_FP32_MIXED
+    K = cfg.refresh_every if mixed else 0
+    systems = [ew.System(sm, precision=precision, refresh_every=K, jastrow_a=b.jastrow_a) for sm in cfg.systems]
+    batch = ew.Batch(systems, b.walker_sys, device="cuda")
+    dev = "cuda"
+    pos = torch.tensor(b.pos, device=dev)
+    k = torch.tensor(b.k, device=dev)
+    newp = torch.tensor(b.new_pos, device=dev)
+    acc = torch.tensor(b.accept, device=dev)
+    W, S = b.walkers, b.steps
+    energy = torch.zeros(W, dtype=torch.float64, device=dev)
+    delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
+    batch.energy(pos, energy)
+    batch.autotune(n_moves=max(32, 2 * K) if K else 32)
+    stream = torch.cuda.current_stream()
+    run_ms, step_ms = [], []
+    for it in range(steps + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        batch.energy(pos, energy)
+        e1.record(stream)
+        batch.run_moves(k, newp, acc, delta)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if it:  # the first pass warms up
+            run_ms.append(e1.elapsed_time(e2))
+            step_ms.append(e0.elapsed_time(e2))
+    assert np.all(np.isfinite(delta.cpu().numpy()))
+    flops = 0.0
+    for w in range(W):
+        si = int(b.walker_sys[w])
+        sm, ng = cfg.systems[si], systems[si].info["n_g"]
+        n_tot = sm.n_mobile + sm.n_fixed
+        flops += S * (ng * FLOP_PER_G_DELTA + 2 * (n_tot - 1) * FLOP_PER_PAIR_DELTA)
+        if K:
+            flops += (int(b.accept[:, w].sum()) // K) * sm.n_mobile * ng * FLOP_PER_G_PARTICLE
+    rm, sm_ = float(np.mean(run_ms)), float(np.mean(step_ms))
+    out = dict(config=cfg_id, form="mixed" if mixed else "fp64", walkers=W, moves=S,
+               particles=sorted({int(x.n_mobile) for x in cfg.systems}), refresh_every=K,
+               deltas_per_s=round(W * S / (sm_ * 1e-3), 1), run_deltas_per_s=round(W * S / (rm * 1e-3), 1),
+               launch_ms=round(rm, 4), frac=round(flops / (rm * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4),
+               launch_shape=batch.tuning())
+    batch.close()
+    for x in systems:
+        x.close()
+    return out
+
+
 def cpu_baseline(cfg, n_walkers: int, threads: int):
     import oracle
     from paper_2507_02888_amd import workloads as wl
@@ -189,6 +246,8 @@ def main():
                     help="fixed fused-kernel workgroup size instead of the autotuner's choice")
     ap.add_argument("--k-sweep", default="128,256,512,0",
                     help="further refresh intervals K timed for the mixed form (0 = no rebuild); empty to skip")
+    ap.add_argument("--other", default="2,3,4",
+                    help="smaller configurations also timed (both forms), reported under other_workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -261,6 +320,12 @@ def main():
                               frac=round(flops_run / (r["run_ms"] * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4),
                               drift_max=r["drift_max"] if k_alt > 0 else None))
 
+    others = []
+    if args.other:
+        for cid in [int(x) for x in args.other.split(",")]:
+            for prec in (ew.EWALD_FP32_MIXED, ew.EWALD_FP64):
+                others.append(other_workload(cid, prec))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, args.cpu_walkers, args.cpu_threads)
@@ -294,6 +359,8 @@ def main():
         line["mixed_refresh_sweep"] = [dict(refresh_every=K, run_deltas_per_s=round(deltas_per_step / (k_main["run_ms"] * 1e-3), 1),
                                             launch_ms=round(k_main["run_ms"], 4), rebuilds=k_main["n_refresh"],
                                             frac=k_main["roofline"]["frac"], drift_max=k_main["drift_max"])] + sweep
+    if others:
+        line["other_workloads"] = others
     if "fp64" in results and "mixed" in results:
         f = results["fp64"]
         line["fp64"] = {"value": round(f["value"], 1), "unit": "deltas/s", "ms_per_step": round(f["ms_per_step"], 3),

@@ -1017,7 +1017,7 @@ struct RunLds {
   int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
 };
 
-template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD, bool ORTHO>
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO>
 __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
@@ -1027,7 +1027,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   using WT = R;          // the mixed form multiplies weights with FP32 terms
   using WT2 = cplx<WT>;  // (weight, Jastrow coefficient)
   constexpr int NW = NT / 64;
-  constexpr int PPR = NT >= 1024 ? 1 : 2;  // own particles per thread held in registers
+  // PPR: own particles per thread held in registers (particles j = t + c NT, c < PPR)
   extern __shared__ __align__(16) char lds[];
   const DevWalker W = walkers[blockIdx.x];
   const int w = W.id, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1478,9 +1478,9 @@ struct RunArgs {
   RunPlan* plan;  // non-null: resolve the launch shape only, launch nothing
 };
 
-template <int DIM, bool MIXED, int NT, int SPT, bool JAS, int PD, bool ORTHO>
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO>
 int run_inst(const LaunchBatch& b, const RunArgs& a) {
-  auto* kern = k_run<DIM, MIXED, NT, SPT, JAS, PD, ORTHO>;
+  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO>;
   static const int per_cu = blocks_per_cu(kern, NT);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
   RunLds L{};
@@ -1491,7 +1491,7 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
   while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT>(b, --ch, L);
   if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
   if (a.plan) {
-    *a.plan = RunPlan{1, NT, SPT, ch, ORTHO ? 0 : 1, int(lds), per_cu};
+    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu};
     return 0;
   }
   if (int rc = allow_lds(kern, lds)) return rc;
@@ -1505,7 +1505,10 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
 // shapes available for that count (0: the default, the first listed).
 //   <= 256 segments: (256, 1)      <= 512: (256, 2)
 //   <= 1024: (1024, 1) or (512, 2)  <= 2048: (512, 4)
-int run_shape(int max_n_seg, int threads, int* nt, int* spt) {
+// Particles per thread in registers: 1 when the largest walker has at most
+// NT particles (always with 1024 threads, where larger walkers' remaining
+// particles are read from LDS), else 2.
+int run_shape(int max_n_seg, int max_particles, int threads, int* nt, int* spt, int* ppr) {
   struct Shape { int lim, nt, spt; };
   static const Shape shapes[] = {{256, 256, 1}, {512, 256, 2}, {1024, 1024, 1}, {1024, 512, 2}, {2048, 512, 4}};
   int lim = 0;
@@ -1516,6 +1519,7 @@ int run_shape(int max_n_seg, int threads, int* nt, int* spt) {
     if (threads == 0 || threads == sh.nt) {
       *nt = sh.nt;
       *spt = sh.spt;
+      *ppr = (sh.nt >= 1024 || max_particles <= sh.nt) ? 1 : 2;
       return 1;
     }
   }
@@ -1525,15 +1529,17 @@ int run_shape(int max_n_seg, int threads, int* nt, int* spt) {
 template <int DIM, bool MIXED, bool JAS, int PD, bool ORTHO>
 int run_jp(const LaunchBatch& b, const RunArgs& a) {
   static_assert(RUN_CHUNK <= 256, "staging uses one thread per move");
-  int nt = 0, spt = 0;
-  if (!run_shape(b.max_n_seg, b.run_threads, &nt, &spt)) return RUN_NO_FIT;
-#define EW_RUN(NT, SPT) \
-  if (nt == NT && spt == SPT) return run_inst<DIM, MIXED, NT, SPT, JAS, PD, ORTHO>(b, a)
-  EW_RUN(256, 1);
-  EW_RUN(256, 2);
-  EW_RUN(1024, 1);
-  EW_RUN(512, 2);
-  EW_RUN(512, 4);
+  int nt = 0, spt = 0, ppr = 0;
+  if (!run_shape(b.max_n_seg, b.max_particles, b.run_threads, &nt, &spt, &ppr)) return RUN_NO_FIT;
+#define EW_RUN(NT, SPT, PPR) \
+  if (nt == NT && spt == SPT && ppr == PPR) return run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO>(b, a)
+  EW_RUN(256, 1, 1);
+  EW_RUN(256, 1, 2);
+  EW_RUN(256, 2, 1);
+  EW_RUN(256, 2, 2);
+  EW_RUN(1024, 1, 1);
+  EW_RUN(512, 2, 2);
+  EW_RUN(512, 4, 2);
 #undef EW_RUN
   return RUN_NO_FIT;
 }
@@ -1599,8 +1605,8 @@ void plan_run(const LaunchBatch& b, RunPlan* plan) {
 }
 
 bool run_threads_valid(int max_n_seg, int threads) {
-  int nt, spt;
-  return threads == 0 || run_shape(max_n_seg, threads, &nt, &spt);
+  int nt, spt, ppr;
+  return threads == 0 || run_shape(max_n_seg, 0, threads, &nt, &spt, &ppr);
 }
 
 int time_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,

@@ -140,6 +140,7 @@ struct RunPlan {
   int fused;          // 1 if the fused kernel runs
   int threads;        // workgroup size
   int spt;            // segments per thread
+  int ppr;            // particles per thread held in registers
   int chunk;          // moves per chunk
   int general_frame;  // 1 = general minimum-image reduction
   int lds_bytes;

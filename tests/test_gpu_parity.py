@@ -481,3 +481,37 @@ def test_autotune_keeps_state_and_caches(tmp_path, oracle_lib):
         r = c.oracle(oracle_lib, w)
         scale = max(abs(r["energy0"]), e_scale(c.system(w)))
         assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_uneven_batch_fused_graph(precision):
+    """The uneven batch (walkers of 64/216/512 electrons plus ions in one
+    launch): the fused sweep, autotuned, captured once in a HIP graph and
+    replayed three times, equals three eager sweeps over the same proposals."""
+    W, S = 24, 12
+    say(f"[uneven graph] cfg=4 precision={precision}")
+    eager = Case(4, W, S, precision, refresh_every=3)
+    assert len(set(int(x) for x in eager.b.walker_sys)) == 3
+    eager.run_energy()
+    eager.batch.autotune(n_moves=8)
+    ref = [eager.fused() for _ in range(3)]
+    g_case = Case(4, W, S, precision, refresh_every=3)
+    g_case.run_energy()
+    g_case.batch.set_tuning(**{k: v for k, v in eager.batch.tuning().items() if k != "fused"})
+    d = torch.zeros((S, W), dtype=torch.float64, device="cuda")
+    dj = torch.zeros_like(d)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        g_case.batch.run_moves(g_case.k, g_case.new_pos, g_case.accept, d, dj)
+    torch.cuda.synchronize()
+    tol = 1e-12 if precision == FP64 else 1e-9
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        scale = max(1.0, float(np.max(np.abs(ref[r][0]))))
+        assert np.max(np.abs(d.cpu().numpy() - ref[r][0])) <= tol * scale, r
+        assert np.max(np.abs(dj.cpu().numpy() - ref[r][1])) <= tol * scale, r
+    for w in range(W):
+        assert np.array_equal(g_case.batch.walker_positions(w), eager.batch.walker_positions(w))
+        assert g_case.batch.walker_header(w)["n_accepts"] == eager.batch.walker_header(w)["n_accepts"]

@@ -1075,6 +1075,25 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
     geo_pos<DIM, ORTHO>(sj, S, ps[c]);
     pq[c] = j < n ? S->mobile_q[j] : 0.0;
   }
+  // Workgroups of up to 512 threads (256 vector registers per lane) hold the
+  // pair-polynomial coefficients in vector registers for the whole sweep
+  // (loaded with a lane-varying index, so they are not taken for scalars);
+  // that leaves the scalar registers to the loop state, which otherwise
+  // spills into vector-register lanes.  With 1024 threads they stay scalar.
+  constexpr int PF = PD == 16 ? 12 : 22;
+  constexpr bool CV = NT <= 512;
+  double cf64[CV ? PD + 1 : 1];
+  float cf32[CV ? PF + 1 : 1];
+  if (CV) {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+#pragma unroll
+    for (int i = 0; i <= (CV ? PD : 0); ++i) cf64[i] = S->p64[i + z];
+#pragma unroll
+    for (int i = 0; i <= (CV ? PF : 0); ++i) cf32[i] = S->p32[i + z];
+  }
+  const double* c64 = CV ? cf64 : S->p64;
+  const float* c32 = CV ? cf32 : S->p32;
   uint32_t an[SPT];
   cplx<double> rv[SPT][SEG];
   uint32_t shp[SPT][SEG / 2];  // two 16-bit shell-table byte offsets per register
@@ -1214,7 +1233,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
           if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO>(xn, xo, k, ps, pq, lpos, lq, n, S, S->p64, S->p32);
+          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO>(xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32);
         }
         if (acc) {
           if ((k % NT) == tid) {  // the owner moves its particle

@@ -152,18 +152,71 @@ __device__ __forceinline__ double min_r2(const double* a, const double* b, const
 // each axis into the box (|x_d| <= box_d / 2), then for each coset offset by
 // half box sides along the axes in its mask the nearest image is at
 // sum_mask (box_d/2 - |x_d|)^2 + sum_other x_d^2 = |x|^2 + cc - sum_mask box_d |x_d|.
-template <int DIM>
-__device__ __forceinline__ double min_r2_ortho(const double* a, const double* b, const DevSys* __restrict__ S) {
+// The frame constants a pair distance needs (box, its inverse, the first
+// coset); further cosets are read from the system tables.
+struct FrameK {
+  double box[3], ibox[3], cw0[3], cc0;
+};
+
+__device__ __forceinline__ FrameK frame_k(const DevSys* __restrict__ S) {
+  FrameK K;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    K.box[d] = S->box[d];
+    K.ibox[d] = S->ibox[d];
+    K.cw0[d] = S->cw[0][d];
+  }
+  K.cc0 = S->cc[0];
+  return K;
+}
+
+// The same constants loaded with a lane-varying index, so that the compiler
+// keeps them in vector registers (for kernels with vector registers to
+// spare, where scalar registers are the scarce ones).
+__device__ __forceinline__ FrameK frame_k_vector(const DevSys* __restrict__ S) {
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  FrameK K;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    K.box[d] = S->box[d + z];
+    K.ibox[d] = S->ibox[d + z];
+    K.cw0[d] = S->cw[0][d + z];
+  }
+  K.cc0 = S->cc[z];
+  return K;
+}
+
+// USEK: the box and first coset from K (vector registers) rather than from
+// the system tables.
+template <int DIM, bool USEK>
+__device__ __forceinline__ double min_r2_ortho(const double* a, const double* b, const DevSys* __restrict__ S,
+                                               const FrameK& K) {
   double x[DIM], r0sq = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     x[d] = a[d] - b[d];
-    x[d] = fma(-S->box[d], rint(x[d] * S->ibox[d]), x[d]);
+    x[d] = fma(-(USEK ? K.box[d] : S->box[d]), rint(x[d] * (USEK ? K.ibox[d] : S->ibox[d])), x[d]);
     r0sq = fma(x[d], x[d], r0sq);
   }
   double r2 = r0sq;
   const int nc = S->n_coset;
-  for (int c = 0; c < nc; ++c) {
+  if (!USEK) {
+    for (int c = 0; c < nc; ++c) {
+      double t = r0sq + S->cc[c];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) t = fma(-S->cw[c][d], fabs(x[d]), t);
+      r2 = fmin(r2, t);
+    }
+    return r2;
+  }
+  if (nc > 0) {
+    double t = r0sq + K.cc0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) t = fma(-K.cw0[d], fabs(x[d]), t);
+    r2 = fmin(r2, t);
+  }
+  for (int c = 1; c < nc; ++c) {
     double t = r0sq + S->cc[c];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) t = fma(-S->cw[c][d], fabs(x[d]), t);
@@ -186,10 +239,10 @@ __device__ __forceinline__ void frame_coords(const double* s, const DevSys* __re
 
 // Minimum-image r^2 between two positions given in the kernel's geometry:
 // frame coordinates (ORTHO) or fractional coordinates (general cells).
-template <int DIM, bool ORTHO>
+template <int DIM, bool ORTHO, bool USEK = false>
 __device__ __forceinline__ double image_r2(const double* a, const double* b, const DevSys* __restrict__ S,
-                                           int n_cand) {
-  if (ORTHO) return min_r2_ortho<DIM>(a, b, S);
+                                           int n_cand, const FrameK& K) {
+  if (ORTHO) return min_r2_ortho<DIM, USEK>(a, b, S, K);
   return min_r2<DIM>(a, b, S, n_cand);
 }
 
@@ -367,12 +420,12 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
 // charges in registers (ps, pq); it alone updates them when they move.  Particles beyond
 // PPR NT (larger systems than the launch shape covers) are read from the LDS
 // copy, again only by their owner t = j mod NT.
-template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO>
+template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO, bool USEK>
 __device__ __forceinline__ double real_move_own(const double* sn, const double* so, int k,
                                                 const double (&ps)[PPR][DIM], const double (&pq)[PPR],
                                                 const double* lpos, const double* lq, int n,
                                                 const DevSys* __restrict__ S, const double* c64,
-                                                const float* c32) {
+                                                const float* c32, const FrameK& K) {
   PairAcc<MIXED, PD> pr(S, c64, c32);
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
@@ -382,8 +435,8 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
     for (int c = 0; c < PPR; ++c) {
       const int j = threadIdx.x + c * NT;
       const bool ok = j < n && j != k;
-      r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, ps[c], S, n_cand) : rc2;
-      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, ps[c], S, n_cand) : rc2;
+      r2[2 * c] = ok ? image_r2<DIM, ORTHO, USEK>(sn, ps[c], S, n_cand, K) : rc2;
+      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO, USEK>(so, ps[c], S, n_cand, K) : rc2;
       qq[2 * c] = pq[c];
       qq[2 * c + 1] = -pq[c];
     }
@@ -394,8 +447,8 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
     const bool ok = j != k;
     double xj[DIM];
     geo_pos<DIM, ORTHO>(lpos + j * DIM, S, xj);
-    r2[0] = ok ? image_r2<DIM, ORTHO>(sn, xj, S, n_cand) : rc2;
-    r2[1] = ok ? image_r2<DIM, ORTHO>(so, xj, S, n_cand) : rc2;
+    r2[0] = ok ? image_r2<DIM, ORTHO, USEK>(sn, xj, S, n_cand, K) : rc2;
+    r2[1] = ok ? image_r2<DIM, ORTHO, USEK>(so, xj, S, n_cand, K) : rc2;
     qq[0] = lq[j];
     qq[1] = -lq[j];
     pr.template add<2>(qq, r2, S);
@@ -411,8 +464,8 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
       double sj[DIM];
       geo_pos<DIM, ORTHO>(S->fixed_s + jj * DIM, S, sj);
       const double qj = ok ? S->fixed_q[jj] : 0.0;
-      r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, sj, S, n_cand) : rc2;
-      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, sj, S, n_cand) : rc2;
+      r2[2 * c] = ok ? image_r2<DIM, ORTHO, USEK>(sn, sj, S, n_cand, K) : rc2;
+      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO, USEK>(so, sj, S, n_cand, K) : rc2;
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
     }
@@ -706,6 +759,7 @@ __global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys
   // real space: each unordered mobile pair once (pair i with i+1..i+(n-1)/2
   // cyclically, plus i+n/2 for i < n/2 when n is even), then every fixed ion
   PairAcc<false, PD> pr(S, S->p64, S->p32);
+  const FrameK K = frame_k(S);
   const double rc2 = S->rc2;
   const int half = (n - 1) / 2;
   for (int i = tid; i < n; i += BLOCK) {
@@ -731,7 +785,7 @@ __global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys
           geo_pos<DIM, ORTHO>(S->fixed_s + (fix ? m - n_mob : 0) * DIM, S, sj);
         }
         qq[c] = mob ? qi * lq[j] : fix ? qi * S->fixed_q[m - n_mob] : 0.0;
-        r2[c] = (mob || fix) ? image_r2<DIM, ORTHO>(si, sj, S, n_cand) : rc2;
+        r2[c] = (mob || fix) ? image_r2<DIM, ORTHO>(si, sj, S, n_cand, K) : rc2;
       }
       pr.template add<4>(qq, r2, S);
     }
@@ -1094,6 +1148,8 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   }
   const double* c64 = CV ? cf64 : S->p64;
   const float* c32 = CV ? cf32 : S->p32;
+  FrameK fk{};  // with 1024 threads the frame constants are read where they are used
+  if (CV) fk = frame_k_vector(S);
   uint32_t an[SPT];
   cplx<double> rv[SPT][SEG];
   uint32_t shp[SPT][SEG / 2];  // two 16-bit shell-table byte offsets per register
@@ -1233,7 +1289,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
           if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO>(xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32);
+          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO, CV>(xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32, fk);
         }
         if (acc) {
           if ((k % NT) == tid) {  // the owner moves its particle

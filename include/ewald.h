@@ -138,12 +138,12 @@ ewald_status ewald_sys_tables(const ewald_sys *sys, int32_t *n, double *weight, 
  * [n][3]; `cand` may be NULL to query the count. */
 ewald_status ewald_sys_candidates(const ewald_sys *sys, int *n_cand, double *cand);
 
-/* The minimum-image geometry the fused kernel uses for this cell.  If the
- * lattice contains mutually orthogonal vectors spanning a sublattice of index
- * m <= 4 whose cosets are offset by half box sides (simple-cubic, bcc, fcc and
+/* The minimum-image geometry the kernels use for this cell.  If the lattice
+ * contains mutually orthogonal vectors spanning a sublattice of index m <= 2
+ * whose nonzero coset is offset by half box sides (simple-cubic, bcc, fcc and
  * hexagonal cells), *index = m and box[0..dim) receives their lengths
  * (bohr): pair distances are then reduced per axis in that box with one
- * extra image check per coset.  Otherwise *index = 0 and the general
+ * extra image check for the coset.  Otherwise *index = 0 and the general
  * reduction (fractional rint plus the candidate offsets above) is used.
  * Either pointer may be NULL; box must hold 3 doubles.  Status: E_ARG. */
 ewald_status ewald_sys_geometry(const ewald_sys *sys, int *index, double *box);

@@ -149,13 +149,17 @@ __device__ __forceinline__ double min_r2(const double* a, const double* b, const
 }
 
 // Squared minimum-image distance in the orthogonal-sublattice frame: wrap
-// each axis into the box (|x_d| <= box_d / 2), then for each coset offset by
-// half box sides along the axes in its mask the nearest image is at
-// sum_mask (box_d/2 - |x_d|)^2 + sum_other x_d^2 = |x|^2 + cc - sum_mask box_d |x_d|.
-// The frame constants a pair distance needs (box, its inverse, the first
-// coset); further cosets are read from the system tables.
+// each axis into the box (|x_d| <= box_d / 2); the nearest image in the coset
+// offset by half box sides along the axes of its mask is at
+// sum_mask (box_d/2 - |x_d|)^2 + sum_other x_d^2 = |x|^2 + cc - sum_d cw_d |x_d|
+// (cw_d = box_d on the mask, else 0; cc = +inf when the frame has no coset,
+// so the expression needs no branch).
+// The constants a pair distance and a pair term need, by value: for kernels
+// with vector registers to spare they are loaded once into vector registers
+// (frame_k_vector), elsewhere read from the system tables (frame_k).
 struct FrameK {
-  double box[3], ibox[3], cw0[3], cc0;
+  double box[3], ibox[3], cw[3], cc;
+  double rc2, alpha, scale;  // r_cut^2, alpha, 2 / r_cut^2 (pair potential)
 };
 
 __device__ __forceinline__ FrameK frame_k(const DevSys* __restrict__ S) {
@@ -164,15 +168,17 @@ __device__ __forceinline__ FrameK frame_k(const DevSys* __restrict__ S) {
   for (int d = 0; d < 3; ++d) {
     K.box[d] = S->box[d];
     K.ibox[d] = S->ibox[d];
-    K.cw0[d] = S->cw[0][d];
+    K.cw[d] = S->cw[0][d];
   }
-  K.cc0 = S->cc[0];
+  K.cc = S->cc[0];
+  K.rc2 = S->rc2;
+  K.alpha = S->alpha;
+  K.scale = S->poly_scale;
   return K;
 }
 
-// The same constants loaded with a lane-varying index, so that the compiler
-// keeps them in vector registers (for kernels with vector registers to
-// spare, where scalar registers are the scarce ones).
+// Loaded with a lane-varying index, so that the compiler keeps them in vector
+// registers rather than in the scarcer scalar ones.
 __device__ __forceinline__ FrameK frame_k_vector(const DevSys* __restrict__ S) {
   int z = 0;
   asm volatile("" : "+v"(z));
@@ -181,48 +187,28 @@ __device__ __forceinline__ FrameK frame_k_vector(const DevSys* __restrict__ S) {
   for (int d = 0; d < 3; ++d) {
     K.box[d] = S->box[d + z];
     K.ibox[d] = S->ibox[d + z];
-    K.cw0[d] = S->cw[0][d + z];
+    K.cw[d] = S->cw[0][d + z];
   }
-  K.cc0 = S->cc[z];
+  K.cc = S->cc[z];
+  K.rc2 = (&S->rc2)[z];
+  K.alpha = (&S->alpha)[z];
+  K.scale = (&S->poly_scale)[z];
   return K;
 }
 
-// USEK: the box and first coset from K (vector registers) rather than from
-// the system tables.
-template <int DIM, bool USEK>
-__device__ __forceinline__ double min_r2_ortho(const double* a, const double* b, const DevSys* __restrict__ S,
-                                               const FrameK& K) {
+template <int DIM>
+__device__ __forceinline__ double min_r2_ortho(const double* a, const double* b, const FrameK& K) {
   double x[DIM], r0sq = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     x[d] = a[d] - b[d];
-    x[d] = fma(-(USEK ? K.box[d] : S->box[d]), rint(x[d] * (USEK ? K.ibox[d] : S->ibox[d])), x[d]);
+    x[d] = fma(-K.box[d], rint(x[d] * K.ibox[d]), x[d]);
     r0sq = fma(x[d], x[d], r0sq);
   }
-  double r2 = r0sq;
-  const int nc = S->n_coset;
-  if (!USEK) {
-    for (int c = 0; c < nc; ++c) {
-      double t = r0sq + S->cc[c];
+  double t = r0sq + K.cc;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) t = fma(-S->cw[c][d], fabs(x[d]), t);
-      r2 = fmin(r2, t);
-    }
-    return r2;
-  }
-  if (nc > 0) {
-    double t = r0sq + K.cc0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) t = fma(-K.cw0[d], fabs(x[d]), t);
-    r2 = fmin(r2, t);
-  }
-  for (int c = 1; c < nc; ++c) {
-    double t = r0sq + S->cc[c];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) t = fma(-S->cw[c][d], fabs(x[d]), t);
-    r2 = fmin(r2, t);
-  }
-  return r2;
+  for (int d = 0; d < DIM; ++d) t = fma(-K.cw[d], fabs(x[d]), t);
+  return fmin(r0sq, t);
 }
 
 // Coordinates of a fractional position in the orthogonal-sublattice frame.
@@ -239,10 +225,10 @@ __device__ __forceinline__ void frame_coords(const double* s, const DevSys* __re
 
 // Minimum-image r^2 between two positions given in the kernel's geometry:
 // frame coordinates (ORTHO) or fractional coordinates (general cells).
-template <int DIM, bool ORTHO, bool USEK = false>
+template <int DIM, bool ORTHO>
 __device__ __forceinline__ double image_r2(const double* a, const double* b, const DevSys* __restrict__ S,
                                            int n_cand, const FrameK& K) {
-  if (ORTHO) return min_r2_ortho<DIM, USEK>(a, b, S, K);
+  if (ORTHO) return min_r2_ortho<DIM>(a, b, K);
   return min_r2<DIM>(a, b, S, n_cand);
 }
 
@@ -296,12 +282,13 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
 template <int PD>
 struct PairAcc<false, PD> {
   double s = 0.0;
-  const double* __restrict__ c;  // the polynomial coefficients (system tables, or an LDS copy)
-  __device__ __forceinline__ PairAcc(const DevSys* __restrict__ S, const double* c64, const float*) : c(c64) {}
+  const double* __restrict__ c;  // the polynomial coefficients (system tables, or registers)
+  const FrameK& K;
+  __device__ __forceinline__ PairAcc(const double* c64, const float*, const FrameK& k) : c(c64), K(k) {}
   template <int NE>
-  __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE], const DevSys* __restrict__ S) {
+  __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE]) {
     double ir[NE], t[NE], p[NE];
-    const double scale = S->poly_scale;
+    const double scale = K.scale;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       ir[e] = rsqrt_pos(r2[e]);
@@ -314,7 +301,7 @@ struct PairAcc<false, PD> {
 #pragma unroll
       for (int e = 0; e < NE; ++e) p[e] = fma(p[e], t[e], ci);
     }
-    const double rc2 = S->rc2, alpha = S->alpha;
+    const double rc2 = K.rc2, alpha = K.alpha;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       const double phi = fma(-alpha, p[e], ir[e]);
@@ -329,13 +316,14 @@ struct PairAcc<true, PD> {
   static constexpr int PF = PD == 16 ? 12 : 22;
   double inv = 0.0;
   Kahan erfpart;
-  const float* __restrict__ c;  // the FP32 polynomial coefficients (system tables, or an LDS copy)
-  __device__ __forceinline__ PairAcc(const DevSys* __restrict__ S, const double*, const float* c32) : c(c32) {}
+  const float* __restrict__ c;  // the FP32 polynomial coefficients (system tables, or registers)
+  const FrameK& K;
+  __device__ __forceinline__ PairAcc(const double*, const float* c32, const FrameK& k) : c(c32), K(k) {}
   template <int NE>
-  __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE], const DevSys* __restrict__ S) {
+  __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE]) {
     float t[NE], p[NE];
     double ir[NE];
-    const float scale = float(S->poly_scale);
+    const float scale = float(K.scale);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       ir[e] = rsqrt_pos(r2[e]);
@@ -348,8 +336,8 @@ struct PairAcc<true, PD> {
 #pragma unroll
       for (int e = 0; e < NE; ++e) p[e] = fmaf(p[e], t[e], ci);
     }
-    const double rc2 = S->rc2;
-    const float alpha = float(S->alpha);
+    const double rc2 = K.rc2;
+    const float alpha = float(K.alpha);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       const double qe = r2[e] < rc2 ? q[e] : 0.0;
@@ -371,7 +359,8 @@ template <int DIM, bool MIXED, int PD, int NT>
 __device__ __forceinline__ double real_move(const double* sn, const double* so, int k, const double* pos,
                                             const double* q, int n, const DevSys* __restrict__ S) {
   constexpr int PPR = NT >= 1024 ? 1 : 2;
-  PairAcc<MIXED, PD> pr(S, S->p64, S->p32);
+  const FrameK K = frame_k(S);
+  PairAcc<MIXED, PD> pr(S->p64, S->p32, K);
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
   for (int j0 = threadIdx.x; j0 < n; j0 += PPR * NT) {
@@ -390,7 +379,7 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
     }
-    pr.template add<2 * PPR>(qq, r2, S);
+    pr.template add<2 * PPR>(qq, r2);
   }
   const int nfix = S->n_fixed;
   for (int j0 = threadIdx.x; j0 < nfix; j0 += PPR * NT) {
@@ -409,7 +398,7 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
     }
-    pr.template add<2 * PPR>(qq, r2, S);
+    pr.template add<2 * PPR>(qq, r2);
   }
   return pr.value();
 }
@@ -420,13 +409,13 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
 // charges in registers (ps, pq); it alone updates them when they move.  Particles beyond
 // PPR NT (larger systems than the launch shape covers) are read from the LDS
 // copy, again only by their owner t = j mod NT.
-template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO, bool USEK>
+template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO>
 __device__ __forceinline__ double real_move_own(const double* sn, const double* so, int k,
                                                 const double (&ps)[PPR][DIM], const double (&pq)[PPR],
                                                 const double* lpos, const double* lq, int n,
                                                 const DevSys* __restrict__ S, const double* c64,
                                                 const float* c32, const FrameK& K) {
-  PairAcc<MIXED, PD> pr(S, c64, c32);
+  PairAcc<MIXED, PD> pr(c64, c32, K);
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
   {
@@ -435,23 +424,23 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
     for (int c = 0; c < PPR; ++c) {
       const int j = threadIdx.x + c * NT;
       const bool ok = j < n && j != k;
-      r2[2 * c] = ok ? image_r2<DIM, ORTHO, USEK>(sn, ps[c], S, n_cand, K) : rc2;
-      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO, USEK>(so, ps[c], S, n_cand, K) : rc2;
+      r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, ps[c], S, n_cand, K) : rc2;
+      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, ps[c], S, n_cand, K) : rc2;
       qq[2 * c] = pq[c];
       qq[2 * c + 1] = -pq[c];
     }
-    pr.template add<2 * PPR>(qq, r2, S);
+    pr.template add<2 * PPR>(qq, r2);
   }
   for (int j = threadIdx.x + PPR * NT; j < n; j += NT) {
     double qq[2], r2[2];
     const bool ok = j != k;
     double xj[DIM];
     geo_pos<DIM, ORTHO>(lpos + j * DIM, S, xj);
-    r2[0] = ok ? image_r2<DIM, ORTHO, USEK>(sn, xj, S, n_cand, K) : rc2;
-    r2[1] = ok ? image_r2<DIM, ORTHO, USEK>(so, xj, S, n_cand, K) : rc2;
+    r2[0] = ok ? image_r2<DIM, ORTHO>(sn, xj, S, n_cand, K) : rc2;
+    r2[1] = ok ? image_r2<DIM, ORTHO>(so, xj, S, n_cand, K) : rc2;
     qq[0] = lq[j];
     qq[1] = -lq[j];
-    pr.template add<2>(qq, r2, S);
+    pr.template add<2>(qq, r2);
   }
   const int nfix = S->n_fixed;
   for (int j0 = threadIdx.x; j0 < nfix; j0 += 2 * NT) {
@@ -464,12 +453,12 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
       double sj[DIM];
       geo_pos<DIM, ORTHO>(S->fixed_s + jj * DIM, S, sj);
       const double qj = ok ? S->fixed_q[jj] : 0.0;
-      r2[2 * c] = ok ? image_r2<DIM, ORTHO, USEK>(sn, sj, S, n_cand, K) : rc2;
-      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO, USEK>(so, sj, S, n_cand, K) : rc2;
+      r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, sj, S, n_cand, K) : rc2;
+      r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, sj, S, n_cand, K) : rc2;
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
     }
-    pr.template add<4>(qq, r2, S);
+    pr.template add<4>(qq, r2);
   }
   return pr.value();
 }
@@ -758,8 +747,8 @@ __global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys
 
   // real space: each unordered mobile pair once (pair i with i+1..i+(n-1)/2
   // cyclically, plus i+n/2 for i < n/2 when n is even), then every fixed ion
-  PairAcc<false, PD> pr(S, S->p64, S->p32);
   const FrameK K = frame_k(S);
+  PairAcc<false, PD> pr(S->p64, S->p32, K);
   const double rc2 = S->rc2;
   const int half = (n - 1) / 2;
   for (int i = tid; i < n; i += BLOCK) {
@@ -787,7 +776,7 @@ __global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys
         qq[c] = mob ? qi * lq[j] : fix ? qi * S->fixed_q[m - n_mob] : 0.0;
         r2[c] = (mob || fix) ? image_r2<DIM, ORTHO>(si, sj, S, n_cand, K) : rc2;
       }
-      pr.template add<4>(qq, r2, S);
+      pr.template add<4>(qq, r2);
     }
   }
   double v[3] = {pr.value(), er, ej};
@@ -1148,7 +1137,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
   }
   const double* c64 = CV ? cf64 : S->p64;
   const float* c32 = CV ? cf32 : S->p32;
-  FrameK fk{};  // with 1024 threads the frame constants are read where they are used
+  FrameK fk{};  // with 1024 threads the constants are read where they are used
   if (CV) fk = frame_k_vector(S);
   uint32_t an[SPT];
   cplx<double> rv[SPT][SEG];
@@ -1289,7 +1278,8 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
           if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO, CV>(xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32, fk);
+          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO>(xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32,
+                                                                CV ? fk : frame_k(S));
         }
         if (acc) {
           if ((k % NT) == tid) {  // the owner moves its particle

@@ -71,14 +71,14 @@ double wrap01(double x) {
   return f >= 1.0 ? 0.0 : f;
 }
 
-// Orthogonal sublattice of small index whose cosets sit at half box sides
+// Orthogonal sublattice of index 1 or 2 whose coset sits at half box sides
 // (simple-cubic, bcc, fcc and hexagonal cells have one).  Integer vectors
 // with coefficients in [-2, 2] are searched for dim mutually orthogonal
-// lattice vectors v_d = n_d A of the smallest index |det n| <= 4; the cosets of
-// the sublattice they span are found by reducing lattice points into the box
-// spanned by them, and accepted only if every component of every coset offset
-// is 0 or half the box side.  Returns false if no such frame exists (the
-// kernels then use the general reduction with candidate images).
+// lattice vectors v_d = n_d A of the smallest index |det n| <= 2; the coset of
+// the sublattice they span is found by reducing lattice points into the box
+// spanned by them, and accepted only if every component of its offset is 0
+// or half the box side.  Returns false if no such frame exists (the kernels
+// then use the general reduction with candidate images).
 struct OrthoFrame {
   double F[9] = {0};    // x = s F (frame coordinates from fractional ones)
   double box[3] = {0};
@@ -110,7 +110,7 @@ bool ortho_frame(const double* A, int dim, OrthoFrame& out) {
   auto orth = [&](size_t i, size_t j) {
     return std::fabs(dot(vs[i], vs[j])) <= 1e-12 * std::sqrt(dot(vs[i], vs[i]) * dot(vs[j], vs[j]));
   };
-  int best_index = 5;
+  int best_index = 3;
   double best_len = INFINITY;
   size_t pick[3] = {0, 0, 0};
   const size_t nv = vs.size();
@@ -139,7 +139,7 @@ bool ortho_frame(const double* A, int dim, OrthoFrame& out) {
         pick[2] = k;
       }
     }
-  if (best_index > 4) return false;
+  if (best_index > 2) return false;
   double e[3][3] = {{0}};
   for (int d = 0; d < dim; ++d) {
     const auto& v = vs[pick[d]];
@@ -729,7 +729,8 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
     D.n_coset = of.n_coset;
     for (int c = 0; c < MAX_COSET; ++c) {
       for (int d = 0; d < 3; ++d) D.cw[c][d] = of.cw[c][d];
-      D.cc[c] = of.cc[c];
+      // an absent coset never gives the nearest image
+      D.cc[c] = c < of.n_coset ? of.cc[c] : HUGE_VAL;
     }
   }
   *out = S.release();

@@ -16,7 +16,7 @@ namespace ewald {
 constexpr int SEG = 4;            // G slots per segment: consecutive n along the last reduced index
 constexpr int BLOCK = 256;        // threads per workgroup of every kernel
 constexpr int MAX_CAND = 16;      // +-pairs of minimum-image candidate offsets
-constexpr int MAX_COSET = 3;      // nonzero cosets of an orthogonal sublattice (index <= 4)
+constexpr int MAX_COSET = 1;      // nonzero cosets of an orthogonal sublattice (index <= 2)
 constexpr int HDR_BYTES = 256;    // per-walker state header
 constexpr int MAX_SPT = 8;        // segments per thread held in registers (MAX_SEGMENTS / BLOCK)
 constexpr int TILE_P = 8;         // particles per phase-table tile when rebuilding rho
@@ -59,16 +59,17 @@ struct DevSys {
   double cand[MAX_CAND][4];  // (v_x, v_y, v_z, |v|^2) of one of each +-pair, rotated frame
   // Orthogonal-sublattice frame (ortho = 1): the lattice contains mutually
   // orthogonal vectors of lengths box[d] spanning a sublattice of index
-  // n_coset + 1 whose nonzero cosets are offset by half box sides.  Positions
-  // in this frame are x = s F; the minimum image is a per-axis wrap into the
-  // box plus, per coset c, |x|^2 + cc[c] - sum_d cw[c][d] |x_d|.
+  // n_coset + 1 <= 2 whose nonzero coset is offset by half box sides.
+  // Positions in this frame are x = s F; the minimum image is a per-axis wrap
+  // into the box and min(|x|^2, |x|^2 + cc - sum_d cw[d] |x_d|) (cc = +inf
+  // when there is no coset).
   int ortho;
   int n_coset;
   double F[9];
   double box[3];
   double ibox[3];
-  double cw[MAX_COSET][3];  // box[d] where coset c has a half-box offset along d, else 0
-  double cc[MAX_COSET];     // sum over those d of box[d]^2 / 4
+  double cw[MAX_COSET][3];  // box[d] where the coset has a half-box offset along d, else 0
+  double cc[MAX_COSET];     // sum over those d of box[d]^2 / 4 (+inf: no coset)
   // erf(alpha r)/(alpha r) = sum_i p64[i] t^i for r < r_cut (p32: FP32 copy of lower accuracy)
   double p64[POLY_MAX + 1];
   float p32[POLY32_MAX + 1];

@@ -1056,6 +1056,7 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
 struct RunLds {
   // byte offsets into dynamic LDS; positions start at 0
   uint32_t q, red, wtab, ctab, sn, so, xn, xo, c2q, part, k, acc, cnt;
+  uint32_t rcopy;  // 0, or the LDS copy of the running rho during a rebuild
   int ch;     // moves per chunk
   int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
 };
@@ -1323,15 +1324,23 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
       if (djas) djas[idx] = j;
     }
     if (MIXED && K > 0 && counter >= K) {  // uniform: rebuild rho in FP64 between chunks
+      __syncthreads();  // the chunk's outputs have been read from the staging area
+      // keep the running rho for the drift check: in LDS when the layout has
+      // room for it, else in the walker state
+      cplx<double>* rc = reinterpret_cast<cplx<double>*>(lds + L.rcopy);
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
         const int s = tid + i * NT;
         if (s < nseg)
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
-            const size_t g = size_t(j) * nseg + s;
-            rho[2 * g] = rv[i][j].x;
-            rho[2 * g + 1] = rv[i][j].y;
+            if (L.rcopy) {
+              rc[(i * NT + tid) * SEG + j] = rv[i][j];
+            } else {
+              const size_t g = size_t(j) * nseg + s;
+              rho[2 * g] = rv[i][j].x;
+              rho[2 * g + 1] = rv[i][j].y;
+            }
           }
       }
       rebuild_rho<DIM, SPT, NT>(rv, an, tid, S, lpos, lq, n, tabs, L.rtile);
@@ -1342,8 +1351,14 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
         if (s < nseg)
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
-            const size_t g = size_t(j) * nseg + s;
-            dm = fmax(dm, fmax(fabs(rv[i][j].x - rho[2 * g]), fabs(rv[i][j].y - rho[2 * g + 1])));
+            cplx<double> old;
+            if (L.rcopy) {
+              old = rc[(i * NT + tid) * SEG + j];
+            } else {
+              const size_t g = size_t(j) * nseg + s;
+              old = {rho[2 * g], rho[2 * g + 1]};
+            }
+            dm = fmax(dm, fmax(fabs(rv[i][j].x - old.x), fabs(rv[i][j].y - old.y)));
           }
       }
       for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, 64));
@@ -1480,7 +1495,7 @@ constexpr int RUN_NO_FIT = -1;                 // the fused kernel's LDS does no
 size_t up16(size_t x) { return (x + 15) & ~size_t(15); }
 
 // LDS layout of the fused kernel for a chunk of ch moves; returns the total bytes.
-template <int DIM, bool MIXED, int NT>
+template <int DIM, bool MIXED, int NT, int SPT>
 size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int NW = NT / 64;
@@ -1517,6 +1532,17 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   o = up16(o + size_t(ch) * 4);
   L.ch = ch;
   L.rtile = int(std::min<size_t>(ctab / rpart, 64));
+  // Between chunks the tables and the staging area are free: the mixed form's
+  // rebuild keeps the running rho there (for the drift check) when it fits
+  // beside tiles of at least TILE_P particles, instead of a round trip
+  // through HBM.
+  L.rcopy = 0;
+  const size_t rcopy = size_t(SPT) * NT * SEG * sizeof(cplx<double>);
+  const size_t region = o - L.ctab;
+  if (MIXED && region >= rcopy + size_t(TILE_P) * rpart) {
+    L.rcopy = uint32_t((o - rcopy) & ~size_t(15));
+    L.rtile = int(std::min<size_t>((L.rcopy - L.ctab) / rpart, 64));
+  }
   return o;
 }
 
@@ -1550,10 +1576,10 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
   RunLds L{};
   int ch = b.run_chunk > 0 ? std::min(b.run_chunk, RUN_CHUNK) : RUN_CHUNK;
-  size_t lds = run_layout<DIM, MIXED, NT>(b, ch, L);
+  size_t lds = run_layout<DIM, MIXED, NT, SPT>(b, ch, L);
   if (b.run_chunk <= 0)
-    while (lds > budget && ch > 8) lds = run_layout<DIM, MIXED, NT>(b, --ch, L);
-  while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT>(b, --ch, L);
+    while (lds > budget && ch > 8) lds = run_layout<DIM, MIXED, NT, SPT>(b, --ch, L);
+  while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT, SPT>(b, --ch, L);
   if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
   if (a.plan) {
     *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu};

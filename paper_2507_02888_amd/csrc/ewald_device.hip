@@ -680,7 +680,7 @@ __global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys
                                                   const DevWalker* __restrict__ walkers,
                                                   const double* __restrict__ pos, char* __restrict__ state,
                                                   double* __restrict__ energy, double* __restrict__ jastrow,
-                                                  int lds_pos) {
+                                                  int lds_pos, int tile) {
   extern __shared__ double smem[];
   const DevWalker W = walkers[blockIdx.x];
   const int w = W.id, tid = threadIdx.x;
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys
     an[i] = s < nseg ? S->seg_n[s] : 0u;
   }
   cplx<double> acc[SPT][SEG];
-  rebuild_rho<DIM, SPT>(acc, an, tid, S, spos, lq, n, tabs);
+  rebuild_rho<DIM, SPT>(acc, an, tid, S, spos, lq, n, tabs, tile);
   double er = 0.0, ej = 0.0;
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
@@ -1423,16 +1423,38 @@ int allow_lds(F* kernel, size_t bytes) {
 
 int even(int x) { return (x + 1) & ~1; }
 
+constexpr size_t RUN_LDS_BUDGET = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int RUN_NO_FIT = -1;                 // the fused kernel's LDS does not fit: use the per-step kernels
+
+// Workgroups of this kernel that fit on one CU by registers (4 SIMDs, 512
+// VGPRs per lane each); the fused kernel sizes its LDS so as not to lower it.
+template <typename F>
+int blocks_per_cu(F* kernel, int nt) {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)) != hipSuccess || a.numRegs <= 0) return 1;
+  const int vgpr = (a.numRegs + 7) & ~7;
+  const int waves_per_simd = std::min(8, 512 / vgpr);
+  return std::max(1, 4 * waves_per_simd / (nt / 64));
+}
+
+
 template <int DIM, int SPT, int PD, bool ORTHO>
 int energy_inst(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
                 void* stream) {
   const int lds_pos = even(b.max_particles);
-  const size_t tab = size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>);
-  const size_t lds = size_t(lds_pos) * (DIM + 1) * 8 + 16 * 8 + tab;
+  const size_t rpart = size_t(DIM) * (2 * b.max_nm + 1) * sizeof(cplx<double>);
+  const size_t fixed = size_t(lds_pos) * (DIM + 1) * 8 + 16 * 8;
   auto* kern = k_energy<DIM, SPT, PD, ORTHO>;
+  // rebuild tiles as large as LDS allows without lowering the workgroups per
+  // CU that registers allow (fewer barriers per particle), at most 64
+  static const int per_cu = blocks_per_cu(kern, BLOCK);
+  const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
+  int tile = budget > fixed ? int(std::min<size_t>((budget - fixed) / rpart, 64)) : 0;
+  tile = std::max(tile, TILE_P);
+  const size_t lds = fixed + size_t(tile) * rpart;
   if (int rc = allow_lds(kern, lds)) return rc;
   hipLaunchKernelGGL(kern, dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), b.d_sys, b.d_walk, pos, state,
-                     energy, jastrow, lds_pos);
+                     energy, jastrow, lds_pos, tile);
   return last_launch();
 }
 
@@ -1489,8 +1511,6 @@ int accept_dim(const LaunchBatch& b, char* state, const uint8_t* accept, void* s
   return last_launch();
 }
 
-constexpr size_t RUN_LDS_BUDGET = 160 * 1024;  // LDS per workgroup on gfx950
-constexpr int RUN_NO_FIT = -1;                 // the fused kernel's LDS does not fit: use the per-step kernels
 
 size_t up16(size_t x) { return (x + 15) & ~size_t(15); }
 
@@ -1546,16 +1566,6 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   return o;
 }
 
-// Workgroups of this kernel that fit on one CU by registers (4 SIMDs, 512
-// VGPRs per lane each); the fused kernel sizes its LDS so as not to lower it.
-template <typename F>
-int blocks_per_cu(F* kernel, int nt) {
-  hipFuncAttributes a{};
-  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)) != hipSuccess || a.numRegs <= 0) return 1;
-  const int vgpr = (a.numRegs + 7) & ~7;
-  const int waves_per_simd = std::min(8, 512 / vgpr);
-  return std::max(1, 4 * waves_per_simd / (nt / 64));
-}
 
 struct RunArgs {
   char* state;

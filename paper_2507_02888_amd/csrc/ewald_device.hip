@@ -676,7 +676,7 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
 // the cell has one (ORTHO); rho is built from the fractional positions just
 // stored in the walker state.
 template <int DIM, int SPT, int PD, bool ORTHO>
-__global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys* __restrict__ systems,
+__global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ systems,
                                                   const DevWalker* __restrict__ walkers,
                                                   const double* __restrict__ pos, char* __restrict__ state,
                                                   double* __restrict__ energy, double* __restrict__ jastrow,
@@ -747,8 +747,16 @@ __global__ __launch_bounds__(BLOCK, SPT >= 8 ? 1 : 3) void k_energy(const DevSys
 
   // real space: each unordered mobile pair once (pair i with i+1..i+(n-1)/2
   // cyclically, plus i+n/2 for i < n/2 when n is even), then every fixed ion
-  const FrameK K = frame_k(S);
-  PairAcc<false, PD> pr(S->p64, S->p32, K);
+  // the pair loop's constants in vector registers (see frame_k_vector)
+  const FrameK K = frame_k_vector(S);
+  double cf64[PD + 1];
+  {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+#pragma unroll
+    for (int i = 0; i <= PD; ++i) cf64[i] = S->p64[i + z];
+  }
+  PairAcc<false, PD> pr(cf64, S->p32, K);
   const double rc2 = S->rc2;
   const int half = (n - 1) / 2;
   for (int i = tid; i < n; i += BLOCK) {

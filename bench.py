@@ -90,7 +90,7 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_
     if threads:
         batch.set_tuning(threads=threads)
     else:
-        batch.autotune(n_moves=max(32, 2 * K) if precision == ew.EWALD_FP32_MIXED and K > 0 else 32)
+        batch.autotune(n_moves=max(64, 2 * K) if precision == ew.EWALD_FP32_MIXED and K > 0 else 64)
     tuning = batch.tuning()
     W, S = b.walkers, b.steps
     energy = torch.zeros(W, dtype=torch.float64, device=dev)
@@ -180,7 +180,7 @@ def other_workload(cfg_id: int, precision: int, steps: int = 2):
     energy = torch.zeros(W, dtype=torch.float64, device=dev)
     delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
     batch.energy(pos, energy)
-    batch.autotune(n_moves=max(32, 2 * K) if K else 32)
+    batch.autotune(n_moves=max(64, 2 * K) if K else 64)
     stream = torch.cuda.current_stream()
     run_ms, step_ms = [], []
     for it in range(steps + 1):

@@ -554,6 +554,19 @@ __device__ __forceinline__ void fill_row(cplx<R>* row, double s, int nm) {
   }
 }
 
+// The same row in FP64, every entry multiplied by `scale` (a particle's charge
+// carried by its first row, so that the products of its rows include it).
+__device__ __forceinline__ void fill_row_scaled(cplx<double>* row, double s, int nm, double scale) {
+  const cplx<double> u = turn(s);
+  cplx<double> c = {1.0, 0.0};
+  row[nm] = {scale, 0.0};
+  for (int m = 1; m <= nm; ++m) {
+    c = (m & 7) == 0 ? turn(double(m) * s) : cmul(c, u);
+    row[nm + m] = {c.x * scale, c.y * scale};
+    row[nm - m] = {c.x * scale, -c.y * scale};
+  }
+}
+
 // Coordinate r of (a, b) read as one array of 2 DIM values, with the index
 // resolved by selects (a runtime index into register arrays would place
 // them in scratch memory).
@@ -603,15 +616,24 @@ struct SegWalk {
 // Rebuild rho over the segments segs[i] = seg0 + i * NT (i < NS) of one
 // walker in FP64: rho = rho_fix + sum_p q_p exp(i G.r_p), particles taken
 // `tile` at a time through LDS phase tables (tabs: tile * DIM * (2nm+1)).
-// `pos` may point to global or LDS memory.  All NT threads must call it.
+// The first row of each particle's tables carries its charge, so a segment's
+// anchor already holds q_p exp(i G.r_p) and the walk along the segment (a
+// linear recurrence) keeps the factor.  Two particles per pass give two
+// independent chains; with one segment per thread the next pass's table
+// entries are read while the current pass computes.  `pos` and `q` may point
+// to global or LDS memory.  All NT threads must call it.
 template <int DIM, int NS, int NT = BLOCK>
 __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[NS], int seg0,
                             const DevSys* __restrict__ S, const double* pos, const double* q, int n,
                             cplx<double>* tabs, int tile = TILE_P) {
-  const int nseg = S->n_seg, nm = S->nm, tbl = 2 * nm + 1;
+  constexpr bool PIPE = false;
+  const int nseg = S->n_seg, nm = S->nm, tbl = 2 * nm + 1, pstride = DIM * tbl;
+  int off[NS][DIM];  // the anchor's entry in each row of one particle's tables
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int s = seg0 + i * NT;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) off[i][d] = d * tbl + nm + unpack_n(an[i], d);
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
       if (s < nseg) {
@@ -622,42 +644,91 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
       }
     }
   }
+  auto entries = [&](int i, int p, cplx<double> (&e)[DIM]) {
+    const cplx<double>* t = tabs + p * pstride;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) e[d] = t[off[i][d]];
+  };
+  auto product = [](const cplx<double> (&e)[DIM]) {
+    cplx<double> v = cmul(e[0], e[1]);
+    if (DIM == 3) v = cmul(v, e[DIM - 1]);
+    return v;
+  };
   for (int p0 = 0; p0 < n; p0 += tile) {
     const int np = min(tile, n - p0);
-    for (int e = threadIdx.x; e < np * DIM; e += NT)  // row e: particle e / DIM, dimension e % DIM
-      fill_row<double>(tabs + e * tbl, pos[p0 * DIM + e], nm);
+    for (int e = threadIdx.x; e < np * DIM; e += NT) {  // row e: particle e / DIM, dimension e % DIM
+      const int pp = e / DIM;
+      fill_row_scaled(tabs + e * tbl, pos[p0 * DIM + e], nm, e == pp * DIM ? q[p0 + pp] : 1.0);
+    }
     __syncthreads();
-    // the charge and step phase exp(2 pi i s_last) of particle p0 + l sit in
-    // lane l of every wave (tiles hold at most 64 particles); the passes
-    // below take them from there into scalar registers, so that the LDS
-    // serves only the per-lane table entries
+    // the step phase exp(2 pi i s_last) of particle p0 + l sits in lane l of
+    // every wave (tiles hold at most 64 particles); the passes below take it
+    // from there into scalar registers, so that the LDS serves only the
+    // per-lane table entries
     const int lane = threadIdx.x & 63;
-    const double lq_ = lane < np ? q[p0 + lane] : 0.0;
     const cplx<double> lu_ =
-        lane < np ? tab_at(tabs + lane * DIM * tbl, DIM - 1, nm + 1, tbl) : cplx<double>{1.0, 0.0};
-    // two particles per pass: independent chains for latency hiding (an odd
-    // tile's last pass pairs the particle with itself at zero charge)
-    for (int p = 0; p < np; p += 2) {
-      const bool two = p + 1 < np;
-      const int p1 = two ? p + 1 : p;
-      const cplx<double>* t0 = tabs + p * DIM * tbl;
-      const cplx<double>* t1 = tabs + p1 * DIM * tbl;
-      const double q0 = lane_value(lq_, p), q1 = two ? lane_value(lq_, p1) : 0.0;
+        lane < np ? tab_at(tabs + lane * pstride, DIM - 1, nm + 1, tbl) : cplx<double>{1.0, 0.0};
+    const int npair = np >> 1;
+    // one pass: the pair (p, p + 1) with the entries a (particle p) and b
+    auto pass = [&](int i, int p, const cplx<double> (&a)[DIM], const cplx<double> (&b)[DIM]) {
+      if (seg0 + i * NT < nseg) {
+        const cplx<double> u0 = {lane_value(lu_.x, p), lane_value(lu_.y, p)};
+        const cplx<double> u1 = {lane_value(lu_.x, p + 1), lane_value(lu_.y, p + 1)};
+        SegWalk<double> w0(product(a), u0), w1(product(b), u1);
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) {
+          acc[i][j].x = (acc[i][j].x + w0.cur.x) + w1.cur.x;
+          acc[i][j].y = (acc[i][j].y + w0.cur.y) + w1.cur.y;
+          if (j + 1 < SEG) {
+            w0.step(j);
+            w1.step(j);
+          }
+        }
+      }
+    };
+    if (PIPE) {
+      // two register sets: the entries of pair k + 1 are read while pair k
+      // is processed (pairs past the last read the last one again)
+      cplx<double> a0[DIM], b0[DIM], a1[DIM], b1[DIM];
+      if (npair > 0) {
+        entries(0, 0, a0);
+        entries(0, 1, b0);
+      }
+      for (int pr = 0; pr < npair; pr += 2) {
+        const int q1 = 2 * min(pr + 1, npair - 1), q2 = 2 * min(pr + 2, npair - 1);
+        entries(0, q1, a1);
+        entries(0, q1 + 1, b1);
+        pass(0, 2 * pr, a0, b0);
+        if (pr + 1 < npair) {
+          entries(0, q2, a0);
+          entries(0, q2 + 1, b0);
+          pass(0, 2 * pr + 2, a1, b1);
+        }
+      }
+    } else {
+      cplx<double> a0[DIM], b0[DIM];
+      for (int pr = 0; pr < npair; ++pr)
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          entries(i, 2 * pr, a0);
+          entries(i, 2 * pr + 1, b0);
+          pass(i, 2 * pr, a0, b0);
+        }
+    }
+    if (np & 1) {  // the tile's last particle, alone
+      const int p = np - 1;
       const cplx<double> u0 = {lane_value(lu_.x, p), lane_value(lu_.y, p)};
-      const cplx<double> u1 = {lane_value(lu_.x, p1), lane_value(lu_.y, p1)};
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
+        cplx<double> a0[DIM];
+        entries(i, p, a0);
         if (seg0 + i * NT < nseg) {
-          SegWalk<double> w0(anchor<DIM, double>(t0, an[i], nm), u0);
-          SegWalk<double> w1(anchor<DIM, double>(t1, an[i], nm), u1);
+          SegWalk<double> w0(product(a0), u0);
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
-            acc[i][j].x = fma(q1, w1.cur.x, fma(q0, w0.cur.x, acc[i][j].x));
-            acc[i][j].y = fma(q1, w1.cur.y, fma(q0, w0.cur.y, acc[i][j].y));
-            if (j + 1 < SEG) {
-              w0.step(j);
-              w1.step(j);
-            }
+            acc[i][j].x += w0.cur.x;
+            acc[i][j].y += w0.cur.y;
+            if (j + 1 < SEG) w0.step(j);
           }
         }
       }

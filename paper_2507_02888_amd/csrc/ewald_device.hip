@@ -539,6 +539,17 @@ __device__ __forceinline__ cplx<R> tab_at(const cplx<R>* tab, int row, int idx, 
   return tab[row * tbl + idx];
 }
 
+// FP64 entries as one 16-byte read (every table base in LDS is 16-byte aligned).
+__device__ __forceinline__ cplx<double> ld_entry(const cplx<double>* tab, int i) {
+  const double2 v = reinterpret_cast<const double2*>(tab)[i];
+  return {v.x, v.y};
+}
+
+template <>
+__device__ __forceinline__ cplx<double> tab_at<double>(const cplx<double>* tab, int row, int idx, int tbl) {
+  return ld_entry(tab, row * tbl + idx);
+}
+
 // One row, by one thread: powers of exp(2 pi i s) formed by repeated FP64
 // multiplication (the paper's buffered powers, Sec. 5.2), with an exact
 // restart every 8 powers so the rounding error stays below ~8 ulp; stored in R.
@@ -619,14 +630,13 @@ struct SegWalk {
 // The first row of each particle's tables carries its charge, so a segment's
 // anchor already holds q_p exp(i G.r_p) and the walk along the segment (a
 // linear recurrence) keeps the factor.  Two particles per pass give two
-// independent chains; with one segment per thread the next pass's table
-// entries are read while the current pass computes.  `pos` and `q` may point
-// to global or LDS memory.  All NT threads must call it.
+// independent chains; a pass reads all its table entries before its
+// arithmetic.  `pos` and `q` may point to global or LDS memory.  All NT
+// threads must call it.
 template <int DIM, int NS, int NT = BLOCK>
 __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[NS], int seg0,
                             const DevSys* __restrict__ S, const double* pos, const double* q, int n,
                             cplx<double>* tabs, int tile = TILE_P) {
-  constexpr bool PIPE = false;
   const int nseg = S->n_seg, nm = S->nm, tbl = 2 * nm + 1, pstride = DIM * tbl;
   int off[NS][DIM];  // the anchor's entry in each row of one particle's tables
 #pragma unroll
@@ -647,7 +657,7 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
   auto entries = [&](int i, int p, cplx<double> (&e)[DIM]) {
     const cplx<double>* t = tabs + p * pstride;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) e[d] = t[off[i][d]];
+    for (int d = 0; d < DIM; ++d) e[d] = ld_entry(t, off[i][d]);
   };
   auto product = [](const cplx<double> (&e)[DIM]) {
     cplx<double> v = cmul(e[0], e[1]);
@@ -686,35 +696,14 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
         }
       }
     };
-    if (PIPE) {
-      // two register sets: the entries of pair k + 1 are read while pair k
-      // is processed (pairs past the last read the last one again)
-      cplx<double> a0[DIM], b0[DIM], a1[DIM], b1[DIM];
-      if (npair > 0) {
-        entries(0, 0, a0);
-        entries(0, 1, b0);
-      }
-      for (int pr = 0; pr < npair; pr += 2) {
-        const int q1 = 2 * min(pr + 1, npair - 1), q2 = 2 * min(pr + 2, npair - 1);
-        entries(0, q1, a1);
-        entries(0, q1 + 1, b1);
-        pass(0, 2 * pr, a0, b0);
-        if (pr + 1 < npair) {
-          entries(0, q2, a0);
-          entries(0, q2 + 1, b0);
-          pass(0, 2 * pr + 2, a1, b1);
-        }
-      }
-    } else {
-      cplx<double> a0[DIM], b0[DIM];
-      for (int pr = 0; pr < npair; ++pr)
+    for (int pr = 0; pr < npair; ++pr)
 #pragma unroll
-        for (int i = 0; i < NS; ++i) {
-          entries(i, 2 * pr, a0);
-          entries(i, 2 * pr + 1, b0);
-          pass(i, 2 * pr, a0, b0);
-        }
-    }
+      for (int i = 0; i < NS; ++i) {
+        cplx<double> a0[DIM], b0[DIM];
+        entries(i, 2 * pr, a0);
+        entries(i, 2 * pr + 1, b0);
+        pass(i, 2 * pr, a0, b0);
+      }
     if (np & 1) {  // the tile's last particle, alone
       const int p = np - 1;
       const cplx<double> u0 = {lane_value(lu_.x, p), lane_value(lu_.y, p)};

@@ -550,6 +550,21 @@ __device__ __forceinline__ cplx<double> tab_at<double>(const cplx<double>* tab, 
   return ld_entry(tab, row * tbl + idx);
 }
 
+// FP32 entries as one 8-byte read.
+template <>
+__device__ __forceinline__ cplx<float> tab_at<float>(const cplx<float>* tab, int row, int idx, int tbl) {
+  const float2 v = reinterpret_cast<const float2*>(tab)[row * tbl + idx];
+  return {v.x, v.y};
+}
+
+// An entry at a byte offset into a 16-byte aligned LDS table, as one read.
+template <typename R>
+__device__ __forceinline__ cplx<R> ld_at_byte(const cplx<R>* tab, uint32_t byte_off) {
+  using V = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
+  const V v = *reinterpret_cast<const V*>(reinterpret_cast<const char*>(tab) + byte_off);
+  return {v.x, v.y};
+}
+
 // One row, by one thread: powers of exp(2 pi i s) formed by repeated FP64
 // multiplication (the paper's buffered powers, Sec. 5.2), with an exact
 // restart every 8 powers so the rounding error stays below ~8 ulp; stored in R.
@@ -1317,8 +1332,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
 #pragma unroll
               for (int j = 0; j < SEG; ++j) {
                 const cplx<R> eo = wo.cur, en = wn.cur;
-                const WT2 wa = *reinterpret_cast<const WT2*>(reinterpret_cast<const char*>(ltab) +
-                                                             ((shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu));
+                const WT2 wa = ld_at_byte(ltab, (shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu);
                 const R dx = en.x - eo.x, dy = en.y - eo.y;
                 const R ux = fma(c2q, R(rv[i][j].x), dx), uy = fma(c2q, R(rv[i][j].y), dy);
                 const R t = fma(ux, dx, uy * dy);

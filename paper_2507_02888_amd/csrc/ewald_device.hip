@@ -524,13 +524,6 @@ __device__ __forceinline__ double wave_sum_to_lane63(double v) {
   return v;
 }
 
-// The value lane l of the wave holds, in scalar registers (l uniform).
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
 // Phase tables: per dimension d one row of tbl = 2 nm + 1 complex entries,
 // exp(2 pi i n s_d) at [nm + n] for n = -nm..nm; a table of one position is
 // DIM rows.
@@ -581,15 +574,16 @@ __device__ __forceinline__ void fill_row(cplx<R>* row, double s, int nm) {
 }
 
 // The same row in FP64, every entry multiplied by `scale` (a particle's charge
-// carried by its first row, so that the products of its rows include it).
-__device__ __forceinline__ void fill_row_scaled(cplx<double>* row, double s, int nm, double scale) {
+// carried by its first row, so that the products of its rows include it),
+// entry k stored at row[k * stride].
+__device__ __forceinline__ void fill_row_scaled(cplx<double>* row, double s, int nm, double scale, int stride) {
   const cplx<double> u = turn(s);
   cplx<double> c = {1.0, 0.0};
-  row[nm] = {scale, 0.0};
+  row[nm * stride] = {scale, 0.0};
   for (int m = 1; m <= nm; ++m) {
     c = (m & 7) == 0 ? turn(double(m) * s) : cmul(c, u);
-    row[nm + m] = {c.x * scale, c.y * scale};
-    row[nm - m] = {c.x * scale, -c.y * scale};
+    row[(nm + m) * stride] = {c.x * scale, c.y * scale};
+    row[(nm - m) * stride] = {c.x * scale, -c.y * scale};
   }
 }
 
@@ -653,12 +647,15 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
                             const DevSys* __restrict__ S, const double* pos, const double* q, int n,
                             cplx<double>* tabs, int tile = TILE_P) {
   const int nseg = S->n_seg, nm = S->nm, tbl = 2 * nm + 1, pstride = DIM * tbl;
-  int off[NS][DIM];  // the anchor's entry in each row of one particle's tables
+  // tile layout: the tables of particles 2k and 2k + 1 interleaved entry by
+  // entry, so that a pass reads both particles' entries at one address and
+  // the next 16 bytes; entry (p, d, idx) at ((p / 2) pstride + d tbl + idx) 2 + p % 2
+  int off[NS][DIM];  // 2 x the anchor's entry in each row of one particle's tables
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int s = seg0 + i * NT;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) off[i][d] = d * tbl + nm + unpack_n(an[i], d);
+    for (int d = 0; d < DIM; ++d) off[i][d] = 2 * (d * tbl + nm + unpack_n(an[i], d));
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
       if (s < nseg) {
@@ -669,8 +666,9 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
       }
     }
   }
+  auto base = [&](int p) { return tabs + (p >> 1) * (2 * pstride) + (p & 1); };
   auto entries = [&](int i, int p, cplx<double> (&e)[DIM]) {
-    const cplx<double>* t = tabs + p * pstride;
+    const cplx<double>* t = base(p);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) e[d] = ld_entry(t, off[i][d]);
   };
@@ -679,27 +677,21 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
     if (DIM == 3) v = cmul(v, e[DIM - 1]);
     return v;
   };
-  for (int p0 = 0; p0 < n; p0 += tile) {
+  for (int p0 = 0; p0 < n; p0 += tile) {  // tile is even
     const int np = min(tile, n - p0);
     for (int e = threadIdx.x; e < np * DIM; e += NT) {  // row e: particle e / DIM, dimension e % DIM
-      const int pp = e / DIM;
-      fill_row_scaled(tabs + e * tbl, pos[p0 * DIM + e], nm, e == pp * DIM ? q[p0 + pp] : 1.0);
+      const int pp = e / DIM, d = e - pp * DIM;
+      fill_row_scaled(base(pp) + 2 * d * tbl, pos[p0 * DIM + e], nm, d == 0 ? q[p0 + pp] : 1.0, 2);
     }
     __syncthreads();
-    // the step phase exp(2 pi i s_last) of particle p0 + l sits in lane l of
-    // every wave (tiles hold at most 64 particles); the passes below take it
-    // from there into scalar registers, so that the LDS serves only the
-    // per-lane table entries
-    const int lane = threadIdx.x & 63;
-    const cplx<double> lu_ =
-        lane < np ? tab_at(tabs + lane * pstride, DIM - 1, nm + 1, tbl) : cplx<double>{1.0, 0.0};
+    // the step phase exp(2 pi i s_last) of a particle is one entry of its
+    // tables, read by every lane at the same address (an LDS broadcast)
+    auto step_phase = [&](int p) { return ld_entry(base(p), 2 * ((DIM - 1) * tbl + nm + 1)); };
     const int npair = np >> 1;
     // one pass: the pair (p, p + 1) with the entries a (particle p) and b
     auto pass = [&](int i, int p, const cplx<double> (&a)[DIM], const cplx<double> (&b)[DIM]) {
       if (seg0 + i * NT < nseg) {
-        const cplx<double> u0 = {lane_value(lu_.x, p), lane_value(lu_.y, p)};
-        const cplx<double> u1 = {lane_value(lu_.x, p + 1), lane_value(lu_.y, p + 1)};
-        SegWalk<double> w0(product(a), u0), w1(product(b), u1);
+        SegWalk<double> w0(product(a), step_phase(p)), w1(product(b), step_phase(p + 1));
 #pragma unroll
         for (int j = 0; j < SEG; ++j) {
           acc[i][j].x = (acc[i][j].x + w0.cur.x) + w1.cur.x;
@@ -721,13 +713,12 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
       }
     if (np & 1) {  // the tile's last particle, alone
       const int p = np - 1;
-      const cplx<double> u0 = {lane_value(lu_.x, p), lane_value(lu_.y, p)};
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
         cplx<double> a0[DIM];
         entries(i, p, a0);
         if (seg0 + i * NT < nseg) {
-          SegWalk<double> w0(product(a0), u0);
+          SegWalk<double> w0(product(a0), step_phase(p));
 #pragma unroll
           for (int j = 0; j < SEG; ++j) {
             acc[i][j].x += w0.cur.x;
@@ -1532,7 +1523,7 @@ int energy_inst(const LaunchBatch& b, const double* pos, char* state, double* en
   static const int per_cu = blocks_per_cu(kern, BLOCK);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
   int tile = budget > fixed ? int(std::min<size_t>((budget - fixed) / rpart, 64)) : 0;
-  tile = std::max(tile, TILE_P);
+  tile = std::max(tile & ~1, TILE_P);  // even (the tiles interleave particle pairs)
   const size_t lds = fixed + size_t(tile) * rpart;
   if (int rc = allow_lds(kern, lds)) return rc;
   hipLaunchKernelGGL(kern, dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), b.d_sys, b.d_walk, pos, state,
@@ -1633,7 +1624,7 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   L.cnt = uint32_t(o);
   o = up16(o + size_t(ch) * 4);
   L.ch = ch;
-  L.rtile = int(std::min<size_t>(ctab / rpart, 64));
+  L.rtile = int(std::min<size_t>(ctab / rpart, 64)) & ~1;  // even (the tiles interleave particle pairs)
   // Between chunks the tables and the staging area are free: the mixed form's
   // rebuild keeps the running rho there (for the drift check) when it fits
   // beside tiles of at least TILE_P particles, instead of a round trip
@@ -1643,7 +1634,7 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   const size_t region = o - L.ctab;
   if (MIXED && region >= rcopy + size_t(TILE_P) * rpart) {
     L.rcopy = uint32_t((o - rcopy) & ~size_t(15));
-    L.rtile = int(std::min<size_t>((L.rcopy - L.ctab) / rpart, 64));
+    L.rtile = int(std::min<size_t>((L.rcopy - L.ctab) / rpart, 64)) & ~1;
   }
   return o;
 }

@@ -19,7 +19,8 @@ constexpr int MAX_CAND = 16;      // +-pairs of minimum-image candidate offsets
 constexpr int MAX_COSET = 1;      // nonzero cosets of an orthogonal sublattice (index <= 2)
 constexpr int HDR_BYTES = 256;    // per-walker state header
 constexpr int MAX_SPT = 8;        // segments per thread held in registers (MAX_SEGMENTS / BLOCK)
-constexpr int TILE_P = 8;         // particles per phase-table tile when rebuilding rho
+constexpr int TILE_P = 8;         // particles per phase-table tile when rebuilding rho (tiles are even)
+static_assert(TILE_P % 2 == 0, "rebuild tiles hold whole particle pairs");
 constexpr int RUN_CHUNK = 64;     // proposals staged in LDS per chunk by the fused kernel
 constexpr int WTAB_MAX = 1024;    // largest shell table kept in LDS by the fused kernel
 constexpr int POLY_MAX = 32;      // largest degree of the pair-potential polynomial (FP64)

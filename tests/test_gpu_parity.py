@@ -330,6 +330,50 @@ def test_two_particles_and_ions(oracle_lib):
         assert np.max(np.abs(df.cpu().numpy()[:, 0] - r["delta"])) <= tol
 
 
+@pytest.mark.parametrize("n", [7, 65])
+def test_odd_particle_counts(oracle_lib, n):
+    """An odd number of particles leaves one particle alone in the last rho
+    rebuild tile (the tiles take particles in pairs): energy, per-step and
+    fused moves, with rebuilds every 2 accepts in the mixed form."""
+    rng = np.random.default_rng([11, n])
+    lat = np.array([[6.0, 0.3, 0.0], [0.5, 5.5, 0.2], [0.1, -0.4, 6.2]])
+    ions = rng.uniform(0, 6, (3, 3))
+    q = np.where(np.arange(n) % 3 == 0, -0.5, -1.0)
+    s = wl.System("odd%d" % n, 3, lat, n, q, ions, np.array([1.0, 2.0, 1.5]), 1.1, 2.6, 8 * 2 * math.pi / 6.0)
+    p0 = rng.uniform(0, 6, (n, 3))
+    M = 12
+    ks = rng.integers(0, n, M).astype(np.int32)
+    newp = rng.uniform(-1, 7, (M, 3))
+    acc = (rng.uniform(size=M) < 0.6).astype(np.uint8)
+    r = oracle_lib.run(s, p0, ks, newp, acc)
+    scale = max(abs(r["energy0"]), e_scale(s))
+    for prec in (FP64, MIXED):
+        say(f"[odd n={n} prec={prec}]")
+        sysh = ew.System(s, precision=prec, refresh_every=2 if prec == MIXED else 0)
+        batch = ew.Batch([sysh], np.zeros(1, dtype=np.int32))
+        pos = torch.tensor(p0, device="cuda")
+        e = torch.zeros(1, dtype=torch.float64, device="cuda")
+        batch.energy(pos, e)
+        torch.cuda.synchronize()
+        assert abs(e.item() - r["energy0"]) <= (1e-10 if prec == FP64 else 1e-6) * scale
+        tol = 1e-10 * scale if prec == FP64 else 1e-5
+        d = torch.zeros(M, dtype=torch.float64, device="cuda")
+        for m in range(M):
+            batch.move_delta(torch.tensor(ks[m:m + 1], device="cuda"),
+                             torch.tensor(newp[m:m + 1], device="cuda"), d[m:m + 1])
+            batch.accept(torch.tensor(acc[m:m + 1], device="cuda"))
+        torch.cuda.synchronize()
+        assert np.max(np.abs(d.cpu().numpy() - r["delta"])) <= tol
+        batch.energy(pos, e)
+        df = torch.zeros((M, 1), dtype=torch.float64, device="cuda")
+        batch.run_moves(torch.tensor(ks.reshape(M, 1), device="cuda"), torch.tensor(newp.reshape(M, 1, 3), device="cuda"),
+                        torch.tensor(acc.reshape(M, 1), device="cuda"), df)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(df.cpu().numpy()[:, 0] - r["delta"])) <= tol
+        if prec == MIXED:
+            assert batch.walker_header(0)["n_refresh"] == int(acc.sum()) // 2
+
+
 @pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("cfg_id", [2, 3, 5])
 def test_general_frame_matches_ortho(cfg_id, precision):

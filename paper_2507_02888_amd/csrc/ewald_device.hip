@@ -408,8 +408,10 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
 // kernel's geometry: frame or fractional coordinates, as sn and so) and
 // charges in registers (ps, pq); it alone updates them when they move.  Particles beyond
 // PPR NT (larger systems than the launch shape covers) are read from the LDS
-// copy, again only by their owner t = j mod NT.
-template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO>
+// copy, again only by their owner t = j mod NT.  XTRA = false: the batch has
+// no such particles and no fixed ions, and those loops are left out (at 1024
+// threads their mere presence costs scalar-register reloads on every move).
+template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO, bool XTRA>
 __device__ __forceinline__ double real_move_own(const double* sn, const double* so, int k,
                                                 const double (&ps)[PPR][DIM], const double (&pq)[PPR],
                                                 const double* lpos, const double* lq, int n,
@@ -431,6 +433,7 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
     }
     pr.template add<2 * PPR>(qq, r2);
   }
+  if (!XTRA) return pr.value();
   for (int j = threadIdx.x + PPR * NT; j < n; j += NT) {
     double qq[2], r2[2];
     const bool ok = j != k;
@@ -1135,7 +1138,7 @@ struct RunLds {
   int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
 };
 
-template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO>
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO, bool XTRA>
 __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
@@ -1352,7 +1355,7 @@ __global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
           if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO>(xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32,
+          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO, XTRA>(xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32,
                                                                 CV ? fk : frame_k(S));
         }
         if (acc) {
@@ -1652,9 +1655,9 @@ struct RunArgs {
   RunPlan* plan;  // non-null: resolve the launch shape only, launch nothing
 };
 
-template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO>
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO, bool XTRA>
 int run_inst(const LaunchBatch& b, const RunArgs& a) {
-  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO>;
+  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, XTRA>;
   static const int per_cu = blocks_per_cu(kern, NT);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
   RunLds L{};
@@ -1705,8 +1708,12 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   static_assert(RUN_CHUNK <= 256, "staging uses one thread per move");
   int nt = 0, spt = 0, ppr = 0;
   if (!run_shape(b.max_n_seg, b.max_particles, b.run_threads, &nt, &spt, &ppr)) return RUN_NO_FIT;
-#define EW_RUN(NT, SPT, PPR) \
-  if (nt == NT && spt == SPT && ppr == PPR) return run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO>(b, a)
+  // particles beyond the registers' share, or fixed ions, in any walker
+  const bool xtra = b.max_particles > ppr * nt || b.max_fixed > 0;
+#define EW_RUN(NT, SPT, PPR)                                                                            \
+  if (nt == NT && spt == SPT && ppr == PPR)                                                            \
+    return xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, true>(b, a)                       \
+                : run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, false>(b, a)
   EW_RUN(256, 1, 1);
   EW_RUN(256, 1, 2);
   EW_RUN(256, 2, 1);

@@ -1138,8 +1138,11 @@ struct RunLds {
   int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
 };
 
+// At least two waves per SIMD for workgroups of up to 512 threads (the
+// register budget stays within 256 per lane; without the bound the compiler
+// may take accumulation registers as well, which leaves one wave per SIMD).
 template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO, bool XTRA>
-__global__ __launch_bounds__(NT) void k_run(const DevSys* __restrict__ systems,
+__global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
                                             const double* __restrict__ new_pos, const uint8_t* __restrict__ accept,
@@ -1708,9 +1711,14 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   static_assert(RUN_CHUNK <= 256, "staging uses one thread per move");
   int nt = 0, spt = 0, ppr = 0;
   if (!run_shape(b.max_n_seg, b.max_particles, b.run_threads, &nt, &spt, &ppr)) return RUN_NO_FIT;
-  // particles beyond the registers' share, or fixed ions, in any walker
+  // XTRA: particles beyond the registers' share, or fixed ions, in some
+  // walker.  Leaving those loops out pays at 512 and 1024 threads; the
+  // 256-thread kernels keep them (without them the compiler spends more
+  // registers there and runs slower).
   const bool xtra = b.max_particles > ppr * nt || b.max_fixed > 0;
-#define EW_RUN(NT, SPT, PPR)                                                                            \
+#define EW_RUN(NT, SPT, PPR) \
+  if (nt == NT && spt == SPT && ppr == PPR) return run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, true>(b, a)
+#define EW_RUN_X(NT, SPT, PPR)                                                                          \
   if (nt == NT && spt == SPT && ppr == PPR)                                                            \
     return xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, true>(b, a)                       \
                 : run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, false>(b, a)
@@ -1718,9 +1726,10 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   EW_RUN(256, 1, 2);
   EW_RUN(256, 2, 1);
   EW_RUN(256, 2, 2);
-  EW_RUN(1024, 1, 1);
-  EW_RUN(512, 2, 2);
-  EW_RUN(512, 4, 2);
+  EW_RUN_X(1024, 1, 1);
+  EW_RUN_X(512, 2, 2);
+  EW_RUN_X(512, 4, 2);
+#undef EW_RUN_X
 #undef EW_RUN
   return RUN_NO_FIT;
 }

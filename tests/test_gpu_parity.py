@@ -494,6 +494,64 @@ def test_tuning_shapes_agree(precision):
         ref.batch.set_tuning(chunk=65)
 
 
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_extra_particles_and_ions_at_large_shapes(precision):
+    """The 512- and 1024-thread fused kernels built with their loops over
+    particles beyond the registers' share and over fixed ions: a walker of
+    1100 electrons (more than a 1024-thread workgroup holds in registers)
+    beside a small walker with ions, both with ~1000 G segments, against the
+    per-step kernels."""
+    rng = np.random.default_rng([13, precision])
+    systems = []
+    for n, nion in ((1100, 0), (40, 3)):
+        L = (4 * math.pi * n / 3) ** (1 / 3) if n > 100 else 8.0
+        lat = np.eye(3) * L
+        ions = rng.uniform(0, L, (nion, 3))
+        qf = np.full(nion, 2.0)
+        systems.append(wl.System("x%d" % n, 3, lat, n, -np.ones(n), ions, qf, 5.0 / L, 0.5 * L,
+                                 12 * 2 * math.pi / L))
+    walker_sys = np.array([0, 1], dtype=np.int32)
+    M = 8
+    pos = [rng.uniform(0, systems[i].lattice[0, 0], (systems[i].n_mobile, 3)) for i in walker_sys]
+    packed = torch.tensor(np.concatenate(pos), device="cuda")
+    k = np.stack([rng.integers(0, systems[i].n_mobile, M) for i in walker_sys], axis=1).astype(np.int32)
+    newp = np.stack([rng.uniform(0, systems[i].lattice[0, 0], (M, 3)) for i in walker_sys], axis=1)
+    acc = (rng.uniform(size=(M, 2)) < 0.6).astype(np.uint8)
+    kt, nt, at = (torch.tensor(x, device="cuda") for x in (k, newp, acc))
+
+    def batch():
+        hs = [ew.System(sy, precision=precision, refresh_every=2 if precision == MIXED else 0) for sy in systems]
+        b = ew.Batch(hs, walker_sys)
+        e = torch.zeros(2, dtype=torch.float64, device="cuda")
+        b.energy(packed, e)
+        return hs, b, e
+
+    hs, ref, e = batch()
+    assert min(ew.ewald_sys_query(h.handle)["n_slots"] for h in hs) > 4 * 512
+    say(f"[extra loops] precision={precision} per-step")
+    d0 = torch.zeros((M, 2), dtype=torch.float64, device="cuda")
+    for m in range(M):
+        ref.move_delta(kt[m], nt[m], d0[m])
+        ref.accept(at[m])
+    torch.cuda.synchronize()
+    scale = max(1.0, float(e.abs().max()))
+    tol = 1e-12 * scale if precision == FP64 else 1e-5
+    for threads in (1024, 512):
+        say(f"[extra loops] precision={precision} threads={threads}")
+        _, b, _ = batch()
+        b.set_tuning(threads=threads)
+        t = b.tuning()
+        assert t["fused"] == 1 and t["threads"] == threads
+        d = torch.zeros((M, 2), dtype=torch.float64, device="cuda")
+        b.run_moves(kt, nt, at, d)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(d.cpu().numpy() - d0.cpu().numpy())) <= tol, threads
+        for w in range(2):
+            assert np.array_equal(b.walker_positions(w), ref.walker_positions(w))
+            assert np.max(np.abs(b.walker_rho(w) - ref.walker_rho(w))) <= 1e-9 * math.sqrt(systems[w].n_mobile)
+            assert b.walker_header(w)["n_accepts"] == int(acc[:, w].sum())
+
+
 def test_autotune_keeps_state_and_caches(tmp_path, oracle_lib):
     """The autotuner probes on a copy of the state (the walkers' state is
     unchanged), stores its choice in the cache file and re-applies it from there; the tuned sweep

@@ -236,7 +236,9 @@ ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, in
                                     int *fused);
 
 /* Time every launch shape of ewald_run_moves_batch on this batch and keep
- * the fastest (ewald_batch_set_tuning).  The probe runs n_moves (1..4096)
+ * the fastest (ewald_batch_set_tuning); shapes within 8 % of the fastest
+ * are timed twice more, interleaved, and compared by their best time.  The
+ * probe runs n_moves (1..4096)
  * proposals per walker, every other one accepted, on a device copy of
  * `state`, which must be ready (after ewald_energy_batch, no pending move)
  * and is left unchanged; in the FP32-mixed form n_moves >= 2 refresh_every

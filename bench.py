@@ -67,10 +67,11 @@ def traffic_from_profiles(form: str, shape: dict):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if d.get("threads") != shape.get("threads") or d.get("general_frame", 0) != shape.get("general_frame"):
-        return None
-    f = d.get("forms", {}).get(form)
-    return None if f is None else f.get("hbm_bytes_per_launch")
+    for sh in d.get("shapes", []):  # one entry per profiled workgroup size
+        if sh.get("threads") == shape.get("threads") and sh.get("general_frame", 0) == shape.get("general_frame"):
+            f = sh.get("forms", {}).get(form)
+            return None if f is None else f.get("hbm_bytes_per_launch")
+    return None
 
 
 def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_step: bool = True,

@@ -745,7 +745,7 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
 // the cell has one (ORTHO); rho is built from the fractional positions just
 // stored in the walker state.
 template <int DIM, int SPT, int PD, bool ORTHO>
-__global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ systems,
+__global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ systems,
                                                   const DevWalker* __restrict__ walkers,
                                                   const double* __restrict__ pos, char* __restrict__ state,
                                                   double* __restrict__ energy, double* __restrict__ jastrow,
@@ -759,24 +759,21 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
   double* spos = reinterpret_cast<double*>(st + HDR_BYTES);
   double* rho = reinterpret_cast<double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
-  double* lpos = smem;                       // [n][DIM] in the pair loop's geometry
-  double* lq = smem + lds_pos * DIM;         // [n]
-  double* red = lq + lds_pos;                // [4 * 4]
-  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(red + 16);
+  // LDS: the rebuild's phase-table tiles first, then (in the same space) the
+  // pair loop's positions and charges
+  double* red = smem;                        // [4 * 4]
+  cplx<double>* tabs = reinterpret_cast<cplx<double>*>(smem + 16);
+  double* lpos = smem + 16;                  // [n][DIM] in the pair loop's geometry
+  double* lq = lpos + lds_pos * DIM;         // [n]
 
   const double* pw = pos + size_t(W.pos_off) * DIM;
   for (int i = tid; i < n; i += BLOCK) {
-    double r[DIM], s[DIM], x[DIM];
+    double r[DIM], s[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) r[d] = pw[i * DIM + d];
     to_frac<DIM>(r, S->Ainv, s);
-    geo_pos<DIM, ORTHO>(s, S, x);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      lpos[i * DIM + d] = x[d];
-      spos[i * DIM + d] = s[d];
-    }
-    lq[i] = S->mobile_q[i];
+    for (int d = 0; d < DIM; ++d) spos[i * DIM + d] = s[d];
   }
   if (tid == 0) {
     hdr->counter = 0;
@@ -796,7 +793,7 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
     an[i] = s < nseg ? S->seg_n[s] : 0u;
   }
   cplx<double> acc[SPT][SEG];
-  rebuild_rho<DIM, SPT>(acc, an, tid, S, spos, lq, n, tabs, tile);
+  rebuild_rho<DIM, SPT>(acc, an, tid, S, spos, S->mobile_q, n, tabs, tile);
   double er = 0.0, ej = 0.0;
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
@@ -816,6 +813,18 @@ __global__ __launch_bounds__(BLOCK) void k_energy(const DevSys* __restrict__ sys
 
   // real space: each unordered mobile pair once (pair i with i+1..i+(n-1)/2
   // cyclically, plus i+n/2 for i < n/2 when n is even), then every fixed ion
+  // positions in the pair loop's geometry replace the tiles (the rebuild
+  // ends with a barrier)
+  for (int i = tid; i < n; i += BLOCK) {
+    double sv[DIM], x[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) sv[d] = spos[i * DIM + d];
+    geo_pos<DIM, ORTHO>(sv, S, x);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) lpos[i * DIM + d] = x[d];
+    lq[i] = S->mobile_q[i];
+  }
+  __syncthreads();
   // the pair loop's constants in vector registers (see frame_k_vector)
   const FrameK K = frame_k_vector(S);
   double cf64[PD + 1];
@@ -1522,15 +1531,17 @@ int energy_inst(const LaunchBatch& b, const double* pos, char* state, double* en
                 void* stream) {
   const int lds_pos = even(b.max_particles);
   const size_t rpart = size_t(DIM) * (2 * b.max_nm + 1) * sizeof(cplx<double>);
-  const size_t fixed = size_t(lds_pos) * (DIM + 1) * 8 + 16 * 8;
+  const size_t head = 16 * 8, pairs = size_t(lds_pos) * (DIM + 1) * 8;
   auto* kern = k_energy<DIM, SPT, PD, ORTHO>;
-  // rebuild tiles as large as LDS allows without lowering the workgroups per
-  // CU that registers allow (fewer barriers per particle), at most 64
+  // rebuild tiles (sharing their LDS with the pair loop's positions) as
+  // large as LDS allows without lowering the workgroups per CU that
+  // registers allow (four: the kernel is bounded to four waves per SIMD),
+  // at most 64
   static const int per_cu = blocks_per_cu(kern, BLOCK);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
-  int tile = budget > fixed ? int(std::min<size_t>((budget - fixed) / rpart, 64)) : 0;
+  int tile = budget > head ? int(std::min<size_t>((budget - head) / rpart, 64)) : 0;
   tile = std::max(tile & ~1, TILE_P);  // even (the tiles interleave particle pairs)
-  const size_t lds = fixed + size_t(tile) * rpart;
+  const size_t lds = head + std::max(pairs, size_t(tile) * rpart);
   if (int rc = allow_lds(kern, lds)) return rc;
   hipLaunchKernelGGL(kern, dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), b.d_sys, b.d_walk, pos, state,
                      energy, jastrow, lds_pos, tile);

@@ -50,8 +50,12 @@ def algorithmic_flops_per_energy(n_g: int, n_part: int) -> float:
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2507_02888_amd", "csrc", "ewald_device.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the fused kernel is compiled from."""
+    csrc = os.path.join(ROOT, "paper_2507_02888_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("ewald_internal.h", "ewald_common.h", "ewald_run.h"):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(form: str, shape: dict):

@@ -1132,7 +1132,10 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
     for (void* p : {dk, dp, da, dd, ds})
       if (p) dev_free(p);
   };
-  int rc = dev_alloc(&ds, b->state_bytes);
+  // the caller's stream may still be writing the state (a non-blocking
+  // stream does not order against the synchronous copy below)
+  int rc = stream_sync(stream);
+  if (!rc) rc = dev_alloc(&ds, b->state_bytes);
   if (!rc) rc = dev_copy(ds, state, b->state_bytes);
   if (!rc) rc = dev_alloc(&dk, hk.size() * 4);
   if (!rc) rc = dev_alloc(&dp, hp.size() * 8);

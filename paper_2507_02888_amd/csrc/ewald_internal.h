@@ -1,5 +1,5 @@
 // Internal layout shared by the host set-up (ewald_host.cpp) and the HIP
-// kernels (ewald_device.hip).  Not part of the public ABI.
+// kernels (ewald_device.hip, ewald_run_d*.hip).  Not part of the public ABI.
 #pragma once
 
 #include <cstddef>
@@ -113,7 +113,7 @@ inline uint32_t pack_n(int a, int b, int c) {
   return uint32_t(a & 0xff) | (uint32_t(b & 0xff) << 8) | (uint32_t(c & 0xff) << 16);
 }
 
-// ---- launch interface implemented in ewald_device.hip ----------------------
+// ---- launch interface implemented in ewald_device.hip -----------------------
 
 struct LaunchBatch {
   const DevSys* d_sys;      // device array [n_sys]
@@ -174,5 +174,6 @@ const char* dev_error_string(int code);
 int dev_arch(char* buf, int len);  // the current device's architecture name
 int dev_memset(void* p, int value, size_t bytes);
 int dev_copy(void* dst, const void* src, size_t bytes);  // device to device, synchronous
+int stream_sync(void* stream);  // waits for the work queued on `stream`
 
 }  // namespace ewald

@@ -5,7 +5,9 @@ benchmark's CPU-baseline leg. The library under paper_2507_02888_amd never
 imports it, and the oracle shares no code with the library.
 
 Parity unpinned: none -- every entry point is pinned by tests/test_oracle_pins.py
-(Madelung constants, alpha independence, invariances, incremental moves).
+(Madelung constants, alpha independence, invariances, incremental moves,
+shell populations of cubic reciprocal lattices for the Jastrow shell index,
+the batch driver against the single-walker driver).
 """
 from .oracle import (  # noqa: F401
     build, lib_path, count_g, gvectors, rho_at, energy, run, run_batch, particles, Variant,

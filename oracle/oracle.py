@@ -221,4 +221,7 @@ class Variant:
     def run(self, system, mobile_pos, k, new_pos, accept, jastrow_a=None, **over):
         return run(system, mobile_pos, k, new_pos, accept, jastrow_a, self.path, **over)
 
+    def run_batch(self, system, mobile_pos, k, new_pos, accept, jastrow_a=None, n_threads=0):
+        return run_batch(system, mobile_pos, k, new_pos, accept, jastrow_a, n_threads, self.path)
+
     particles = staticmethod(particles)

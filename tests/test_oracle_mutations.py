@@ -31,6 +31,8 @@ MUTATIONS = [
     ("delta_old_sign", "- real_image_sum(s, bm, dold, 0));", "+ real_image_sum(s, bm, dold, 0));"),
     ("rho_update_sign", "rre[t] += q[kk] * (cos(pn) - cos(po));", "rre[t] -= q[kk] * (cos(pn) - cos(po));"),
     ("jastrow_half", "jas += 0.5 * jastrow_coef(s, g.shell[t]) * r2;", "jas += jastrow_coef(s, g.shell[t]) * r2;"),
+    ("shell_order_reversed", "{ sidx = u; break; }", "{ sidx = nu - 1 - u; break; }"),
+    ("run_batch_k_transposed", "kw[m] = k[(size_t)m * n_walkers + w];", "kw[m] = k[(size_t)w * n_steps + m];"),
 ]
 
 CHECKS = [
@@ -42,6 +44,9 @@ CHECKS = [
     lambda o: pins.test_cutoff_shells(o),
     lambda o: [pins.test_incremental_moves_match_recompute(o, c) for c in (1, 3)],
     lambda o: pins.test_jastrow_structure_factor_equals_pair_form(o),
+    lambda o: [pins.test_jastrow_shells_cubic(o, d) for d in (3, 2)],
+    lambda o: [pins.test_shell_index_order(o, c) for c in (1, 3)],
+    lambda o: [pins.test_run_batch_matches_run(o, c) for c in (2, 3)],
 ]
 
 

@@ -267,3 +267,94 @@ def test_cutoff_shells(oracle_lib):
     r2, r3 = math.sqrt(2.0) * L, math.sqrt(3.0) * L
     assert abs((e[1.5] - e[1.2]) - 6.0 * math.erfc(a * r2) / r2) <= 1e-13
     assert abs((e[1.8] - e[1.5]) - 4.0 * math.erfc(a * r3) / r3) <= 1e-13
+
+
+SHELLS = os.path.join(os.path.dirname(__file__), "golden", "lattice_shells.txt")
+
+
+def shell_table(dim):
+    out = []
+    for line in open(SHELLS):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        d, m, r = (int(x) for x in line.split())
+        if d == dim:
+            out.append((m, r))
+    return out
+
+
+def count_sums_of_squares(m, dim):
+    """Brute force: integer vectors of `dim` components with squared norm m."""
+    n = int(math.isqrt(m)) + 1
+    rng_ = range(-n, n + 1)
+    if dim == 2:
+        return sum(1 for a in rng_ for b in rng_ if a * a + b * b == m)
+    return sum(1 for a in rng_ for b in rng_ for c in rng_ if a * a + b * b + c * c == m)
+
+
+def test_shell_golden_values_are_sums_of_squares():
+    """The golden shell populations equal a direct count of lattice vectors."""
+    for dim in (2, 3):
+        for m, r in shell_table(dim):
+            assert count_sums_of_squares(m, dim) == r
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_jastrow_shells_cubic(oracle_lib, dim):
+    """Shell index s(G) behind J = sum_H a_s(G) |rho(G)|^2 (Sec. 2.3, Eq. (9)):
+    one unit charge in a simple-cubic (square) cell has |rho(G)|^2 = 1 for every
+    G, so J with a = e_s (one shell switched on) counts the half set of shell s,
+    which holds r_dim(m_s)/2 vectors with |G|^2 = (2 pi/L)^2 m_s; m_s runs over
+    the representable norms in ascending order (tests/golden/lattice_shells.txt)."""
+    L = 6.0
+    lat = L * np.eye(3) if dim == 3 else square_cell(L * L)
+    s = one_charge(lat, dim)
+    kw = dict(alpha=5.0 / L, r_cut=0.5 * L, g_cut=8.0 * 2 * math.pi / L)
+    pos = np.full((1, dim), 0.37)
+    table = shell_table(dim)
+    for idx, (m, r) in enumerate(table):
+        a = np.zeros(len(table) + 5)
+        a[idx] = 1.0
+        j = oracle_lib.energy(s, pos, -np.ones(1), jastrow_a=a, **kw)["jastrow"]
+        assert abs(j - r / 2.0) <= 1e-9, (dim, idx, m, j, r / 2.0)
+    # and the shells carry exactly those norms
+    g, g2, shell = oracle_lib.gvectors(s, **kw)
+    unit = (2 * math.pi / L) ** 2
+    for idx, (m, r) in enumerate(table):
+        sel = shell == idx
+        assert int(sel.sum()) == r
+        assert np.allclose(g2[sel] / unit, m, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("cfg_id", [1, 3, 5])
+def test_shell_index_order(oracle_lib, cfg_id):
+    """s(G) is nondecreasing in |G|^2, equal exactly when |G|^2 is equal (to the
+    1e-9 relative tolerance that defines a shell), and starts at 0."""
+    s = wl.config(cfg_id).systems[0]
+    g, g2, shell = oracle_lib.gvectors(s)
+    o = np.argsort(g2, kind="stable")
+    g2s, shs = g2[o], shell[o]
+    assert shs[0] == 0
+    steps = np.diff(shs)
+    assert np.all((steps == 0) | (steps == 1))
+    same = np.abs(np.diff(g2s)) <= 1e-9 * g2s[1:]
+    assert np.array_equal(steps == 0, same)
+
+
+@pytest.mark.parametrize("cfg_id", [2, 3])
+def test_run_batch_matches_run(oracle_lib, cfg_id):
+    """The OpenMP batch driver gives, walker by walker, exactly the single-walker
+    results: it only regroups the [S][W] inputs and outputs."""
+    cfg = wl.config(cfg_id)
+    b = wl.make_batch(cfg, walkers=3, moves=5)
+    s = cfg.systems[0]
+    ja = np.random.default_rng(4).uniform(-0.01, 0.01, 40)
+    pos = b.pos.reshape(3, s.n_mobile, s.dim)
+    r = oracle_lib.run_batch(s, pos, b.k, b.new_pos, b.accept, jastrow_a=ja, n_threads=2)
+    for w in range(3):
+        one = oracle_lib.run(s, b.walker_pos(w), b.k[:, w], b.new_pos[:, w], b.accept[:, w], jastrow_a=ja)
+        assert np.array_equal(r["e0"][w], one["e0"])
+        assert r["j0"][w] == one["j0"]
+        assert np.array_equal(r["delta"][:, w], one["delta"])
+        assert np.array_equal(r["djas"][:, w], one["djas"])

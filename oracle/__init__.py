@@ -10,5 +10,5 @@ shell populations of cubic reciprocal lattices for the Jastrow shell index,
 the batch driver against the single-walker driver).
 """
 from .oracle import (  # noqa: F401
-    build, lib_path, count_g, gvectors, rho_at, energy, run, run_batch, particles, Variant,
+    build, lib_path, count_g, gvectors, rho_at, energy, jastrow_derivs, run, run_batch, particles, Variant,
 )

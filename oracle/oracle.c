@@ -45,6 +45,16 @@
  * structure factor): J = sum_{G in half set} a_{s(G)} |rho(G)|^2 where s(G) is
  * the index of the shell of equal |G| (ascending, 0-based) and a_s = 0 for
  * s >= n_jastrow.  Summed here over the full set with a factor 1/2.
+ *
+ * Its derivatives with respect to one particle's position (the values and
+ * derivatives of the p term that Sec. 5.2 offloads; the kinetic energy of QMC
+ * needs the gradient and the Laplacian, Sec. 2.1) are taken from the pair
+ * form of the same J: with the plane-wave pair function
+ *   P(r) = 1/2 sum_{G != 0} a_{s(G)} cos(G.r)          (Eq. (9), full set)
+ * J = P(0) sum_i q_i^2 + 2 sum_{i<j} q_i q_j P(r_i - r_j), so
+ *   grad_k J = 2 q_k sum_{j != k} q_j grad P(r_k - r_j),  grad P(r) = -1/2 sum_G a G sin(G.r)
+ *   lap_k J  = 2 q_k sum_{j != k} q_j lap P(r_k - r_j),   lap P(r)  = -1/2 sum_G a |G|^2 cos(G.r)
+ * evaluated by direct pair and G loops (no structure factor).
  */
 #include <math.h>
 #include <stdint.h>
@@ -321,15 +331,49 @@ int oracle_energy(const osys *s, int n, const double *pos, const double *q, doub
     return 0;
 }
 
+/* Gradient (grad[0..dim)) and Laplacian (*lap) of J with respect to the
+ * position of particle k, by the pair form above. */
+int oracle_jastrow_derivs(const osys *s, int n, const double *pos, const double *q, int k, double *grad,
+                          double *lap) {
+    int dim = s->dim;
+    gset g;
+    gset_build(s, &g);
+    double gr[3] = {0, 0, 0}, lp = 0;
+    for (int j = 0; j < n; ++j) {
+        if (j == k) continue;
+        double d[3] = {0, 0, 0};
+        for (int e = 0; e < dim; ++e) d[e] = pos[dim * k + e] - pos[dim * j + e];
+        double pg[3] = {0, 0, 0}, pl = 0; /* grad P and lap P at d */
+        for (int t = 0; t < g.n; ++t) {
+            double a = jastrow_coef(s, g.shell[t]);
+            if (a == 0.0) continue;
+            double ph = 0;
+            for (int e = 0; e < dim; ++e) ph += g.g[3 * t + e] * d[e];
+            for (int e = 0; e < dim; ++e) pg[e] += -0.5 * a * g.g[3 * t + e] * sin(ph);
+            pl += -0.5 * a * g.g2[t] * cos(ph);
+        }
+        for (int e = 0; e < dim; ++e) gr[e] += 2 * q[k] * q[j] * pg[e];
+        lp += 2 * q[k] * q[j] * pl;
+    }
+    for (int e = 0; e < dim; ++e) grad[e] = gr[e];
+    *lap = lp;
+    gset_free(&g);
+    return 0;
+}
+
 /* One walker: initial energy, then n_steps proposed moves of mobile particles
  * (indices k[m] < n_mobile; particles are ordered mobile first).  For each
  * move the incremental delta (and Jastrow delta) is written; accepted moves
  * update rho and the position.  Outputs: e0[0..4] parts of the initial energy,
- * delta[m], djas[m], *j0 initial Jastrow, final positions in pos_final.
+ * delta[m], djas[m], *j0 initial Jastrow, final positions in pos_final, and,
+ * when jgrad and jlap are not NULL, the gradient jgrad[m][dim] and Laplacian
+ * jlap[m] of J with respect to the moved particle at the proposed
+ * configuration (particle k[m] at its proposal, whether or not accepted).
  * Returns 0. */
 int oracle_run(const osys *s, int n, int n_mobile, const double *pos0, const double *q,
                int n_steps, const int32_t *k, const double *new_pos, const uint8_t *accept,
-               double *e0, double *j0, double *delta, double *djas, double *pos_final) {
+               double *e0, double *j0, double *delta, double *djas, double *pos_final,
+               double *jgrad, double *jlap) {
     (void)n_mobile;
     int dim = s->dim;
     double bm[9];
@@ -386,6 +430,13 @@ int oracle_run(const osys *s, int n, int n_mobile, const double *pos0, const dou
         }
         delta[m] = dr + drec;
         djas[m] = dj;
+        if (jgrad && jlap) {
+            double *prop = (double *)malloc(sizeof(double) * (size_t)dim * (size_t)n);
+            memcpy(prop, pos, sizeof(double) * (size_t)dim * (size_t)n);
+            for (int e = 0; e < dim; ++e) prop[dim * kk + e] = rn[e];
+            oracle_jastrow_derivs(s, n, prop, q, kk, jgrad + (size_t)dim * (size_t)m, jlap + m);
+            free(prop);
+        }
         if (accept[m]) {
             for (int t = 0; t < g.n; ++t) {
                 double pn = 0, po = 0;
@@ -442,7 +493,7 @@ int oracle_run_batch(const osys *s, int n_walkers, int n, int n_mobile, const do
             for (int e = 0; e < dim; ++e) nw[dim * m + e] = new_pos[((size_t)m * n_walkers + w) * dim + e];
         }
         oracle_run(s, n, n_mobile, pos0 + (size_t)w * n * dim, q, n_steps, kw, nw, aw,
-                   e0 + 5 * (size_t)w, j0 + w, dw, jw, NULL);
+                   e0 + 5 * (size_t)w, j0 + w, dw, jw, NULL, NULL, NULL);
         for (int m = 0; m < n_steps; ++m) {
             delta[(size_t)m * n_walkers + w] = dw[m];
             djas[(size_t)m * n_walkers + w] = jw[m];

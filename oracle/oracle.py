@@ -52,7 +52,8 @@ def _load(path: str = _LIB):
         lib.oracle_rho_at.argtypes = [P(_OSys), i, P(d), P(d), i, P(d), P(d)]
         lib.oracle_energy.argtypes = [P(_OSys), i, P(d), P(d), P(d), P(d)]
         lib.oracle_run.argtypes = [P(_OSys), i, i, P(d), P(d), i, P(ctypes.c_int32), P(d),
-                                   P(ctypes.c_uint8), P(d), P(d), P(d), P(d), P(d)]
+                                   P(ctypes.c_uint8), P(d), P(d), P(d), P(d), P(d), P(d), P(d)]
+        lib.oracle_jastrow_derivs.argtypes = [P(_OSys), i, P(d), P(d), i, P(d), P(d)]
         lib.oracle_run_batch.argtypes = [P(_OSys), i, i, i, P(d), P(d), i, P(ctypes.c_int32),
                                          P(d), P(ctypes.c_uint8), P(d), P(d), P(d), P(d), i]
         lib.oracle_run_batch.restype = i
@@ -148,9 +149,25 @@ def energy(system, pos, q, jastrow_a: Optional[np.ndarray] = None, _path=_LIB, *
                 total=parts[4], jastrow=jas.value)
 
 
-def run(system, mobile_pos, k, new_pos, accept, jastrow_a=None, _path=_LIB, **over):
+def jastrow_derivs(system, pos, q, k, jastrow_a, _path=_LIB, **over):
+    """Gradient [dim] and Laplacian of J with respect to particle k (all
+    particles given explicitly)."""
+    s = _mk(system, jastrow_a=jastrow_a, **over)
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    grad = np.zeros(system.dim)
+    lap = ctypes.c_double(0.0)
+    _load(_path).oracle_jastrow_derivs(s.ref(), int(q.shape[0]), _ptr(pos, ctypes.c_double),
+                                       _ptr(q, ctypes.c_double), int(k), _ptr(grad, ctypes.c_double),
+                                       ctypes.byref(lap))
+    return grad, lap.value
+
+
+def run(system, mobile_pos, k, new_pos, accept, jastrow_a=None, _path=_LIB, derivs=False, **over):
     """One walker: initial energy then the move sequence.  Returns dict with
-    e0 (parts array), j0, delta [S], djas [S], pos_final (mobile)."""
+    e0 (parts array), j0, delta [S], djas [S], pos_final (mobile), and with
+    derivs=True jgrad [S][dim] and jlap [S]: the gradient and Laplacian of J
+    with respect to the moved particle at each proposed configuration."""
     s = _mk(system, jastrow_a=jastrow_a, **over)
     pos, q = particles(system, mobile_pos)
     n = int(q.shape[0])
@@ -163,13 +180,21 @@ def run(system, mobile_pos, k, new_pos, accept, jastrow_a=None, _path=_LIB, **ov
     delta = np.zeros(S)
     djas = np.zeros(S)
     pf = np.zeros_like(pos)
+    jg = np.zeros((S, system.dim)) if derivs else None
+    jl = np.zeros(S) if derivs else None
+    null = ctypes.POINTER(ctypes.c_double)()
     _load(_path).oracle_run(s.ref(), n, system.n_mobile, _ptr(pos, ctypes.c_double),
                        _ptr(q, ctypes.c_double), S, _ptr(k, ctypes.c_int32),
                        _ptr(newp, ctypes.c_double), _ptr(acc, ctypes.c_uint8),
                        _ptr(e0, ctypes.c_double), ctypes.byref(j0), _ptr(delta, ctypes.c_double),
-                       _ptr(djas, ctypes.c_double), _ptr(pf, ctypes.c_double))
-    return dict(e0=e0, energy0=e0[4], j0=j0.value, delta=delta, djas=djas,
-                pos_final=pf[: system.n_mobile])
+                       _ptr(djas, ctypes.c_double), _ptr(pf, ctypes.c_double),
+                       null if jg is None else _ptr(jg, ctypes.c_double),
+                       null if jl is None else _ptr(jl, ctypes.c_double))
+    out = dict(e0=e0, energy0=e0[4], j0=j0.value, delta=delta, djas=djas,
+               pos_final=pf[: system.n_mobile])
+    if derivs:
+        out.update(jgrad=jg, jlap=jl)
+    return out
 
 
 def run_batch(system, mobile_pos, k, new_pos, accept, jastrow_a=None, n_threads=0, _path=_LIB):
@@ -218,8 +243,11 @@ class Variant:
     def energy(self, system, pos, q, jastrow_a=None, **over):
         return energy(system, pos, q, jastrow_a, self.path, **over)
 
-    def run(self, system, mobile_pos, k, new_pos, accept, jastrow_a=None, **over):
-        return run(system, mobile_pos, k, new_pos, accept, jastrow_a, self.path, **over)
+    def run(self, system, mobile_pos, k, new_pos, accept, jastrow_a=None, derivs=False, **over):
+        return run(system, mobile_pos, k, new_pos, accept, jastrow_a, self.path, derivs, **over)
+
+    def jastrow_derivs(self, system, pos, q, k, jastrow_a, **over):
+        return jastrow_derivs(system, pos, q, k, jastrow_a, self.path, **over)
 
     def run_batch(self, system, mobile_pos, k, new_pos, accept, jastrow_a=None, n_threads=0):
         return run_batch(system, mobile_pos, k, new_pos, accept, jastrow_a, n_threads, self.path)

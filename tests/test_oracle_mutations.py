@@ -33,6 +33,11 @@ MUTATIONS = [
     ("jastrow_half", "jas += 0.5 * jastrow_coef(s, g.shell[t]) * r2;", "jas += jastrow_coef(s, g.shell[t]) * r2;"),
     ("shell_order_reversed", "{ sidx = u; break; }", "{ sidx = nu - 1 - u; break; }"),
     ("run_batch_k_transposed", "kw[m] = k[(size_t)m * n_walkers + w];", "kw[m] = k[(size_t)w * n_steps + m];"),
+    ("jgrad_factor", "gr[e] += 2 * q[k] * q[j] * pg[e];", "gr[e] += q[k] * q[j] * pg[e];"),
+    ("jgrad_cos", "pg[e] += -0.5 * a * g.g[3 * t + e] * sin(ph);", "pg[e] += -0.5 * a * g.g[3 * t + e] * cos(ph);"),
+    ("jlap_norm", "pl += -0.5 * a * g.g2[t] * cos(ph);", "pl += -0.5 * a * sqrt(g.g2[t]) * cos(ph);"),
+    ("jlap_sign", "lp += 2 * q[k] * q[j] * pl;", "lp -= 2 * q[k] * q[j] * pl;"),
+    ("jderiv_old_position", "prop[dim * kk + e] = rn[e];", "prop[dim * kk + e] = ro[e];"),
 ]
 
 CHECKS = [
@@ -47,6 +52,8 @@ CHECKS = [
     lambda o: [pins.test_jastrow_shells_cubic(o, d) for d in (3, 2)],
     lambda o: [pins.test_shell_index_order(o, c) for c in (1, 3)],
     lambda o: [pins.test_run_batch_matches_run(o, c) for c in (2, 3)],
+    lambda o: [pins.test_jastrow_derivs_finite_differences(o, d) for d in (3, 2)],
+    lambda o: pins.test_run_derivs_at_proposed_configuration(o),
 ]
 
 

@@ -358,3 +358,89 @@ def test_run_batch_matches_run(oracle_lib, cfg_id):
         assert r["j0"][w] == one["j0"]
         assert np.array_equal(r["delta"][:, w], one["delta"])
         assert np.array_equal(r["djas"][:, w], one["djas"])
+
+
+def jastrow_system(dim, n, seed):
+    """A small cell (the 54-electron cubic cell of the workloads, or the 2D
+    hexagonal one) with mixed charges and seeded Jastrow coefficients."""
+    s = wl.config(1 if dim == 3 else 3).systems[0]
+    g = np.random.default_rng([31, dim, seed])
+    pos = wl.random_positions(s, n, seed)
+    q = np.where(np.arange(n) % 4 == 3, 2.0, -1.0)
+    ja = g.uniform(-0.01, 0.01, 60)
+    return s, pos, q, ja
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_jastrow_derivs_finite_differences(oracle_lib, dim):
+    """grad_k J and lap_k J (pair form) against central differences of the
+    oracle's J value (itself pinned by the pair-form identity and the shell
+    populations): fourth-order stencils, h = 1e-3 bohr."""
+    s, pos, q, ja = jastrow_system(dim, 10, 1)
+    h = 1e-3
+
+    def J(p):
+        return oracle_lib.energy(s, p, q, jastrow_a=ja)["jastrow"]
+
+    for k in (0, 3, 7):
+        grad, lap = oracle_lib.jastrow_derivs(s, pos, q, k, ja)
+        j0 = J(pos)
+        fd_grad = np.zeros(dim)
+        fd_lap = 0.0
+        for d in range(dim):
+            f = {}
+            for m in (-2, -1, 1, 2):
+                p = pos.copy()
+                p[k, d] += m * h
+                f[m] = J(p)
+            fd_grad[d] = (f[-2] - 8 * f[-1] + 8 * f[1] - f[2]) / (12 * h)
+            fd_lap += (-f[-2] + 16 * f[-1] - 30 * j0 + 16 * f[1] - f[2]) / (12 * h * h)
+        scale = max(1.0, float(np.max(np.abs(grad))), abs(lap))
+        assert np.max(np.abs(grad - fd_grad)) <= 1e-8 * scale, (k, grad, fd_grad)
+        assert abs(lap - fd_lap) <= 1e-6 * scale, (k, lap, fd_lap)
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_jastrow_derivs_structure_factor_form(oracle_lib, dim):
+    """The pair-form derivatives equal the structure-factor form
+    grad_k J = -q_k sum_G a G Im(conj(rho) e_k), lap_k J = -q_k sum_G a |G|^2
+    (Re(conj(rho) e_k) - q_k) over the full G set, e_k = exp(i G.r_k), and the
+    gradients of all particles sum to zero (translation invariance)."""
+    s, pos, q, ja = jastrow_system(dim, 9, 2)
+    g, g2, shell = oracle_lib.gvectors(s)
+    a = np.where(shell < len(ja), ja[np.minimum(shell, len(ja) - 1)], 0.0)
+    pos3 = np.zeros((pos.shape[0], 3))
+    pos3[:, :dim] = pos
+    rho = oracle_lib.rho_at(s, pos, q, g)
+    total = np.zeros(dim)
+    for k in range(pos.shape[0]):
+        grad, lap = oracle_lib.jastrow_derivs(s, pos, q, k, ja)
+        ek = np.exp(1j * (g @ pos3[k]))
+        z = np.conj(rho) * ek
+        sf_grad = -q[k] * (a * z.imag) @ g[:, :dim]
+        sf_lap = -q[k] * np.sum(a * g2 * (z.real - q[k]))
+        scale = max(1.0, float(np.max(np.abs(sf_grad))), abs(sf_lap))
+        assert np.max(np.abs(grad - sf_grad)) <= 1e-11 * scale
+        assert abs(lap - sf_lap) <= 1e-11 * scale
+        total += grad
+    assert np.max(np.abs(total)) <= 1e-11 * max(1.0, scale)
+
+
+def test_run_derivs_at_proposed_configuration(oracle_lib):
+    """The move driver's derivative outputs are those of the proposed
+    configuration (moved particle at its proposal), accepted or not."""
+    cfg = wl.config(1)
+    b = wl.make_batch(cfg, walkers=1, moves=6)
+    s = cfg.systems[0]
+    acc = np.array([1, 0, 1, 0, 0, 1], dtype=np.uint8)
+    ja = np.random.default_rng(12).uniform(-0.01, 0.01, 50)
+    r = oracle_lib.run(s, b.walker_pos(0), b.k[:, 0], b.new_pos[:, 0], acc, jastrow_a=ja, derivs=True)
+    cur = b.walker_pos(0).copy()
+    for m in range(6):
+        k = int(b.k[m, 0])
+        prop = cur.copy()
+        prop[k] = b.new_pos[m, 0]
+        grad, lap = oracle_lib.jastrow_derivs(s, *oracle_lib.particles(s, prop), k, ja)
+        assert np.array_equal(r["jgrad"][m], grad) and r["jlap"][m] == lap
+        if acc[m]:
+            cur = prop

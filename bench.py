@@ -79,7 +79,7 @@ def traffic_from_profiles(form: str, shape: dict):
 
 
 def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_step: bool = True,
-             threads: int = 0):
+             threads: int = 0, n_parity: int = 64):
     import torch
     from paper_2507_02888_amd import ewald as ew
     cfg, b = batch_inputs["cfg"], batch_inputs["b"]
@@ -138,9 +138,13 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_
                for h, w in zip(hdr, (0, W // 2, W - 1)))
     d = delta.cpu().numpy()
     assert np.all(np.isfinite(d))
+    ns = min(W, n_parity)
     out = dict(elapsed=elapsed, ms_per_step=1e3 * elapsed / steps, energy_ms=float(np.mean(e_ms)),
                run_ms=float(np.mean(r_ms)), n_refresh=n_refresh_total, sample_delta=d[:4, 0].tolist(), tuning=tuning,
-               drift_max=max(h["drift_max"] for h in hdr))
+               drift_max=max(h["drift_max"] for h in hdr),
+               # the last timed step's outputs of walkers 0..ns-1, for the parity check
+               parity_sample=dict(energy=energy[:ns].cpu().numpy(), jastrow=jas[:ns].cpu().numpy(),
+                                  delta=d[:, :ns].copy(), djas=djas[:, :ns].cpu().numpy()))
     if not per_step:
         batch.close()
         s.close()
@@ -220,19 +224,100 @@ def other_workload(cfg_id: int, precision: int, steps: int = 2):
     return out
 
 
-def cpu_baseline(cfg, n_walkers: int, threads: int):
+def host_threads() -> int:
+    """Threads for the oracle: the OpenMP setting where the host sets one (the
+    GPU host's share of its cores), else every core this process may use."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, n_walkers: int, n_moves: int, threads: int):
+    """The FP64 oracle on the first n_walkers walkers of the workload, OpenMP
+    over walkers.  It runs twice: once with no moves (set-up, initial energy
+    and rho) and once with the n_moves-move sweep; the rate is the deltas of
+    the sweep over the difference of the two times.  Returns the rate and the
+    oracle's outputs (the same trajectory the GPU computes)."""
     import oracle
     from paper_2507_02888_amd import workloads as wl
-    b = wl.make_batch(cfg, walkers=n_walkers)
+    b = wl.make_batch(cfg, walkers=n_walkers, moves=n_moves)
     sysm = cfg.systems[0]
     pos = b.pos.reshape(n_walkers, sysm.n_mobile, sysm.dim)
     t0 = time.perf_counter()
+    oracle.run_batch(sysm, pos, b.k[:0], b.new_pos[:0], b.accept[:0], jastrow_a=b.jastrow_a, n_threads=threads)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
     r = oracle.run_batch(sysm, pos, b.k, b.new_pos, b.accept, jastrow_a=b.jastrow_a, n_threads=threads)
-    el = time.perf_counter() - t0
-    return dict(value=n_walkers * b.steps / el, unit="deltas/s", cores=int(r["threads"]), kind="oracle",
-                sample=f"{n_walkers} walkers x {b.steps} moves (energy + one sweep each) of the same "
-                       f"workload, FP64 oracle, OpenMP over walkers; {el:.1f} s wall",
-                seconds=el)
+    t_full = time.perf_counter() - t0
+    t_moves = max(t_full - t_setup, 1e-9)
+    return dict(value=n_walkers * b.steps / t_moves, unit="deltas/s", cores=int(r["threads"]), kind="oracle",
+                sample=f"{n_walkers} walkers x {b.steps} moves of the same workload (its first walkers, the "
+                       f"trajectory the GPU computes), FP64 oracle, OpenMP over walkers on {int(r['threads'])} "
+                       f"threads of a {cpu_model()}; sweep {t_moves:.1f} s wall (set-up and initial energies "
+                       f"{t_setup:.1f} s, timed apart and excluded)",
+                seconds=t_full + t_setup, cpu_model=cpu_model(), ref=r, n_walkers=n_walkers)
+
+
+U32 = 2.0 ** -24  # FP32 unit roundoff
+
+
+def mixed_djastrow_bound(system, jastrow_a, n_g_half: int) -> float:
+    """Bound on the FP32-mixed form's error in a Jastrow delta dJ, from its
+    arithmetic: t(G) = |rho + q d|^2 - |rho|^2 is formed in FP32 from FP32
+    phases (each within ~4 units of FP32 rounding, u), so |dt| <~ 16 u |q| |rho(G)|;
+    independent over the half set, the weighted sum sum_H a_s dt has a spread
+    of 16 u |q| (sum_H a_s^2 |rho|^2)^(1/2) <= 16 u |q| max|a| (N_H sum_i q_i^2)^(1/2)
+    for uncorrelated positions; four spreads bound the largest of many moves.
+    Unlike the energy weights, the a_s do not decay with |G|, so this exceeds
+    the 1e-5 of the energy deltas when N_H sum q^2 is large (N = 1024: ~7e-5).
+    At least 1e-5."""
+    q = np.concatenate([system.mobile_q, system.fixed_q])
+    a_max = 0.0 if jastrow_a is None else float(np.max(np.abs(jastrow_a)))
+    return max(1e-5, 64.0 * U32 * float(np.max(np.abs(system.mobile_q))) * a_max *
+               float(np.sqrt(n_g_half * np.sum(q * q))))
+
+
+def parity(form: str, got: dict, ref: dict, system, djas_bound: float = 1e-5) -> dict:
+    """Largest errors of the GPU outputs against the oracle on the same walkers
+    and trajectory, and whether they are within the form's bounds: FP64 1e-10
+    relative (to max(|E|, (alpha/sqrt(pi)) sum q^2)) on energies and deltas;
+    FP32-mixed 1e-6 relative on energies and J, 1e-5 Ha on each energy delta,
+    and `djas_bound` (mixed_djastrow_bound) on each Jastrow delta."""
+    q = np.concatenate([system.mobile_q, system.fixed_q])
+    e_scale = system.alpha / np.sqrt(np.pi) * float(np.sum(q * q))
+    n = got["energy"].shape[0]
+    e_ref = ref["e0"][:n, 4]
+    scale = np.maximum(np.abs(e_ref), e_scale)
+    rel_e = float(np.max(np.abs(got["energy"] - e_ref) / scale))
+    d_err = np.abs(got["delta"] - ref["delta"][:, :n])
+    abs_d = float(np.max(d_err))
+    rel_d = float(np.max(d_err / scale[None, :]))
+    jscale = np.maximum(1.0, np.abs(ref["j0"][:n]))
+    rel_j = float(np.max(np.abs(got["jastrow"] - ref["j0"][:n]) / jscale))
+    abs_dj = float(np.max(np.abs(got["djas"] - ref["djas"][:, :n])))
+    if form == "fp64":
+        ok = rel_e <= 1e-10 and rel_d <= 1e-10 and rel_j <= 1e-10 and abs_dj <= 1e-10 * float(np.min(jscale))
+        bounds = "energy, J: 1e-10 relative; delta, dJ: 1e-10 relative"
+    else:
+        ok = rel_e <= 1e-6 and abs_d <= 1e-5 and rel_j <= 1e-6 and abs_dj <= djas_bound
+        bounds = f"energy, J: 1e-6 relative; delta: 1e-5 Ha; dJ: {djas_bound:.3g} (FP32 rounding of the Jastrow sum)"
+    return dict(walkers=int(n), moves=int(got["delta"].shape[0]), max_rel_energy_err=rel_e,
+                max_abs_delta_err=abs_d, max_rel_delta_err=rel_d, max_rel_jastrow_err=rel_j,
+                max_abs_djastrow_err=abs_dj, bounds=bounds, ok=bool(ok))
 
 
 def main():
@@ -243,8 +328,9 @@ def main():
     ap.add_argument("--walkers", type=int, default=None, help="subset of the 8192 walkers (testing only)")
     ap.add_argument("--moves", type=int, default=None, help="subset of the 1024 moves (testing only)")
     ap.add_argument("--refresh-every", type=int, default=None)
-    ap.add_argument("--cpu-walkers", type=int, default=64)
-    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--cpu-walkers", type=int, default=64,
+                    help="walkers of the oracle's CPU baseline, which also serve the in-run parity check")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: the host's share of cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--threads", type=int, default=0,
@@ -294,7 +380,7 @@ def main():
     results = {}
     for form in args.forms.split(","):
         prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
-        r = run_form(prec, inputs, args.steps, args.warmup, K, threads=args.threads)
+        r = run_form(prec, inputs, args.steps, args.warmup, K, threads=args.threads, n_parity=args.cpu_walkers)
         flops_run = deltas_per_step * algorithmic_flops_per_delta(n_g, n_part) + \
             r["n_refresh"] * algorithmic_flops_per_rebuild(n_g, n_part)
         achieved = flops_run / (r["run_ms"] * 1e-3) / 1e12
@@ -332,8 +418,13 @@ def main():
                 others.append(other_workload(cid, prec))
 
     cpu = None
+    parity_ok = True
     if not args.no_cpu:
-        cpu = cpu_baseline(cfg, args.cpu_walkers, args.cpu_threads)
+        cpu = cpu_baseline(cfg, min(args.cpu_walkers, W), S, args.cpu_threads or host_threads())
+        for form, r in results.items():
+            r["parity"] = parity(form, r["parity_sample"], cpu["ref"], sysm,
+                                 mixed_djastrow_bound(sysm, b.jastrow_a, n_g))
+            parity_ok &= r["parity"]["ok"]
 
     head = results.get("mixed") or results[next(iter(results))]
     line = {
@@ -356,6 +447,7 @@ def main():
                    "refresh_every": K, "call": "ewald_energy_batch + ewald_run_moves_batch"},
         "roofline": head["roofline"],
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "parity": None if cpu is None else head.get("parity"),
         "energies_per_s": round(head["energies_per_s"], 1),
         "per_step_path_deltas_per_s": round(head["per_step_deltas_per_s"], 1),
     }
@@ -370,8 +462,12 @@ def main():
         f = results["fp64"]
         line["fp64"] = {"value": round(f["value"], 1), "unit": "deltas/s", "ms_per_step": round(f["ms_per_step"], 3),
                         "roofline": f["roofline"], "energies_per_s": round(f["energies_per_s"], 1),
-                        "per_step_path_deltas_per_s": round(f["per_step_deltas_per_s"], 1)}
+                        "per_step_path_deltas_per_s": round(f["per_step_deltas_per_s"], 1),
+                        "parity": f.get("parity")}
     print(json.dumps(line), flush=True)
+    if not parity_ok:
+        print("bench.py: GPU results differ from the oracle beyond the stated bounds", file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

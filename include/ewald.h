@@ -36,12 +36,15 @@
  *
  * Precision forms (Sec. 6.1: set-up tables always in double precision):
  *   EWALD_FP64        every step in FP64.
- *   EWALD_FP32_MIXED  phases exp(2 pi i frac(n.s)) in FP32 from FP64 fractional
- *                     coordinates, the erf part of phi in FP32, FP32 partial
- *                     sums with Kahan compensation; geometry (displacement,
- *                     minimum image, r^2, 1/r), constants and the running rho
- *                     in FP64, and rho rebuilt from the positions in FP64
- *                     every `refresh_every` accepted moves.
+ *   EWALD_FP32_MIXED  move deltas: phases exp(2 pi i frac(n.s)) in FP32 from
+ *                     FP64 fractional coordinates, the erf part of phi in FP32,
+ *                     FP32 partial sums with Kahan compensation; geometry
+ *                     (displacement, minimum image, r^2, 1/r), constants and
+ *                     the running rho in FP64, and rho rebuilt from the
+ *                     positions in FP64 every `refresh_every` accepted moves.
+ *                     Energies (ewald_energy_batch) are computed in FP64 as in
+ *                     the FP64 form: they add ~N^2/4 pair terms of one sign,
+ *                     where an FP32 bias of the pair function would add up.
  *
  * Conventions
  *   - Units: Hartree atomic units (bohr, Hartree).
@@ -116,8 +119,10 @@ typedef struct {
 
 /* Build the cell's tables on the host in FP64 (reciprocal lattice, G set,
  * shells, weights, fixed-ion structure factor, constants, minimum-image
- * candidates).  Touches no device; device copies are made by
- * ewald_batch_create.  Status: E_ARG, E_LATTICE, E_RCUT, E_GCUT, E_NOMEM. */
+ * candidates): the quantities of Sec. 2.2, Eqs. (2)-(6), that depend on the
+ * cell alone, set up once and kept in double precision (Sec. 6.1).  Touches
+ * no device; device copies are made by ewald_batch_create.  Status: E_ARG,
+ * E_LATTICE, E_RCUT, E_GCUT, E_NOMEM. */
 ewald_status ewald_setup(const ewald_sys_desc *desc, ewald_sys **out);
 
 /* Sizes and constants of a system.  Any output pointer may be NULL.
@@ -195,13 +200,17 @@ ewald_status ewald_move_delta_batch(ewald_batch *b, void *state, const int32_t *
                                     const double *new_pos, double *delta, double *djastrow,
                                     void *stream);
 
-/* Apply (accept[w] != 0) or drop (accept[w] == 0) each walker's pending move:
+/* The update step of a single-particle move (Sec. 2.1: after the accept/reject
+ * decision the configuration and its cached quantities are updated).
+ * Apply (accept[w] != 0) or drop (accept[w] == 0) each walker's pending move:
  * rho <- rho + delta in FP64, r_k <- r', counters; in the FP32-mixed form a
  * walker reaching refresh_every accepted moves gets rho rebuilt from its
  * positions in FP64.  E_STATE if no move is pending. */
 ewald_status ewald_accept_batch(ewald_batch *b, void *state, const uint8_t *accept, void *stream);
 
-/* n_steps consecutive proposals per walker in one launch, rho kept on chip.
+/* n_steps consecutive proposals per walker in one launch, rho kept on chip: a
+ * sequence of the single-particle moves of Sec. 2.1, each with its energy
+ * change as defined for ewald_move_delta_batch (Sec. 2.2, Eqs. (2)-(6)).
  * Same results as n_steps pairs of ewald_move_delta_batch + ewald_accept_batch
  * (accept decisions must therefore be known in advance, as when the Ewald
  * energy is evaluated after a sweep of moves).
@@ -212,8 +221,34 @@ ewald_status ewald_run_moves_batch(ewald_batch *b, void *state, int n_steps, con
                                    const double *new_pos, const uint8_t *accept, double *delta,
                                    double *djastrow, void *stream);
 
-/* Launch shape of ewald_run_moves_batch (the batching of Sec. 5.1, where the
- * paper hand-tunes gang and vector sizes).  One workgroup serves one walker;
+/* Jastrow derivatives (Sec. 2.3, Eq. (9); the values and derivatives of the
+ * p term are what Sec. 5.2 offloads, and the kinetic energy and drift of QMC
+ * need the gradient and the Laplacian, Sec. 2.1).  The same calls as
+ * ewald_move_delta_batch and ewald_run_moves_batch, which also return, for
+ * each proposed move of particle k to r', the gradient and the Laplacian of
+ * J with respect to r_k at the proposed configuration (particle k at r',
+ * whether or not the move is then accepted):
+ *   grad_k J = -2 q_k sum_{G in H} a_s(G) G Im(conj(rho') exp(iG.r'))
+ *   lap_k J  = -2 q_k sum_{G in H} a_s(G) |G|^2 [Re(conj(rho') exp(iG.r')) - q_k]
+ *   rho' = rho + q_k (exp(iG.r') - exp(iG.r_k))
+ * (for unit charges these are the derivatives of 2 sum_{j != k} p(r_k - r_j)).
+ *   jgrad  device out, Cartesian: [n_walkers][dim] (move_delta) or
+ *          [n_steps][n_walkers][dim] (run_moves)
+ *   jlap   device out: [n_walkers] or [n_steps][n_walkers]
+ * Both NULL: exactly ewald_move_delta_batch / ewald_run_moves_batch.  An
+ * invalid k gives NaN derivatives.  Status as for those calls, plus E_ARG if
+ * only one of jgrad/jlap is given or the batch has no Jastrow coefficients.
+ * The FP32-mixed form computes z = conj(rho') exp(iG.r') in FP32 and sums
+ * in FP64 across segments. */
+ewald_status ewald_move_delta_grad_batch(ewald_batch *b, void *state, const int32_t *k,
+                                         const double *new_pos, double *delta, double *djastrow,
+                                         double *jgrad, double *jlap, void *stream);
+ewald_status ewald_run_moves_grad_batch(ewald_batch *b, void *state, int n_steps, const int32_t *k,
+                                        const double *new_pos, const uint8_t *accept, double *delta,
+                                        double *djastrow, double *jgrad, double *jlap, void *stream);
+
+/* Launch shape of ewald_run_moves_batch (the batching of Sec. 5.1; the paper
+ * tunes gang and vector sizes by hand, Sec. 3.3).  One workgroup serves one walker;
  *   threads        workgroup size, which fixes segments of 4 G per thread and
  *                  particles per thread: 0 = default for the largest segment
  *                  count s of the batch (s <= 512: 256; s <= 1024: 1024 or
@@ -235,8 +270,10 @@ ewald_status ewald_batch_set_tuning(ewald_batch *b, int threads, int chunk, int 
 ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, int *general_frame,
                                     int *fused);
 
-/* Time every launch shape of ewald_run_moves_batch on this batch and keep
- * the fastest (ewald_batch_set_tuning); shapes within 8 % of the fastest
+/* The launch-shape choice that Sec. 3.3 makes by hand for each GPU (gang and
+ * vector sizes), made by measurement: time every launch shape of
+ * ewald_run_moves_batch on this batch and keep the fastest
+ * (ewald_batch_set_tuning); shapes within 8 % of the fastest
  * are timed twice more, interleaved, and compared by their best time.  The
  * probe runs n_moves (1..4096)
  * proposals per walker, every other one accepted, on a device copy of

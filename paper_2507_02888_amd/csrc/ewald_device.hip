@@ -167,11 +167,22 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
 // ---------------------------------------------------------------------------
 // Move delta: dE and dJ of moving particle k to new_pos; records the pending
 // move.  rho is streamed from the state once (slot-planar, coalesced).
-template <int DIM, bool MIXED, int PD>
+//
+// DER: also the gradient and Laplacian of J with respect to the moved
+// particle at the proposed configuration (Sec. 2.3, Eq. (9); Sec. 5.2 offloads
+// the values and derivatives of the p term).  With rho' = rho + q (e' - e_old)
+// the proposed structure factor and z = conj(rho') e',
+//   grad_k J = -2 q sum_H a G Im z,   lap_k J = -2 q sum_H a |G|^2 (Re z - q).
+// G = sum_d n_d b_d, so the gradient is accumulated in reduced coordinates,
+// S_d = sum_H a n_d Im z (per segment: the last index runs n_last + j), and
+// turned into Cartesian components once per move; |G|^2 is constant on a
+// shell and comes with a from the shell table.
+template <int DIM, bool MIXED, int PD, bool DER>
 __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ systems,
                                                  const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                                  const int32_t* __restrict__ kk, const double* __restrict__ new_pos,
-                                                 double* __restrict__ delta, double* __restrict__ djas, int lds_tab) {
+                                                 double* __restrict__ delta, double* __restrict__ djas,
+                                                 double* __restrict__ jgrad, double* __restrict__ jlap, int lds_tab) {
   using R = typename std::conditional<MIXED, float, double>::type;
   using WT2 = cplx<R>;  // (weight, Jastrow coefficient) in the form's precision
   extern __shared__ double smem[];
@@ -184,10 +195,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
   const double* spos = reinterpret_cast<const double*>(st + HDR_BYTES);
   const double* rho = reinterpret_cast<const double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
-  double* red = smem;
-  cplx<R>* to = reinterpret_cast<cplx<R>*>(smem + 16);
+  double* red = smem;  // [NV][4]
+  cplx<R>* to = reinterpret_cast<cplx<R>*>(smem + 32);
   cplx<R>* tn = to + DIM * tbl;
-  WT2* ltab = reinterpret_cast<WT2*>(smem + 16 + lds_tab);  // shell table (when it fits)
+  WT2* ltab = reinterpret_cast<WT2*>(smem + 32 + lds_tab);  // shell table (when it fits)
+  R* ltab2 = reinterpret_cast<R*>(ltab + S->n_wtab);      // a |G|^2 per shell (DER)
   const double2* __restrict__ rho2 = reinterpret_cast<const double2*>(rho);
 
   const int k = kk[w];
@@ -195,6 +207,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
     if (tid == 0) {
       delta[w] = NAN;
       if (djas) djas[w] = NAN;
+      if (DER) {
+        for (int d = 0; d < DIM; ++d) jgrad[size_t(w) * DIM + d] = NAN;
+        jlap[w] = NAN;
+      }
       hdr->pending_k = -1;
     }
     return;
@@ -210,7 +226,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
     scur[j] = S->slot_shell[g];
   }
   if (wlds)
-    for (int i = tid; i < S->n_wtab; i += BLOCK) ltab[i] = {R(S->wa_tab[2 * i]), R(S->wa_tab[2 * i + 1])};
+    for (int i = tid; i < S->n_wtab; i += BLOCK) {
+      ltab[i] = {R(S->wa_tab[2 * i]), R(S->wa_tab[2 * i + 1])};
+      if (DER) ltab2[i] = R(S->jg2_tab[i]);
+    }
   double sn[DIM], so[DIM];
   {
     double r[DIM];
@@ -232,7 +251,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
   // once to the sums, and a neutral particle's move changes nothing
   double accE64 = 0.0, accJ64 = 0.0;
   Kahan accE32, accJ32;
+  double dS[DIM], dL = 0.0;  // DER: S_d and sum_H a |G|^2 Re z
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) dS[d] = 0.0;
   const R c2q = qk != 0.0 ? R(2.0 / qk) : R(0);
+  const R qr = R(qk);
   for (int s = tid; s < nseg && qk != 0.0; s += BLOCK) {
     // prefetch the next segment while this one is consumed
     const int s2 = s + BLOCK < nseg ? s + BLOCK : s;
@@ -247,18 +270,21 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
     const uint32_t pn = S->seg_n[s];
     SegWalk<R> wo(anchor<DIM, R>(to, pn, nm), uo), wn(anchor<DIM, R>(tn, pn, nm), un);
     float segE = 0.f, segJ = 0.f;  // mixed form: FP32 sums per segment, compensated across segments
+    R sT = R(0), sT2 = R(0), sL = R(0);  // DER: per-segment sums of a Im z, j a Im z, a |G|^2 Re z
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
       const cplx<R> eo = wo.cur, en = wn.cur;
       const size_t g = size_t(j) * nseg + s;
-      R wg, aj;
+      R wg, aj, ag2 = R(0);
       if (wlds) {
         const WT2 wa = ltab[scur[j]];
         wg = wa.x;
         aj = wa.y;
+        if (DER) ag2 = ltab2[scur[j]];
       } else {
         wg = R(wt[g]);
         aj = ja ? R(ja[g]) : R(0);
+        if (DER) ag2 = R(S->jg2_tab[scur[j]]);
       }
       const R dx = en.x - eo.x, dy = en.y - eo.y;
       const R ux = fma(c2q, R(rcur[j].x), dx), uy = fma(c2q, R(rcur[j].y), dy);
@@ -270,6 +296,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
         accE64 = fma(double(wg), double(t), accE64);
         if (ja) accJ64 = fma(double(aj), double(t), accJ64);
       }
+      if (DER) {
+        const R px = fma(qr, dx, R(rcur[j].x)), py = fma(qr, dy, R(rcur[j].y));  // rho'
+        const R im = fma(px, en.y, -(py * en.x)), re = fma(px, en.x, py * en.y);
+        const R ti = aj * im;
+        sT += ti;
+        sT2 = fma(R(j), ti, sT2);
+        sL = fma(ag2, re, sL);
+      }
       if (j + 1 < SEG) {
         wo.step(j);
         wn.step(j);
@@ -278,6 +312,12 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
     if (MIXED) {
       accE32.add(segE);
       if (ja) accJ32.add(segJ);
+    }
+    if (DER) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) dS[d] = fma(double(sT), double(unpack_n(pn, d)), dS[d]);
+      dS[DIM - 1] += double(sT2);
+      dL += double(sL);
     }
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
@@ -288,11 +328,29 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
   // real space
   const double er = real_move<DIM, MIXED, PD, BLOCK>(sn, so, k, spos, S->mobile_q, n, S);
   const double q2 = qk * qk;
-  double v[2] = {q2 * (MIXED ? accE32.value() : accE64) + qk * er, q2 * (MIXED ? accJ32.value() : accJ64)};
-  block_sum<2>(v, red);
+  constexpr int NV = DER ? 3 + DIM : 2;
+  double v[NV];
+  v[0] = q2 * (MIXED ? accE32.value() : accE64) + qk * er;
+  v[1] = q2 * (MIXED ? accJ32.value() : accJ64);
+  if (DER) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) v[2 + d] = dS[d];
+    v[NV - 1] = dL;
+  }
+  block_sum<NV>(v, red);
   if (tid == 0) {
     delta[w] = v[0];
     if (djas) djas[w] = v[1];
+    if (DER) {
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) {
+        double gx = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) gx = fma(v[2 + d], S->B[d * 3 + e], gx);
+        jgrad[size_t(w) * DIM + e] = -2.0 * qk * gx;
+      }
+      jlap[w] = -2.0 * qk * v[NV - 1] + 2.0 * q2 * S->jlap_c;
+    }
     hdr->pending_k = k;
 #pragma unroll
     for (int d = 0; d < 3; ++d) hdr->pending_s[d] = d < DIM ? sn[d] : 0.0;
@@ -459,17 +517,27 @@ int energy_dim(const LaunchBatch& b, const double* pos, char* state, double* ene
 
 template <int DIM, bool MIXED>
 int delta_dim(const LaunchBatch& b, char* state, const int32_t* k, const double* new_pos, double* delta,
-              double* djas, void* stream) {
+              double* djas, double* jgrad, double* jlap, void* stream) {
   using R = typename std::conditional<MIXED, float, double>::type;
   const size_t mtab = size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
   const int lds_tab = even(int((mtab + 7) / 8));  // in doubles
-  const size_t lds = 16 * 8 + size_t(lds_tab) * 8 + size_t(b.max_wtab) * sizeof(cplx<R>);
-  if (b.poly_deg <= 16)
-    hipLaunchKernelGGL((k_delta<DIM, MIXED, 16>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
-                       b.d_sys, b.d_walk, state, k, new_pos, delta, djas, lds_tab);
-  else
-    hipLaunchKernelGGL((k_delta<DIM, MIXED, 32>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream),
-                       b.d_sys, b.d_walk, state, k, new_pos, delta, djas, lds_tab);
+  const bool der = jgrad != nullptr;
+  const size_t lds = 32 * 8 + size_t(lds_tab) * 8 + size_t(b.max_wtab) * (sizeof(cplx<R>) + (der ? sizeof(R) : 0));
+#define EW_DELTA(PD, DER)                                                                                     \
+  hipLaunchKernelGGL((k_delta<DIM, MIXED, PD, DER>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), \
+                     b.d_sys, b.d_walk, state, k, new_pos, delta, djas, jgrad, jlap, lds_tab)
+  if (b.poly_deg <= 16) {
+    if (der)
+      EW_DELTA(16, true);
+    else
+      EW_DELTA(16, false);
+  } else {
+    if (der)
+      EW_DELTA(32, true);
+    else
+      EW_DELTA(32, false);
+  }
+#undef EW_DELTA
   return last_launch();
 }
 
@@ -491,13 +559,13 @@ int accept_dim(const LaunchBatch& b, char* state, const uint8_t* accept, void* s
 
 int run_any(const LaunchBatch& b, const RunArgs& a) {
   if (!b.all_wtab_lds) return RUN_NO_FIT;
-  const bool j = b.has_jastrow != 0;
+  const int jm = b.has_jastrow == 0 ? 0 : a.jgrad ? 2 : 1;
   if (b.dim == 3) {
-    if (b.mixed) return j ? run_d3_mixed_j1(b, a) : run_d3_mixed_j0(b, a);
-    return j ? run_d3_fp64_j1(b, a) : run_d3_fp64_j0(b, a);
+    if (b.mixed) return jm == 2 ? run_d3_mixed_j2(b, a) : jm ? run_d3_mixed_j1(b, a) : run_d3_mixed_j0(b, a);
+    return jm == 2 ? run_d3_fp64_j2(b, a) : jm ? run_d3_fp64_j1(b, a) : run_d3_fp64_j0(b, a);
   }
-  if (b.mixed) return j ? run_d2_mixed_j1(b, a) : run_d2_mixed_j0(b, a);
-  return j ? run_d2_fp64_j1(b, a) : run_d2_fp64_j0(b, a);
+  if (b.mixed) return jm == 2 ? run_d2_mixed_j2(b, a) : jm ? run_d2_mixed_j1(b, a) : run_d2_mixed_j0(b, a);
+  return jm == 2 ? run_d2_fp64_j2(b, a) : jm ? run_d2_fp64_j1(b, a) : run_d2_fp64_j0(b, a);
 }
 
 }  // namespace
@@ -509,11 +577,11 @@ int launch_energy(const LaunchBatch& b, const double* pos, char* state, double* 
 }
 
 int launch_delta(const LaunchBatch& b, char* state, const int32_t* k, const double* new_pos, double* delta,
-                 double* djas, void* stream) {
-  if (b.dim == 3) return b.mixed ? delta_dim<3, true>(b, state, k, new_pos, delta, djas, stream)
-                                 : delta_dim<3, false>(b, state, k, new_pos, delta, djas, stream);
-  return b.mixed ? delta_dim<2, true>(b, state, k, new_pos, delta, djas, stream)
-                 : delta_dim<2, false>(b, state, k, new_pos, delta, djas, stream);
+                 double* djas, double* jgrad, double* jlap, void* stream) {
+  if (b.dim == 3) return b.mixed ? delta_dim<3, true>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream)
+                                 : delta_dim<3, false>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream);
+  return b.mixed ? delta_dim<2, true>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream)
+                 : delta_dim<2, false>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream);
 }
 
 int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void* stream) {
@@ -522,14 +590,14 @@ int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void
 }
 
 int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, const double* new_pos,
-               const uint8_t* accept, double* delta, double* djas, void* stream) {
-  int rc = run_any(b, RunArgs{state, n_steps, k, new_pos, accept, delta, djas, stream, nullptr});
+               const uint8_t* accept, double* delta, double* djas, double* jgrad, double* jlap, void* stream) {
+  int rc = run_any(b, RunArgs{state, n_steps, k, new_pos, accept, delta, djas, jgrad, jlap, stream, nullptr});
   if (rc != RUN_NO_FIT) return rc;
   // a shell table or walker too large for LDS: the same sequence through the per-step kernels
   const size_t W = size_t(b.n_walkers);
   for (int m = 0; m < n_steps; ++m) {
     rc = launch_delta(b, state, k + m * W, new_pos + m * W * b.dim, delta + m * W, djas ? djas + m * W : nullptr,
-                      stream);
+                      jgrad ? jgrad + m * W * b.dim : nullptr, jlap ? jlap + m * W : nullptr, stream);
     if (!rc) rc = launch_accept(b, state, accept + m * W, stream);
     if (rc) return rc;
   }
@@ -538,7 +606,8 @@ int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k,
 
 void plan_run(const LaunchBatch& b, RunPlan* plan) {
   *plan = RunPlan{};
-  if (run_any(b, RunArgs{nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, plan}) != 0) *plan = RunPlan{};
+  if (run_any(b, RunArgs{nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, plan}) != 0)
+    *plan = RunPlan{};
 }
 
 bool run_threads_valid(int max_n_seg, int threads) {
@@ -554,11 +623,11 @@ int time_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, c
     (void)hipEventDestroy(e0);
     return int(hipErrorOutOfMemory);
   }
-  int rc = launch_run(b, state, n_steps, k, new_pos, accept, delta, nullptr, stream);  // warm-up
+  int rc = launch_run(b, state, n_steps, k, new_pos, accept, delta, nullptr, nullptr, nullptr, stream);  // warm-up
   float best = 0.f;
   for (int r = 0; r < reps && !rc; ++r) {
     rc = int(hipEventRecord(e0, as_stream(stream)));
-    if (!rc) rc = launch_run(b, state, n_steps, k, new_pos, accept, delta, nullptr, stream);
+    if (!rc) rc = launch_run(b, state, n_steps, k, new_pos, accept, delta, nullptr, nullptr, nullptr, stream);
     if (!rc) rc = int(hipEventRecord(e1, as_stream(stream)));
     if (!rc) rc = int(hipEventSynchronize(e1));
     float ms = 0.f;

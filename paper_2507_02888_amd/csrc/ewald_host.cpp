@@ -326,6 +326,7 @@ struct ewald_sys {
   std::vector<int32_t> slot_n;       // slot-planar [n_slots][3]
   std::vector<double> w, ja;         // slot-planar [n_slots]
   std::vector<int32_t> shell;        // slot-planar, -1 for padding
+  std::vector<double> shell_g2;      // |G|^2 of each shell
   std::vector<double> rho_fix;       // slot-planar [n_slots][2]
   std::vector<double> fixed_s, fixed_q, mobile_q;
   std::vector<double> cand_cart;     // [n_cand][3] candidate offsets, caller's frame
@@ -544,6 +545,7 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   int nmax[3] = {0, 0, 0};
   for (auto& g : half)
     for (int d = 0; d < dim; ++d) nmax[d] = std::max(nmax[d], std::abs(g.n[d]));
+  double jlap_c = 0.0;  // sum over the half set of a_s(G) |G|^2
   for (int s = 0; s < n_seg; ++s) {
     const Seg& sg = segs[s];
     S->seg_n[s] = pack_n(sg.n[0], sg.n[1], sg.n[2]);
@@ -560,8 +562,10 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
       int sh = int(std::lower_bound(shells.begin(), shells.end(), g2 * (1.0 - 1e-9)) - shells.begin());
       S->shell[slot] = sh;
       S->ja[slot] = (sh < desc->n_jastrow) ? desc->jastrow_a[sh] : 0.0;
+      jlap_c += S->ja[slot] * g2;
     }
   }
+  S->shell_g2 = shells;
 
   // ---- charges, fixed ions ----
   S->mobile_q.assign(desc->mobile_q, desc->mobile_q + desc->n_mobile);
@@ -700,6 +704,8 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   for (int i = 0; i <= POLY_MAX; ++i) D.p64[i] = i <= deg64 ? p64[i] : 0.0;
   for (int i = 0; i <= POLY32_MAX; ++i) D.p32[i] = i <= deg32 ? float(p32[i]) : 0.0f;
   D.e_const = S->e_const;
+  for (int t = 0; t < 9; ++t) D.B[t] = Bm[t];
+  D.jlap_c = jlap_c;
   // candidate offsets in the rotated frame: c . Lrot
   for (int c = 0; c < n_cand; ++c) {
     int ci[3] = {0, 0, 0};
@@ -819,7 +825,14 @@ ewald_status upload_sys(ewald_sys* s, int device) {
     wa[2 * size_t(sh) + 1] = s->ja[g];
     if (sh16) sl[g] = uint16_t(sh);
   }
+  // a_s |G_s|^2 per shell for the Jastrow Laplacian
+  std::vector<double> jg2(size_t(n_wtab), 0.0);
+  for (size_t g = 0; g < ns; ++g) {
+    const int sh = s->shell[g];
+    if (sh >= 0) jg2[size_t(sh)] = s->ja[g] * s->shell_g2[size_t(sh)];
+  }
   const size_t o_wa = take(wa.size() * 8);
+  const size_t o_jg = take(jg2.size() * 8);
   const size_t o_sl = take(sl.size() * 2);
   std::vector<char> host(off, 0);
   std::memcpy(host.data() + o_seg, s->seg_n.data(), s->seg_n.size() * 4);
@@ -830,6 +843,7 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   if (!s->fixed_q.empty()) std::memcpy(host.data() + o_fq, s->fixed_q.data(), s->fixed_q.size() * 8);
   std::memcpy(host.data() + o_mq, s->mobile_q.data(), s->mobile_q.size() * 8);
   std::memcpy(host.data() + o_wa, wa.data(), wa.size() * 8);
+  std::memcpy(host.data() + o_jg, jg2.data(), jg2.size() * 8);
   std::memcpy(host.data() + o_sl, sl.data(), sl.size() * 2);
   void* d = nullptr;
   int rc = dev_alloc(&d, off);
@@ -849,6 +863,7 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   D.fixed_q = reinterpret_cast<const double*>(base + o_fq);
   D.mobile_q = reinterpret_cast<const double*>(base + o_mq);
   D.wa_tab = reinterpret_cast<const double*>(base + o_wa);
+  D.jg2_tab = reinterpret_cast<const double*>(base + o_jg);
   D.slot_shell = reinterpret_cast<const uint16_t*>(base + o_sl);
   D.n_wtab = n_wtab;
   D.wtab_lds = (sh16 && n_wtab <= WTAB_MAX) ? 1 : 0;
@@ -998,16 +1013,24 @@ ewald_status ewald_energy_batch(ewald_batch* b, const double* pos, void* state, 
   return check_state(b, state, 0, 1);
 }
 
+ewald_status ewald_move_delta_grad_batch(ewald_batch* b, void* state, const int32_t* k, const double* new_pos,
+                                         double* delta, double* djastrow, double* jgrad, double* jlap,
+                                         void* stream) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (!state || !k || !new_pos || !delta) return fail(EWALD_E_ARG, "state, k, new_pos and delta must be non-NULL");
+  if ((jgrad == nullptr) != (jlap == nullptr)) return fail(EWALD_E_ARG, "jgrad and jlap must both be given or both NULL");
+  if (jgrad && !b->lb.has_jastrow) return fail(EWALD_E_ARG, "Jastrow derivatives need Jastrow coefficients");
+  ewald_status st = check_state(b, state, 1, -1);
+  if (st != EWALD_OK) return st;
+  int rc = launch_delta(b->lb, static_cast<char*>(state), k, new_pos, delta, djastrow, jgrad, jlap, stream);
+  if (rc) return launch_status(rc, "move_delta");
+  return check_state(b, state, 0, 2);
+}
+
 ewald_status ewald_move_delta_batch(ewald_batch* b, void* state, const int32_t* k,
                                     const double* new_pos, double* delta, double* djastrow,
                                     void* stream) {
-  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
-  if (!state || !k || !new_pos || !delta) return fail(EWALD_E_ARG, "state, k, new_pos and delta must be non-NULL");
-  ewald_status st = check_state(b, state, 1, -1);
-  if (st != EWALD_OK) return st;
-  int rc = launch_delta(b->lb, static_cast<char*>(state), k, new_pos, delta, djastrow, stream);
-  if (rc) return launch_status(rc, "move_delta");
-  return check_state(b, state, 0, 2);
+  return ewald_move_delta_grad_batch(b, state, k, new_pos, delta, djastrow, nullptr, nullptr, stream);
 }
 
 ewald_status ewald_accept_batch(ewald_batch* b, void* state, const uint8_t* accept, void* stream) {
@@ -1020,20 +1043,29 @@ ewald_status ewald_accept_batch(ewald_batch* b, void* state, const uint8_t* acce
   return check_state(b, state, 0, 1);
 }
 
-ewald_status ewald_run_moves_batch(ewald_batch* b, void* state, int n_steps, const int32_t* k,
-                                   const double* new_pos, const uint8_t* accept, double* delta,
-                                   double* djastrow, void* stream) {
+ewald_status ewald_run_moves_grad_batch(ewald_batch* b, void* state, int n_steps, const int32_t* k,
+                                        const double* new_pos, const uint8_t* accept, double* delta,
+                                        double* djastrow, double* jgrad, double* jlap, void* stream) {
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (n_steps < 0) return fail(EWALD_E_ARG, "n_steps must be >= 0");
   if (!state) return fail(EWALD_E_ARG, "state must be non-NULL");
+  if ((jgrad == nullptr) != (jlap == nullptr)) return fail(EWALD_E_ARG, "jgrad and jlap must both be given or both NULL");
+  if (jgrad && !b->lb.has_jastrow) return fail(EWALD_E_ARG, "Jastrow derivatives need Jastrow coefficients");
   ewald_status st = check_state(b, state, 3, -1);
   if (st != EWALD_OK) return st;
   if (n_steps == 0) return EWALD_OK;
   if (!k || !new_pos || !accept || !delta)
     return fail(EWALD_E_ARG, "k, new_pos, accept and delta must be non-NULL");
-  int rc = launch_run(b->lb, static_cast<char*>(state), n_steps, k, new_pos, accept, delta, djastrow, stream);
+  int rc = launch_run(b->lb, static_cast<char*>(state), n_steps, k, new_pos, accept, delta, djastrow, jgrad, jlap,
+                      stream);
   if (rc) return launch_status(rc, "run_moves");
   return EWALD_OK;
+}
+
+ewald_status ewald_run_moves_batch(ewald_batch* b, void* state, int n_steps, const int32_t* k,
+                                   const double* new_pos, const uint8_t* accept, double* delta,
+                                   double* djastrow, void* stream) {
+  return ewald_run_moves_grad_batch(b, state, n_steps, k, new_pos, accept, delta, djastrow, nullptr, nullptr, stream);
 }
 
 ewald_status ewald_batch_set_tuning(ewald_batch* b, int threads, int chunk, int general_frame) {

@@ -71,6 +71,10 @@ struct DevSys {
   double ibox[3];
   double cw[MAX_COSET][3];  // box[d] where the coset has a half-box offset along d, else 0
   double cc[MAX_COSET];     // sum over those d of box[d]^2 / 4 (+inf: no coset)
+  // Jastrow derivatives: reciprocal lattice rows b_d (G = sum_d n_d b_d) and
+  // jlap_c = sum_{G in H} a_s(G) |G|^2
+  double B[9];
+  double jlap_c;
   // erf(alpha r)/(alpha r) = sum_i p64[i] t^i for r < r_cut (p32: FP32 copy of lower accuracy)
   double p64[POLY_MAX + 1];
   float p32[POLY32_MAX + 1];
@@ -81,6 +85,7 @@ struct DevSys {
   const double* rho_fix;     // [SEG * n_seg][2] fixed-ion structure factor
   const uint16_t* slot_shell;  // [SEG * n_seg] index into wa_tab (n_wtab - 1 for padding)
   const double* wa_tab;      // [n_wtab][2] (weight, Jastrow coefficient) per shell
+  const double* jg2_tab;     // [n_wtab] Jastrow coefficient times |G|^2 per shell (0 for padding)
   int n_wtab;                // n_shells + 1 (a zero entry for padding slots)
   int wtab_lds;              // 1 if n_wtab <= WTAB_MAX: the fused kernel reads wa_tab from LDS
   const double* fixed_s;     // [n_fixed][dim] wrapped fractional ion positions
@@ -152,12 +157,15 @@ struct RunPlan {
 // Each returns 0 on success or the hipError_t of the failed launch.
 int launch_energy(const LaunchBatch& b, const double* pos, char* state, double* energy,
                   double* jastrow, void* stream);
+// jgrad/jlap (both or neither): gradient [W][dim] ([S][W][dim] for launch_run)
+// and Laplacian of the Jastrow value with respect to the moved particle at the
+// proposed configuration.
 int launch_delta(const LaunchBatch& b, char* state, const int32_t* k, const double* new_pos,
-                 double* delta, double* djastrow, void* stream);
+                 double* delta, double* djastrow, double* jgrad, double* jlap, void* stream);
 int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void* stream);
 int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k,
                const double* new_pos, const uint8_t* accept, double* delta, double* djastrow,
-               void* stream);
+               double* jgrad, double* jlap, void* stream);
 
 void plan_run(const LaunchBatch& b, RunPlan* plan);
 bool run_threads_valid(int max_n_seg, int threads);

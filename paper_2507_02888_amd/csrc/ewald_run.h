@@ -33,6 +33,7 @@ namespace ewald {
 struct RunLds {
   // byte offsets into dynamic LDS; positions start at 0
   uint32_t q, red, wtab, ctab, sn, so, xn, xo, c2q, part, k, acc, cnt;
+  uint32_t wtab2, part2;  // Jastrow derivatives: a |G|^2 per shell, and the per-move partial sums
   uint32_t rcopy;  // 0, or the LDS copy of the running rho during a rebuild
   int ch;     // moves per chunk
   int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
@@ -41,12 +42,19 @@ struct RunLds {
 // At least two waves per SIMD for workgroups of up to 512 threads (the
 // register budget stays within 256 per lane; without the bound the compiler
 // may take accumulation registers as well, which leaves one wave per SIMD).
-template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO, bool XTRA>
+// JM: Jastrow mode, 0 = none, 1 = J and dJ, 2 = also the gradient and the
+// Laplacian of J with respect to the moved particle at each proposed
+// configuration (as in k_delta: accumulated as S_d = sum_H a n_d Im z and
+// sum_H a |G|^2 Re z, z = conj(rho') e').
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA>
 __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
                                             const double* __restrict__ new_pos, const uint8_t* __restrict__ accept,
-                                            double* __restrict__ delta, double* __restrict__ djas, RunLds L) {
+                                            double* __restrict__ delta, double* __restrict__ djas,
+                                            double* __restrict__ jgrad, double* __restrict__ jlap, RunLds L) {
+  constexpr bool JAS = JM > 0, DER = JM == 2;
+  constexpr int NDV = DIM + 1;  // derivative partial sums per move: S_0 .. S_{DIM-1}, L
   using R = typename std::conditional<MIXED, float, double>::type;
   using WT = R;          // the mixed form multiplies weights with FP32 terms
   using WT2 = cplx<WT>;  // (weight, Jastrow coefficient)
@@ -76,6 +84,8 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
   double* st_xo = reinterpret_cast<double*>(lds + L.xo);
   double* st_c2q = reinterpret_cast<double*>(lds + L.c2q);  // 2 / q_k of each move (0 for q_k = 0)
   double* st_part = reinterpret_cast<double*>(lds + L.part);  // [CH][NW][4 rows][2]
+  double* st_part2 = reinterpret_cast<double*>(lds + L.part2);  // DER: [CH][NW][4 rows][NDV]
+  WT* ltab2 = reinterpret_cast<WT*>(lds + L.wtab2);              // DER: a |G|^2 per shell
   int* st_k = reinterpret_cast<int*>(lds + L.k);
   int* st_acc = reinterpret_cast<int*>(lds + L.acc);
   int* st_cnt = reinterpret_cast<int*>(lds + L.cnt);
@@ -83,7 +93,10 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
   for (int i = tid; i < n * DIM; i += NT) lpos[i] = spos[i];
   for (int i = tid; i < n; i += NT) lq[i] = S->mobile_q[i];
   // every system of the batch has its shell table in LDS (checked by the launcher)
-  for (int i = tid; i < S->n_wtab; i += NT) ltab[i] = {WT(S->wa_tab[2 * i]), WT(S->wa_tab[2 * i + 1])};
+  for (int i = tid; i < S->n_wtab; i += NT) {
+    ltab[i] = {WT(S->wa_tab[2 * i]), WT(S->wa_tab[2 * i + 1])};
+    if (DER) ltab2[i] = WT(S->jg2_tab[i]);
+  }
   int counter = hdr->counter;
   int n_acc = hdr->n_accepts, n_ref = hdr->n_refresh;
   double drift = hdr->drift_max;
@@ -203,6 +216,9 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
     for (int mm = 0; mm < len; ++mm) {
       const int k = st_k[mm];
       double v0 = 0.0, v1 = 0.0;
+      double dv[DER ? NDV : 1];  // DER: this thread's S_d and a |G|^2 Re z sums
+#pragma unroll
+      for (int d = 0; d < (DER ? NDV : 1); ++d) dv[d] = 0.0;
       if (k >= 0) {  // uniform
         const bool acc = st_acc[mm] != 0;
         const double qk = lq[k];
@@ -226,10 +242,12 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
             if (tid + i * NT < nseg) {
               SegWalk<R> wo(anchor<DIM, R>(to, an[i], nm), uo), wn(anchor<DIM, R>(tn, an[i], nm), un);
               float segE = 0.f, segJ = 0.f;
+              R sT = R(0), sT2 = R(0), sL = R(0);  // DER: sums of a Im z, j a Im z, a |G|^2 Re z
 #pragma unroll
               for (int j = 0; j < SEG; ++j) {
                 const cplx<R> eo = wo.cur, en = wn.cur;
-                const WT2 wa = ld_at_byte(ltab, (shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu);
+                const uint32_t off = (shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                const WT2 wa = ld_at_byte(ltab, off);
                 const R dx = en.x - eo.x, dy = en.y - eo.y;
                 const R ux = fma(c2q, R(rv[i][j].x), dx), uy = fma(c2q, R(rv[i][j].y), dy);
                 const R t = fma(ux, dx, uy * dy);
@@ -239,6 +257,15 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
                 } else {
                   accE64 = fma(double(wa.x), double(t), accE64);
                   if (JAS) accJ64 = fma(double(wa.y), double(t), accJ64);
+                }
+                if (DER) {
+                  const WT ag2 = *reinterpret_cast<const WT*>(reinterpret_cast<const char*>(ltab2) + (off >> 1));
+                  const R px = fma(q, dx, R(rv[i][j].x)), py = fma(q, dy, R(rv[i][j].y));  // rho'
+                  const R im = fma(px, en.y, -(py * en.x)), re = fma(px, en.x, py * en.y);
+                  const R ti = R(wa.y) * im;
+                  sT += ti;
+                  sT2 = fma(R(j), ti, sT2);
+                  sL = fma(R(ag2), re, sL);
                 }
                 if (acc) {
                   rv[i][j].x += double(q * dx);
@@ -252,6 +279,12 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
               if (MIXED) {
                 accE32.add(segE);
                 if (JAS) accJ32.add(segJ);
+              }
+              if (DER) {
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) dv[d] = fma(double(sT), double(unpack_n(an[i], d)), dv[d]);
+                dv[DIM - 1] += double(sT2);
+                dv[DIM] += double(sL);
               }
             }
           }
@@ -276,10 +309,18 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
       }
       v0 = row_sum16(v0);
       if (JAS) v1 = row_sum16(v1);
+      if (DER)
+#pragma unroll
+        for (int d = 0; d < NDV; ++d) dv[d] = row_sum16(dv[d]);
       if ((lane & 15) == 0) {
         double* p = st_part + ((mm * NW + wave) * 4 + (lane >> 4)) * 2;
         p[0] = v0;
         p[1] = v1;
+        if (DER) {
+          double* p2 = st_part2 + ((mm * NW + wave) * 4 + (lane >> 4)) * NDV;
+#pragma unroll
+          for (int d = 0; d < NDV; ++d) p2[d] = dv[d];
+        }
       }
     }
     if (len > 0) counter = st_cnt[len - 1];
@@ -301,6 +342,27 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
       }
       delta[idx] = e;
       if (djas) djas[idx] = j;
+      if (DER) {
+        const int kq = st_k[tid];
+        double sv[NDV];
+#pragma unroll
+        for (int d = 0; d < NDV; ++d) sv[d] = 0.0;
+        if (kq >= 0) {
+          const double* p2 = st_part2 + tid * NW * 4 * NDV;
+          for (int v = 0; v < NW * 4; ++v)
+#pragma unroll
+            for (int d = 0; d < NDV; ++d) sv[d] += p2[v * NDV + d];
+        }
+        const double qk = kq >= 0 ? lq[kq] : 0.0;
+#pragma unroll
+        for (int e2 = 0; e2 < DIM; ++e2) {
+          double gx = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) gx = fma(sv[d], S->B[d * 3 + e2], gx);
+          jgrad[idx * DIM + e2] = kq < 0 ? NAN : -2.0 * qk * gx;
+        }
+        jlap[idx] = kq < 0 ? NAN : -2.0 * qk * sv[DIM] + 2.0 * qk * qk * S->jlap_c;
+      }
     }
     if (MIXED && K > 0 && counter >= K) {  // uniform: rebuild rho in FP64 between chunks
       __syncthreads();  // the chunk's outputs have been read from the staging area
@@ -378,7 +440,7 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
 
 
 // LDS layout of the fused kernel for a chunk of ch moves; returns the total bytes.
-template <int DIM, bool MIXED, int NT, int SPT>
+template <int DIM, bool MIXED, int NT, int SPT, bool DER>
 size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int NW = NT / 64;
@@ -413,6 +475,13 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   o = up16(o + size_t(ch) * 4);
   L.cnt = uint32_t(o);
   o = up16(o + size_t(ch) * 4);
+  L.wtab2 = L.part2 = 0;
+  if (DER) {
+    L.wtab2 = uint32_t(o);
+    o = up16(o + size_t(b.max_wtab) * sizeof(R));
+    L.part2 = uint32_t(o);
+    o = up16(o + size_t(ch) * NW * 4 * (DIM + 1) * 8);
+  }
   L.ch = ch;
   L.rtile = int(std::min<size_t>(ctab / rpart, 64)) & ~1;  // even (the tiles interleave particle pairs)
   // Between chunks the tables and the staging area are free: the mixed form's
@@ -438,21 +507,24 @@ struct RunArgs {
   const uint8_t* accept;
   double* delta;
   double* djas;
+  double* jgrad;  // non-null (with jlap): Jastrow derivatives per move
+  double* jlap;
   void* stream;
   RunPlan* plan;  // non-null: resolve the launch shape only, launch nothing
 };
 
-template <int DIM, bool MIXED, int NT, int SPT, int PPR, bool JAS, int PD, bool ORTHO, bool XTRA>
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA>
 int run_inst(const LaunchBatch& b, const RunArgs& a) {
-  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, XTRA>;
+  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, XTRA>;
+  constexpr bool DER = JM == 2;
   static const int per_cu = blocks_per_cu(kern, NT);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
   RunLds L{};
   int ch = b.run_chunk > 0 ? std::min(b.run_chunk, RUN_CHUNK) : RUN_CHUNK;
-  size_t lds = run_layout<DIM, MIXED, NT, SPT>(b, ch, L);
+  size_t lds = run_layout<DIM, MIXED, NT, SPT, DER>(b, ch, L);
   if (b.run_chunk <= 0)
-    while (lds > budget && ch > 8) lds = run_layout<DIM, MIXED, NT, SPT>(b, --ch, L);
-  while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT, SPT>(b, --ch, L);
+    while (lds > budget && ch > 8) lds = run_layout<DIM, MIXED, NT, SPT, DER>(b, --ch, L);
+  while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT, SPT, DER>(b, --ch, L);
   if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
   if (a.plan) {
     *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu};
@@ -460,7 +532,7 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
   }
   if (int rc = allow_lds(kern, lds)) return rc;
   hipLaunchKernelGGL(kern, dim3(b.n_walkers), dim3(NT), lds, as_stream(a.stream), b.d_sys, b.d_walk, a.state,
-                     a.n_steps, b.n_walkers, a.k, a.new_pos, a.accept, a.delta, a.djas, L);
+                     a.n_steps, b.n_walkers, a.k, a.new_pos, a.accept, a.delta, a.djas, a.jgrad, a.jlap, L);
   return last_launch();
 }
 
@@ -490,7 +562,7 @@ inline int run_shape(int max_n_seg, int max_particles, int threads, int* nt, int
   return 0;
 }
 
-template <int DIM, bool MIXED, bool JAS, int PD, bool ORTHO>
+template <int DIM, bool MIXED, int JM, int PD, bool ORTHO>
 int run_jp(const LaunchBatch& b, const RunArgs& a) {
   static_assert(RUN_CHUNK <= 256, "staging uses one thread per move");
   int nt = 0, spt = 0, ppr = 0;
@@ -501,11 +573,11 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   // registers there and runs slower).
   const bool xtra = b.max_particles > ppr * nt || b.max_fixed > 0;
 #define EW_RUN(NT, SPT, PPR) \
-  if (nt == NT && spt == SPT && ppr == PPR) return run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, true>(b, a)
+  if (nt == NT && spt == SPT && ppr == PPR) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true>(b, a)
 #define EW_RUN_X(NT, SPT, PPR)                                                                          \
   if (nt == NT && spt == SPT && ppr == PPR)                                                            \
-    return xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, true>(b, a)                       \
-                : run_inst<DIM, MIXED, NT, SPT, PPR, JAS, PD, ORTHO, false>(b, a)
+    return xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true>(b, a)                       \
+                : run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, false>(b, a)
   EW_RUN(256, 1, 1);
   EW_RUN(256, 1, 2);
   EW_RUN(256, 2, 1);
@@ -518,26 +590,30 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   return RUN_NO_FIT;
 }
 
-template <int DIM, bool MIXED, bool JAS, int PD>
+template <int DIM, bool MIXED, int JM, int PD>
 int run_jpo(const LaunchBatch& b, const RunArgs& a) {
-  return b.all_ortho && !b.general_frame ? run_jp<DIM, MIXED, JAS, PD, true>(b, a)
-                                         : run_jp<DIM, MIXED, JAS, PD, false>(b, a);
+  return b.all_ortho && !b.general_frame ? run_jp<DIM, MIXED, JM, PD, true>(b, a)
+                                         : run_jp<DIM, MIXED, JM, PD, false>(b, a);
 }
 
 
-template <int DIM, bool MIXED, bool JAS>
+template <int DIM, bool MIXED, int JM>
 int run_entry(const LaunchBatch& b, const RunArgs& a) {
-  return b.poly_deg <= 16 ? run_jpo<DIM, MIXED, JAS, 16>(b, a) : run_jpo<DIM, MIXED, JAS, 32>(b, a);
+  return b.poly_deg <= 16 ? run_jpo<DIM, MIXED, JM, 16>(b, a) : run_jpo<DIM, MIXED, JM, 32>(b, a);
 }
 
-// One per translation unit: run_entry<DIM, MIXED, JAS>.
+// One per translation unit: run_entry<DIM, MIXED, JM> (JM = Jastrow mode).
 int run_d3_fp64_j0(const LaunchBatch& b, const RunArgs& a);
 int run_d3_fp64_j1(const LaunchBatch& b, const RunArgs& a);
+int run_d3_fp64_j2(const LaunchBatch& b, const RunArgs& a);
 int run_d3_mixed_j0(const LaunchBatch& b, const RunArgs& a);
 int run_d3_mixed_j1(const LaunchBatch& b, const RunArgs& a);
+int run_d3_mixed_j2(const LaunchBatch& b, const RunArgs& a);
 int run_d2_fp64_j0(const LaunchBatch& b, const RunArgs& a);
 int run_d2_fp64_j1(const LaunchBatch& b, const RunArgs& a);
+int run_d2_fp64_j2(const LaunchBatch& b, const RunArgs& a);
 int run_d2_mixed_j0(const LaunchBatch& b, const RunArgs& a);
 int run_d2_mixed_j1(const LaunchBatch& b, const RunArgs& a);
+int run_d2_mixed_j2(const LaunchBatch& b, const RunArgs& a);
 
 }  // namespace ewald

@@ -1,6 +1,6 @@
-// Fused multi-move kernels: 2D, FP32-mixed form, with the Jastrow sum.
+// Fused multi-move kernels: 2D, FP32-mixed form, with the Jastrow value.
 #include "ewald_run.h"
 
 namespace ewald {
-int run_d2_mixed_j1(const LaunchBatch& b, const RunArgs& a) { return run_entry<2, true, true>(b, a); }
+int run_d2_mixed_j1(const LaunchBatch& b, const RunArgs& a) { return run_entry<2, true, 1>(b, a); }
 }  // namespace ewald

@@ -2,5 +2,5 @@
 #include "ewald_run.h"
 
 namespace ewald {
-int run_d3_fp64_j0(const LaunchBatch& b, const RunArgs& a) { return run_entry<3, false, false>(b, a); }
+int run_d3_fp64_j0(const LaunchBatch& b, const RunArgs& a) { return run_entry<3, false, 0>(b, a); }
 }  // namespace ewald

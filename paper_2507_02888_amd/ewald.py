@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "EWALD_OK", 1: "EWALD_E_ARG", 2: "EWALD_E_RCUT", 3: "EWALD_E_
 EXPORTS = ("ewald_setup", "ewald_sys_query", "ewald_sys_tables", "ewald_sys_candidates",
            "ewald_sys_geometry", "ewald_sys_destroy", "ewald_batch_create", "ewald_batch_layout", "ewald_state_offsets",
            "ewald_batch_destroy", "ewald_energy_batch", "ewald_move_delta_batch",
-           "ewald_accept_batch", "ewald_run_moves_batch", "ewald_batch_set_tuning",
+           "ewald_accept_batch", "ewald_run_moves_batch", "ewald_move_delta_grad_batch",
+           "ewald_run_moves_grad_batch", "ewald_batch_set_tuning",
            "ewald_batch_get_tuning", "ewald_autotune", "ewald_last_error")
 
 
@@ -78,6 +79,8 @@ def load() -> ctypes.CDLL:
     lib.ewald_move_delta_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.ewald_accept_batch.argtypes = [vp, vp, vp, vp]
     lib.ewald_run_moves_batch.argtypes = [vp, vp, c_int, vp, vp, vp, vp, vp, vp]
+    lib.ewald_move_delta_grad_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ewald_run_moves_grad_batch.argtypes = [vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ewald_batch_set_tuning.argtypes = [vp, c_int, c_int, c_int]
     lib.ewald_batch_get_tuning.argtypes = [vp, P(c_int), P(c_int), P(c_int), P(c_int)]
     lib.ewald_autotune.argtypes = [vp, vp, c_int, ctypes.c_char_p, vp]
@@ -236,6 +239,24 @@ def ewald_run_moves_batch(batch_h, state_ptr, n_steps, k_ptr, new_pos_ptr, accep
                                         ctypes.c_void_p(djastrow_ptr or None), ctypes.c_void_p(stream or None)))
 
 
+def ewald_move_delta_grad_batch(batch_h, state_ptr, k_ptr, new_pos_ptr, delta_ptr, djastrow_ptr=0, jgrad_ptr=0,
+                                jlap_ptr=0, stream=0) -> None:
+    _check(load().ewald_move_delta_grad_batch(ctypes.c_void_p(batch_h), ctypes.c_void_p(state_ptr),
+                                              ctypes.c_void_p(k_ptr), ctypes.c_void_p(new_pos_ptr),
+                                              ctypes.c_void_p(delta_ptr), ctypes.c_void_p(djastrow_ptr or None),
+                                              ctypes.c_void_p(jgrad_ptr or None), ctypes.c_void_p(jlap_ptr or None),
+                                              ctypes.c_void_p(stream or None)))
+
+
+def ewald_run_moves_grad_batch(batch_h, state_ptr, n_steps, k_ptr, new_pos_ptr, accept_ptr, delta_ptr,
+                               djastrow_ptr=0, jgrad_ptr=0, jlap_ptr=0, stream=0) -> None:
+    _check(load().ewald_run_moves_grad_batch(ctypes.c_void_p(batch_h), ctypes.c_void_p(state_ptr), int(n_steps),
+                                             ctypes.c_void_p(k_ptr), ctypes.c_void_p(new_pos_ptr),
+                                             ctypes.c_void_p(accept_ptr), ctypes.c_void_p(delta_ptr),
+                                             ctypes.c_void_p(djastrow_ptr or None), ctypes.c_void_p(jgrad_ptr or None),
+                                             ctypes.c_void_p(jlap_ptr or None), ctypes.c_void_p(stream or None)))
+
+
 def ewald_batch_set_tuning(batch_h, threads=0, chunk=0, general_frame=0) -> None:
     _check(load().ewald_batch_set_tuning(ctypes.c_void_p(batch_h), int(threads), int(chunk), int(general_frame)))
 
@@ -319,6 +340,17 @@ class Batch:
         ewald_run_moves_batch(self.handle, self.state.data_ptr(), int(k.shape[0]), k.data_ptr(),
                               new_pos.data_ptr(), accept.data_ptr(), delta.data_ptr(),
                               0 if djastrow is None else djastrow.data_ptr(), self.stream())
+
+    def move_delta_grad(self, k, new_pos, delta, djastrow, jgrad, jlap):
+        ewald_move_delta_grad_batch(self.handle, self.state.data_ptr(), k.data_ptr(), new_pos.data_ptr(),
+                                    delta.data_ptr(), 0 if djastrow is None else djastrow.data_ptr(),
+                                    jgrad.data_ptr(), jlap.data_ptr(), self.stream())
+
+    def run_moves_grad(self, k, new_pos, accept, delta, djastrow, jgrad, jlap):
+        ewald_run_moves_grad_batch(self.handle, self.state.data_ptr(), int(k.shape[0]), k.data_ptr(),
+                                   new_pos.data_ptr(), accept.data_ptr(), delta.data_ptr(),
+                                   0 if djastrow is None else djastrow.data_ptr(), jgrad.data_ptr(),
+                                   jlap.data_ptr(), self.stream())
 
     def set_tuning(self, threads=0, chunk=0, general_frame=0):
         ewald_batch_set_tuning(self.handle, threads, chunk, general_frame)

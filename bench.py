@@ -167,7 +167,7 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_
     return out
 
 
-def other_workload(cfg_id: int, precision: int, steps: int = 2):
+def other_workload(cfg_id: int, precision: int, steps: int = 2, threads: int = 0):
     """A whole-workload sweep of one of the smaller configurations (energy plus
     the fused sweep, autotuned launch shape): deltas/s and the fused kernel's
     VALU fraction by the same algorithmic count."""
@@ -189,7 +189,10 @@ def other_workload(cfg_id: int, precision: int, steps: int = 2):
     energy = torch.zeros(W, dtype=torch.float64, device=dev)
     delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
     batch.energy(pos, energy)
-    batch.autotune(n_moves=max(64, 2 * K) if K else 64)
+    if threads:
+        batch.set_tuning(threads=threads)
+    else:
+        batch.autotune(n_moves=max(64, 2 * K) if K else 64)
     stream = torch.cuda.current_stream()
     run_ms, step_ms = [], []
     for it in range(steps + 1):
@@ -339,6 +342,8 @@ def main():
                     help="further refresh intervals K timed for the mixed form (0 = no rebuild); empty to skip")
     ap.add_argument("--other", default="2,3,4",
                     help="smaller configurations also timed (both forms), reported under other_workloads")
+    ap.add_argument("--skip-main", action="store_true",
+                    help="time only the smaller configurations (--other); prints their results, not the bench line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -361,6 +366,12 @@ def main():
     from paper_2507_02888_amd import workloads as wl
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ew.load()
+    if args.skip_main:
+        for cid in [int(x) for x in args.other.split(",") if x]:
+            for form in args.forms.split(","):
+                prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
+                print(json.dumps(other_workload(cid, prec, threads=args.threads)), flush=True)
+        return
 
     cfg = wl.config(CFG_ID)
     K = cfg.refresh_every if args.refresh_every is None else args.refresh_every

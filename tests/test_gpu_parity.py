@@ -625,6 +625,44 @@ def test_uneven_batch_fused_graph(precision):
         assert g_case.batch.walker_header(w)["n_accepts"] == eager.batch.walker_header(w)["n_accepts"]
 
 
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_uneven_batch_fused_vs_oracle(oracle_lib, precision):
+    """The uneven batch in one fused launch (walkers of 64, 216 and 512
+    electrons with their +4 ions, launched most expensive first), autotuned,
+    against the oracle walker by walker: every delta and Jastrow delta, the
+    accept counts, the mixed form's rebuild counts at K=4, and the final
+    positions."""
+    W, S, K = 6, 24, 4
+    say(f"[uneven fused vs oracle] cfg=4 precision={precision}")
+    c = Case(4, W, S, precision, refresh_every=K)
+    assert len(set(int(x) for x in c.b.walker_sys)) == 3
+    e0, _ = c.run_energy()
+    c.batch.autotune(n_moves=8)
+    assert c.batch.tuning()["fused"] == 1
+    d, dj = c.fused()
+    fin = c.final_cartesian()
+    for w in range(W):
+        r, sysw = c.oracle(oracle_lib, w), c.system(w)
+        scale = max(abs(r["energy0"]), e_scale(sysw))
+        acc = int(c.b.accept[:, w].sum())
+        h = c.batch.walker_header(w)
+        assert h["n_accepts"] == acc
+        if precision == FP64:
+            assert abs(e0[w] - r["energy0"]) <= 1e-10 * scale
+            assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale, w
+            assert np.max(np.abs(dj[:, w] - r["djas"])) <= 1e-10 * max(1.0, abs(r["j0"])), w
+        else:
+            assert h["n_refresh"] == acc // K
+            assert abs(e0[w] - r["energy0"]) <= 1e-6 * scale
+            assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5, w
+            assert np.max(np.abs(dj[:, w] - r["djas"])) <= djas_bound(c, w), w
+        # final positions (wrapped by the library) equal the oracle's modulo the lattice
+        lat = sysw.lattice[: c.dim, : c.dim]
+        got = fin[c.b.pos_offsets[w]: c.b.pos_offsets[w + 1]]
+        diff = (got - r["pos_final"][: sysw.n_mobile]) @ np.linalg.inv(lat)
+        assert np.max(np.abs(diff - np.rint(diff))) <= 1e-12
+
+
 @pytest.mark.parametrize("precision", [MIXED, FP64], ids=["mixed", "fp64"])
 def test_n1024_long_sweep_with_rebuilds(oracle_lib, precision):
     """The N=1024 workload (bcc cell, 3577 G, Jastrow) at its refresh interval

@@ -7,7 +7,9 @@ imports it, and the oracle shares no code with the library.
 Parity unpinned: none -- every entry point is pinned by tests/test_oracle_pins.py
 (Madelung constants, alpha independence, invariances, incremental moves,
 shell populations of cubic reciprocal lattices for the Jastrow shell index,
-the batch driver against the single-walker driver).
+the batch driver against the single-walker driver) and by
+tests/test_oracle_pins_u.py for the Jastrow u term (hand-evaluated values,
+the Kato cusp, the order-C zero at the cutoff, finite differences, images).
 """
 from .oracle import (  # noqa: F401
     build, lib_path, count_g, gvectors, rho_at, energy, jastrow_derivs, run, run_batch, particles, Variant,

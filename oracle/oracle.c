@@ -55,6 +55,20 @@
  *   grad_k J = 2 q_k sum_{j != k} q_j grad P(r_k - r_j),  grad P(r) = -1/2 sum_G a G sin(G.r)
  *   lap_k J  = 2 q_k sum_{j != k} q_j lap P(r_k - r_j),   lap P(r)  = -1/2 sum_G a |G|^2 cos(G.r)
  * evaluated by direct pair and G loops (no structure factor).
+ *
+ * Jastrow two-body polynomial term (paper Sec. 2.3, Eq. (8)), optional:
+ *   u_c(r) = sum_{l=0}^{N_u} alpha_{c,l} r^l (r - L_u)^C   for r < L_u, else 0,
+ * with a coefficient set c per spin channel (c = 0 for a pair of equal spin
+ * labels, 1 for unequal labels: u differs for parallel and antiparallel
+ * spins, Sec. 2.3).  Particles with a negative label (the fixed ions) take
+ * no part.  U = sum_{i<j} u_c(|r_i - r_j - R|) summed by brute force over
+ * every lattice vector R with |r_i - r_j - R| < L_u (with L_u no larger than
+ * half the shortest lattice vector that is the nearest image alone).  U is
+ * added to the Jastrow value, its move change to the Jastrow delta and
+ *   grad_k U = sum_{j,R} u'(rho) (d - R)/rho,
+ *   lap_k U  = sum_{j,R} [u''(rho) + (dim - 1) u'(rho)/rho],  d = r_k - r_j,
+ * to the Jastrow gradient and Laplacian, with u' and u'' from the product
+ * rule on the polynomial and the (r - L_u)^C factor.
  */
 #include <math.h>
 #include <stdint.h>
@@ -73,6 +87,11 @@ typedef struct {
     double alpha, r_cut, g_cut;
     int n_jastrow;           /* number of shell coefficients (0: no Jastrow) */
     const double *jastrow_a; /* [n_jastrow] */
+    int n_u;                 /* u-term coefficients per spin channel, N_u + 1 (0: no u term) */
+    int u_c;                 /* the exponent C of (r - L_u) */
+    double u_cut;            /* L_u */
+    const double *u_alpha;   /* [2][n_u]: channel 0 equal spin labels, 1 unequal */
+    const int *spin;         /* [n] per particle: spin label, negative = no u term */
 } osys;
 
 /* ---- small helpers (plain, written out) -------------------------------- */
@@ -233,6 +252,84 @@ static double real_image_sum(const osys *s, const double *bm, const double *dv, 
     return sum;
 }
 
+/* ---- Jastrow u term ------------------------------------------------------------ */
+
+/* u_c(r), u_c'(r), u_c''(r) of Eq. (8), for 0 <= r < L_u. */
+static void u_eval(const osys *s, int c, double r, double *u, double *du, double *d2u) {
+    const double *a = s->u_alpha + (size_t)c * (size_t)s->n_u;
+    double P = 0, dP = 0, d2P = 0; /* the polynomial sum_l alpha_l r^l and its derivatives */
+    for (int l = 0; l < s->n_u; ++l) {
+        P += a[l] * pow(r, l);
+        if (l >= 1) dP += l * a[l] * pow(r, l - 1);
+        if (l >= 2) d2P += l * (l - 1) * a[l] * pow(r, l - 2);
+    }
+    int C = s->u_c;
+    double x = r - s->u_cut;
+    double xc = pow(x, C), xc1 = pow(x, C - 1), xc2 = C >= 2 ? pow(x, C - 2) : 0.0;
+    *u = P * xc;
+    *du = dP * xc + C * P * xc1;
+    *d2u = d2P * xc + 2.0 * C * dP * xc1 + (double)C * (C - 1) * P * xc2;
+}
+
+static int u_channel(const osys *s, int i, int j) {
+    if (s->n_u <= 0 || !s->spin || s->spin[i] < 0 || s->spin[j] < 0) return -1;
+    return s->spin[i] == s->spin[j] ? 0 : 1;
+}
+
+/* sum over lattice vectors R with |d - R| < L_u of u_c(|d - R|) (val), and of
+ * its gradient with respect to d (grad) and Laplacian (lap); the index box is
+ * chosen as in real_image_sum. */
+static void u_image_sum(const osys *s, const double *bm, const double *dv, int c, double *val, double *grad,
+                        double *lap) {
+    int dim = s->dim;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+        double f = 0;
+        for (int e = 0; e < dim; ++e) f += dv[e] * bm[3 * d + e];
+        f /= 2 * O_PI;
+        double ext = s->u_cut * vnorm(bm + 3 * d, dim) / (2 * O_PI);
+        lo[d] = (int)floor(f - ext);
+        hi[d] = (int)ceil(f + ext);
+    }
+    double v = 0, g[3] = {0, 0, 0}, l = 0;
+    for (int i = lo[0]; i <= hi[0]; ++i)
+        for (int j = lo[1]; j <= hi[1]; ++j)
+            for (int k = lo[2]; k <= hi[2]; ++k) {
+                double r[3] = {0, 0, 0};
+                for (int e = 0; e < dim; ++e)
+                    r[e] = dv[e] - (i * s->lat[e] + j * s->lat[3 + e] + k * s->lat[6 + e]);
+                double d2 = 0;
+                for (int e = 0; e < dim; ++e) d2 += r[e] * r[e];
+                double rho = sqrt(d2);
+                if (rho >= s->u_cut) continue;
+                double u, du, d2u;
+                u_eval(s, c, rho, &u, &du, &d2u);
+                v += u;
+                for (int e = 0; e < dim; ++e) g[e] += du * r[e] / rho;
+                l += d2u + (dim - 1) * du / rho;
+            }
+    if (val) *val = v;
+    if (grad)
+        for (int e = 0; e < dim; ++e) grad[e] = g[e];
+    if (lap) *lap = l;
+}
+
+/* U = sum_{i<j} u(r_ij) over one configuration. */
+static double u_total(const osys *s, const double *bm, int n, const double *pos) {
+    int dim = s->dim;
+    double tot = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            int c = u_channel(s, i, j);
+            if (c < 0) continue;
+            double dv[3] = {0, 0, 0}, v;
+            for (int e = 0; e < dim; ++e) dv[e] = pos[dim * i + e] - pos[dim * j + e];
+            u_image_sum(s, bm, dv, c, &v, NULL, NULL);
+            tot += v;
+        }
+    return tot;
+}
+
 /* ---- public entry points --------------------------------------------------- */
 
 int oracle_count_g(const osys *s, int *n_full, int *n_shells) {
@@ -327,6 +424,7 @@ int oracle_energy(const osys *s, int n, const double *pos, const double *q, doub
     parts[2] = e_self;
     parts[3] = e_bg;
     parts[4] = e_real + e_recip + e_self + e_bg;
+    if (s->n_u > 0) jas += u_total(s, bm, n, pos);
     if (jastrow) *jastrow = jas;
     return 0;
 }
@@ -336,6 +434,8 @@ int oracle_energy(const osys *s, int n, const double *pos, const double *q, doub
 int oracle_jastrow_derivs(const osys *s, int n, const double *pos, const double *q, int k, double *grad,
                           double *lap) {
     int dim = s->dim;
+    double bm[9];
+    recip_vectors(s, bm);
     gset g;
     gset_build(s, &g);
     double gr[3] = {0, 0, 0}, lp = 0;
@@ -354,6 +454,13 @@ int oracle_jastrow_derivs(const osys *s, int n, const double *pos, const double 
         }
         for (int e = 0; e < dim; ++e) gr[e] += 2 * q[k] * q[j] * pg[e];
         lp += 2 * q[k] * q[j] * pl;
+        int c = u_channel(s, k, j);
+        if (c >= 0) {
+            double ug[3] = {0, 0, 0}, ul = 0;
+            u_image_sum(s, bm, d, c, NULL, ug, &ul);
+            for (int e = 0; e < dim; ++e) gr[e] += ug[e];
+            lp += ul;
+        }
     }
     for (int e = 0; e < dim; ++e) grad[e] = gr[e];
     *lap = lp;
@@ -427,6 +534,19 @@ int oracle_run(const osys *s, int n, int n_mobile, const double *pos0, const dou
             double tt = 2 * (rre[t] * dre + rim[t] * dim_) + dre * dre + dim_ * dim_;
             drec += fac[t] * tt;
             dj += jc[t] * tt;
+        }
+        /* Jastrow u term: pairs of particle k with every other labelled particle */
+        for (int j = 0; j < n; ++j) {
+            int c = j == kk ? -1 : u_channel(s, kk, j);
+            if (c < 0) continue;
+            double dn[3] = {0, 0, 0}, dold[3] = {0, 0, 0}, un, uo;
+            for (int e = 0; e < dim; ++e) {
+                dn[e] = rn[e] - pos[dim * j + e];
+                dold[e] = ro[e] - pos[dim * j + e];
+            }
+            u_image_sum(s, bm, dn, c, &un, NULL, NULL);
+            u_image_sum(s, bm, dold, c, &uo, NULL, NULL);
+            dj += un - uo;
         }
         delta[m] = dr + drec;
         djas[m] = dj;

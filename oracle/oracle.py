@@ -34,7 +34,9 @@ class _OSys(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("lat", ctypes.c_double * 9),
                 ("alpha", ctypes.c_double), ("r_cut", ctypes.c_double),
                 ("g_cut", ctypes.c_double), ("n_jastrow", ctypes.c_int),
-                ("jastrow_a", ctypes.POINTER(ctypes.c_double))]
+                ("jastrow_a", ctypes.POINTER(ctypes.c_double)),
+                ("n_u", ctypes.c_int), ("u_c", ctypes.c_int), ("u_cut", ctypes.c_double),
+                ("u_alpha", ctypes.POINTER(ctypes.c_double)), ("spin", ctypes.POINTER(ctypes.c_int))]
 
 
 _libs = {}
@@ -68,8 +70,11 @@ def _ptr(a: np.ndarray, ct):
 class _Sys:
     """Keeps the ctypes struct and the arrays it points to alive together."""
 
-    def __init__(self, dim, lattice, alpha, r_cut, g_cut, jastrow_a=None):
+    def __init__(self, dim, lattice, alpha, r_cut, g_cut, jastrow_a=None, u_alpha=None, u_C=3, u_cut=0.0,
+                 spin=None):
         self.ja = None if jastrow_a is None else np.ascontiguousarray(jastrow_a, dtype=np.float64)
+        self.ua = None if u_alpha is None else np.ascontiguousarray(u_alpha, dtype=np.float64).reshape(2, -1)
+        self.spin = None if spin is None else np.ascontiguousarray(spin, dtype=np.int32)
         s = _OSys()
         s.dim = int(dim)
         lat = np.zeros((3, 3))
@@ -83,15 +88,36 @@ class _Sys:
         else:
             s.n_jastrow = int(self.ja.shape[0])
             s.jastrow_a = _ptr(self.ja, ctypes.c_double)
+        if self.ua is None or self.spin is None:
+            s.n_u, s.u_c, s.u_cut = 0, 0, 0.0
+            s.u_alpha = ctypes.POINTER(ctypes.c_double)()
+            s.spin = ctypes.POINTER(ctypes.c_int)()
+        else:
+            s.n_u, s.u_c, s.u_cut = int(self.ua.shape[1]), int(u_C), float(u_cut)
+            s.u_alpha = _ptr(self.ua, ctypes.c_double)
+            s.spin = _ptr(self.spin, ctypes.c_int)
         self.s = s
 
     def ref(self):
         return ctypes.byref(self.s)
 
 
-def _mk(system, jastrow_a=None, **over):
+def spins(system) -> Optional[np.ndarray]:
+    """Spin labels of all particles of a walker (mobile first, then the fixed
+    ions with -1), or None when the system has no u term."""
+    if getattr(system, "u_alpha", None) is None:
+        return None
+    ms = getattr(system, "mobile_spin", None)
+    ms = np.zeros(system.n_mobile, dtype=np.int32) if ms is None else np.asarray(ms, dtype=np.int32)
+    return np.concatenate([ms, -np.ones(system.n_fixed, dtype=np.int32)])
+
+
+def _mk(system, jastrow_a=None, spin=None, **over):
     kw = dict(dim=system.dim, lattice=system.lattice, alpha=system.alpha,
               r_cut=system.r_cut, g_cut=system.g_cut)
+    if getattr(system, "u_alpha", None) is not None:
+        kw.update(u_alpha=system.u_alpha, u_C=system.u_C, u_cut=system.u_cut,
+                  spin=spins(system) if spin is None else spin)
     kw.update(over)
     return _Sys(jastrow_a=jastrow_a, **kw)
 
@@ -141,6 +167,7 @@ def energy(system, pos, q, jastrow_a: Optional[np.ndarray] = None, _path=_LIB, *
     s = _mk(system, jastrow_a=jastrow_a, **over)
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     q = np.ascontiguousarray(q, dtype=np.float64)
+    assert s.spin is None or s.spin.shape[0] == q.shape[0], "one spin label per particle"
     parts = np.zeros(5)
     jas = ctypes.c_double(0.0)
     _load(_path).oracle_energy(s.ref(), int(q.shape[0]), _ptr(pos, ctypes.c_double),
@@ -155,6 +182,7 @@ def jastrow_derivs(system, pos, q, k, jastrow_a, _path=_LIB, **over):
     s = _mk(system, jastrow_a=jastrow_a, **over)
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     q = np.ascontiguousarray(q, dtype=np.float64)
+    assert s.spin is None or s.spin.shape[0] == q.shape[0], "one spin label per particle"
     grad = np.zeros(system.dim)
     lap = ctypes.c_double(0.0)
     _load(_path).oracle_jastrow_derivs(s.ref(), int(q.shape[0]), _ptr(pos, ctypes.c_double),

@@ -70,6 +70,21 @@ def hex_cell(area: float) -> np.ndarray:
     return m
 
 
+def inscribed_radius(shape: str, measure: float) -> float:
+    """Half the shortest nonzero lattice vector of the cells above (the radius
+    of the sphere inscribed in the Wigner-Seitz cell), in closed form from
+    the cell constructors: sc c, bcc c sqrt(3)/2, fcc c/sqrt(2), hex a."""
+    if shape == "sc":
+        return 0.5 * measure ** (1.0 / 3.0)
+    if shape == "bcc":
+        return 0.5 * (2.0 * measure) ** (1.0 / 3.0) * math.sqrt(3.0) / 2.0
+    if shape == "fcc":
+        return 0.5 * (4.0 * measure) ** (1.0 / 3.0) / math.sqrt(2.0)
+    if shape == "hex":
+        return 0.5 * math.sqrt(measure / (math.sqrt(3.0) / 2.0))
+    raise ValueError(shape)
+
+
 @dataclasses.dataclass
 class System:
     """One periodic cell with its mobile electrons and fixed ions."""
@@ -83,6 +98,13 @@ class System:
     alpha: float
     r_cut: float
     g_cut: float
+    # optional Jastrow two-body polynomial term u (Eq. (8)): coefficients
+    # [2][N_u + 1] (channel 0: equal spin labels, 1: unequal), exponent C,
+    # cutoff L_u, and a spin label (0/1) per mobile particle
+    u_alpha: Optional[np.ndarray] = None
+    u_C: int = 3
+    u_cut: float = 0.0
+    mobile_spin: Optional[np.ndarray] = None
 
     @property
     def n_fixed(self) -> int:
@@ -257,3 +279,32 @@ def random_positions(system: System, n: int, seed: int) -> np.ndarray:
     g = np.random.default_rng([SEED[0], SEED[1], 99, int(seed)])
     d = system.dim
     return g.random((n, d)) @ system.lattice[:d, :d]
+
+
+U_TERMS = 9   # N_u + 1 (the paper: N_u typically 8..12)
+U_C = 3       # the paper: C = 2 or 3
+CELL_SHAPE = {1: "sc", 2: "fcc", 3: "hex", 5: "bcc"}
+
+
+def cusp_slope(dim: int, parallel: bool) -> float:
+    """Kato cusp of the electron-electron Jastrow term, u'(0): 1/(d+1) for
+    parallel and 1/(d-1) for antiparallel spins (unit charges and masses)."""
+    return 1.0 / (dim + 1) if parallel else 1.0 / (dim - 1)
+
+
+def with_u_term(system: System, cfg_id: int) -> System:
+    """A copy of an electron-gas system with a seeded Jastrow u term (Eq. (8)):
+    cutoff L_u = the Wigner-Seitz inscribed radius (as in the paper's HEG
+    runs), C = 3, N_u = 8; coefficients alpha_l = x_l / L_u^(l+C) with
+    x_l ~ U(-0.5, 0.5) (stream 5), except alpha_1, which is fixed by the cusp
+    u'(0) = C alpha_0 (-L_u)^(C-1) + alpha_1 (-L_u)^C = Gamma; the first half
+    of the electrons carry spin label 0, the rest 1."""
+    Lu = inscribed_radius(CELL_SHAPE[cfg_id], system.measure)
+    x = rng(cfg_id, 5).uniform(-0.5, 0.5, size=(2, U_TERMS))
+    a = x / Lu ** (np.arange(U_TERMS)[None, :] + U_C)
+    for c, parallel in ((0, True), (1, False)):
+        gam = cusp_slope(system.dim, parallel)
+        a[c, 1] = (gam - U_C * a[c, 0] * (-Lu) ** (U_C - 1)) / (-Lu) ** U_C
+    n = system.n_mobile
+    spin = np.concatenate([np.zeros(n // 2, dtype=np.int32), np.ones(n - n // 2, dtype=np.int32)])
+    return dataclasses.replace(system, u_alpha=a, u_C=U_C, u_cut=Lu, mobile_spin=spin)

@@ -17,6 +17,11 @@ typedef struct {
   double alpha, r_cut, g_cut;
   int n_jastrow;
   const double* jastrow_a;
+  int n_u;
+  int u_c;
+  double u_cut;
+  const double* u_alpha;
+  const int* spin;
 } osys;
 int oracle_energy(const osys* s, int n, const double* pos, const double* q, double* parts, double* jastrow);
 int oracle_run(const osys* s, int n, int n_mobile, const double* pos0, const double* q, int n_steps,
@@ -71,6 +76,17 @@ static void run_cell(const Cell& c, int n, int n_ions) {
   s.n_jastrow = int(ja.size());
   s.jastrow_a = ja.data();
   const int nt = n + n_ions;
+  // Jastrow u term: two channels of 6 coefficients, C = 3, L_u = r_cut;
+  // mobile particles alternate spin labels, ions take no part
+  std::vector<double> ua(12);
+  for (double& x : ua) x = (urand() - 0.5) * 1e-3;
+  std::vector<int> spin(nt, -1);
+  for (int i = 0; i < n; ++i) spin[i] = i & 1;
+  s.n_u = 6;
+  s.u_c = 3;
+  s.u_cut = s.r_cut;
+  s.u_alpha = ua.data();
+  s.spin = spin.data();
   std::vector<double> pos(nt * dim), q(nt);
   for (int i = 0; i < n; ++i) {
     q[i] = qm[i];

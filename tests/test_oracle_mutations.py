@@ -10,6 +10,7 @@ import pytest
 import oracle
 from oracle.oracle import Variant, build
 from tests import test_oracle_pins as pins
+from tests import test_oracle_pins_u as upins
 
 SRC = os.path.join(os.path.dirname(oracle.lib_path()), "oracle.c")
 
@@ -38,6 +39,17 @@ MUTATIONS = [
     ("jlap_norm", "pl += -0.5 * a * g.g2[t] * cos(ph);", "pl += -0.5 * a * sqrt(g.g2[t]) * cos(ph);"),
     ("jlap_sign", "lp += 2 * q[k] * q[j] * pl;", "lp -= 2 * q[k] * q[j] * pl;"),
     ("jderiv_old_position", "prop[dim * kk + e] = rn[e];", "prop[dim * kk + e] = ro[e];"),
+    ("u_sign_convention", "double x = r - s->u_cut;", "double x = s->u_cut - r;"),
+    ("u_power_index", "P += a[l] * pow(r, l);", "P += a[l] * pow(r, l + 1);"),
+    ("u_dpoly_index", "if (l >= 1) dP += l * a[l] * pow(r, l - 1);", "if (l >= 1) dP += a[l] * pow(r, l - 1);"),
+    ("u_channel_swapped", "return s->spin[i] == s->spin[j] ? 0 : 1;", "return s->spin[i] == s->spin[j] ? 1 : 0;"),
+    ("u_ions_included", "if (s->n_u <= 0 || !s->spin || s->spin[i] < 0 || s->spin[j] < 0) return -1;",
+     "if (s->n_u <= 0 || !s->spin) return -1;"),
+    ("u_cutoff_widened", "if (rho >= s->u_cut) continue;", "if (rho >= 1.5 * s->u_cut) continue;"),
+    ("u_d2_cross_term", "2.0 * C * dP * xc1", "C * dP * xc1"),
+    ("u_lap_dim", "l += d2u + (dim - 1) * du / rho;", "l += d2u + dim * du / rho;"),
+    ("u_grad_sign", "g[e] += du * r[e] / rho;", "g[e] -= du * r[e] / rho;"),
+    ("u_delta_old_sign", "dj += un - uo;", "dj += un + uo;"),
 ]
 
 CHECKS = [
@@ -54,6 +66,12 @@ CHECKS = [
     lambda o: [pins.test_run_batch_matches_run(o, c) for c in (2, 3)],
     lambda o: [pins.test_jastrow_derivs_finite_differences(o, d) for d in (3, 2)],
     lambda o: pins.test_run_derivs_at_proposed_configuration(o),
+    lambda o: upins.test_u_closed_form_values(o),
+    lambda o: upins.test_u_minimum_image(o),
+    lambda o: [upins.test_u_cusp(o, c, p) for c in (1, 3) for p in (True, False)],
+    lambda o: upins.test_u_order_c_zero_at_cutoff(o),
+    lambda o: [upins.test_u_derivs_finite_differences(o, d) for d in (3, 2)],
+    lambda o: [upins.test_u_incremental_moves_and_invariance(o, c) for c in (1, 3)],
 ]
 
 

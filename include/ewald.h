@@ -251,8 +251,9 @@ ewald_status ewald_run_moves_grad_batch(ewald_batch *b, void *state, int n_steps
  * tunes gang and vector sizes by hand, Sec. 3.3).  One workgroup serves one walker;
  *   threads        workgroup size, which fixes segments of 4 G per thread and
  *                  particles per thread: 0 = default for the largest segment
- *                  count s of the batch (s <= 512: 256; s <= 1024: 1024 or
- *                  512; s <= 2048: 512); other values give E_ARG
+ *                  count s of the batch (s <= 512: 256; s <= 1024: 1024;
+ *                  s <= 2048: 512); also available: 1024 for s <= 1024
+ *                  and 512 for 512 < s <= 1024; other values give E_ARG
  *   chunk          at most this many moves staged per chunk, 1..64 (fewer
  *                  when LDS does not hold them), or 0 = as many as LDS allows
  *                  without lowering the workgroups per CU

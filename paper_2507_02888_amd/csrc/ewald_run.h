@@ -536,22 +536,27 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
   return last_launch();
 }
 
-// Workgroup shapes of the fused kernel (threads NT, segments per thread SPT)
-// by the largest segment count of the batch; `threads` picks among the
-// shapes available for that count (0: the default, the first listed).
-//   <= 256 segments: (256, 1)      <= 512: (256, 2)
-//   <= 1024: (1024, 1) or (512, 2)  <= 2048: (512, 4)
+// Workgroup shapes of the fused kernel (threads NT, segments per thread SPT).
+// A shape is available for a batch when NT SPT covers its largest segment
+// count s and no smaller SPT would (so each NT appears once); `threads`
+// picks among the available ones, 0 = the default (the first listed that is
+// available):
+//   s <= 256: 256 x 1          s <= 512: 256 x 2
+//   s <= 1024: 1024 x 1, or 512 x 2      s <= 2048: 512 x 4
+// (1024 x 1 is also available for s <= 512).  Workgroups sized to small
+// walkers (320, 384 or 512 threads with one segment and one particle per
+// lane) were measured slower than 256 x 2 on the 250-, 300- and uneven
+// 64..512-electron workloads: at ~200 registers per lane such a kernel fits
+// one workgroup per CU, where 256-thread ones fit two.
 // Particles per thread in registers: 1 when the largest walker has at most
 // NT particles (always with 1024 threads, where larger walkers' remaining
 // particles are read from LDS), else 2.
 inline int run_shape(int max_n_seg, int max_particles, int threads, int* nt, int* spt, int* ppr) {
-  struct Shape { int lim, nt, spt; };
-  static const Shape shapes[] = {{256, 256, 1}, {512, 256, 2}, {1024, 1024, 1}, {1024, 512, 2}, {2048, 512, 4}};
-  int lim = 0;
+  struct Shape { int nt, spt; };
+  static const Shape shapes[] = {{256, 1}, {256, 2}, {1024, 1}, {512, 2}, {512, 4}};
   for (const Shape& sh : shapes) {
-    if (max_n_seg > sh.lim) continue;
-    if (lim == 0) lim = sh.lim;
-    if (sh.lim != lim) break;
+    if (sh.nt * sh.spt < max_n_seg) continue;                          // does not cover the segments
+    if (sh.spt > 1 && sh.nt * (sh.spt / 2) >= max_n_seg) continue;    // a smaller SPT would
     if (threads == 0 || threads == sh.nt) {
       *nt = sh.nt;
       *spt = sh.spt;

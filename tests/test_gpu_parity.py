@@ -663,6 +663,42 @@ def test_uneven_batch_fused_vs_oracle(oracle_lib, precision):
         assert np.max(np.abs(diff - np.rint(diff))) <= 1e-12
 
 
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [2, 3, 4])
+def test_small_walker_shapes_vs_oracle(oracle_lib, cfg_id, precision):
+    """Both workgroup sizes available to the smaller workloads (308 or 28
+    segments; 250, 300 or 64/216/512 particles plus ions): 256 threads (two
+    particles per lane where needed, plus the ion loop) and 1024 threads
+    (most lanes idle), through the fused sweep against the oracle: deltas,
+    Jastrow deltas and the mixed form's rebuild counts at K=4."""
+    W = 6 if cfg_id == 4 else 3
+    S, K = 16, 4
+    refs = None
+    for threads in (256, 1024):
+        say(f"[small shapes] cfg={cfg_id} precision={precision} threads={threads}")
+        c = Case(cfg_id, W, S, precision, refresh_every=K)
+        if refs is None:
+            refs = [c.oracle(oracle_lib, w) for w in range(W)]
+        c.batch.set_tuning(threads=threads)
+        t = c.batch.tuning()
+        assert t["fused"] == 1 and t["threads"] == threads
+        e0, _ = c.run_energy()
+        d, dj = c.fused()
+        for w in range(W):
+            r, sysw = refs[w], c.system(w)
+            scale = max(abs(r["energy0"]), e_scale(sysw))
+            acc = int(c.b.accept[:, w].sum())
+            h = c.batch.walker_header(w)
+            assert h["n_accepts"] == acc
+            if precision == FP64:
+                assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale, (threads, w)
+                assert np.max(np.abs(dj[:, w] - r["djas"])) <= 1e-10 * max(1.0, abs(r["j0"])), (threads, w)
+            else:
+                assert h["n_refresh"] == acc // K
+                assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5, (threads, w)
+                assert np.max(np.abs(dj[:, w] - r["djas"])) <= djas_bound(c, w), (threads, w)
+
+
 @pytest.mark.parametrize("precision", [MIXED, FP64], ids=["mixed", "fp64"])
 def test_n1024_long_sweep_with_rebuilds(oracle_lib, precision):
     """The N=1024 workload (bcc cell, 3577 G, Jastrow) at its refresh interval

@@ -9,8 +9,12 @@ Parity unpinned: none -- every entry point is pinned by tests/test_oracle_pins.p
 shell populations of cubic reciprocal lattices for the Jastrow shell index,
 the batch driver against the single-walker driver) and by
 tests/test_oracle_pins_u.py for the Jastrow u term (hand-evaluated values,
-the Kato cusp, the order-C zero at the cutoff, finite differences, images).
+the Kato cusp, the order-C zero at the cutoff, finite differences, images)
+and by tests/test_oracle_pins_blip.py for the blip orbitals (partition of
+unity, reproduction of linear functions, plane waves at grid nodes, lattice
+periodicity, finite differences).
 """
 from .oracle import (  # noqa: F401
     build, lib_path, count_g, gvectors, rho_at, energy, jastrow_derivs, run, run_batch, particles, Variant,
+    blip_eval, spins,
 )

@@ -626,3 +626,111 @@ int oracle_run_batch(const osys *s, int n_walkers, int n, int n_mobile, const do
     }
     return used;
 }
+
+/* ---- blip (B-spline) orbitals (paper Sec. 2.4) ----------------------------------
+ *
+ * Orbitals re-represented on a periodic grid of n1 x n2 x n3 points along the
+ * lattice vectors: with fractional coordinates s = r A^-1 and x_d = n_d s_d,
+ *   psi_m(r) = sum_{i,j,k} a[i][j][k][m] Th(x_1 - i) Th(x_2 - j) Th(x_3 - k),
+ * the sum over every grid point, each blip function taken at the periodic
+ * image of its offset nearest to zero (the grid is periodic with the cell).
+ * Th is the cubic B-spline blip function with Th(0) = 1:
+ *   Th(x) = 1 - 3/2 x^2 + 3/4 |x|^3   (|x| <= 1),   1/4 (2 - |x|)^3   (1 < |x| < 2),
+ * zero beyond (3/2 times the cardinal cubic B-spline).  The gradient and the
+ * Laplacian with respect to r follow by the chain rule: d/dr_e = sum_d
+ * Ainv[e][d] n_d d/dx_d, and the Laplacian takes the full second-derivative
+ * matrix in x (the cell need not be orthogonal). */
+
+static double blip_th(double x, int der) {
+    double ax = fabs(x), sg = x < 0 ? -1.0 : 1.0;
+    if (ax >= 2.0) return 0.0;
+    if (ax <= 1.0) {
+        if (der == 0) return 1.0 - 1.5 * x * x + 0.75 * ax * ax * ax;
+        if (der == 1) return -3.0 * x + 2.25 * sg * x * x;
+        return -3.0 + 4.5 * ax;
+    }
+    double t = 2.0 - ax;
+    if (der == 0) return 0.25 * t * t * t;
+    if (der == 1) return -0.75 * sg * t * t;
+    return 1.5 * t;
+}
+
+/* Values val[p][m], gradients grad[p][3][m] and Laplacians lap[p][m] (either
+ * of the last two may be NULL) of n_orb orbitals at n_pts Cartesian points
+ * pos[p][3], for coefficients coef[n1][n2][n3][n_orb]; lat holds the rows a_i. */
+int oracle_blip_eval(const double *lat, int n1, int n2, int n3, int n_orb, const double *coef, int n_pts,
+                     const double *pos, double *val, double *grad, double *lap) {
+    osys tmp;
+    memset(&tmp, 0, sizeof tmp);
+    tmp.dim = 3;
+    memcpy(tmp.lat, lat, sizeof tmp.lat);
+    double bm[9];
+    recip_vectors(&tmp, bm);
+    /* Ainv[e][d] = bm[d][e] / 2 pi */
+    double ainv[9];
+    for (int e = 0; e < 3; ++e)
+        for (int d = 0; d < 3; ++d) ainv[3 * e + d] = bm[3 * d + e] / (2 * O_PI);
+    int nn[3] = {n1, n2, n3};
+    /* J[e][d] = d x_d / d r_e */
+    double J[9];
+    for (int e = 0; e < 3; ++e)
+        for (int d = 0; d < 3; ++d) J[3 * e + d] = ainv[3 * e + d] * nn[d];
+    for (int p = 0; p < n_pts; ++p) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) {
+            double s = 0;
+            for (int e = 0; e < 3; ++e) s += pos[3 * p + e] * ainv[3 * e + d];
+            x[d] = nn[d] * s;
+        }
+        double *v = val + (size_t)p * n_orb;
+        double *g = grad ? grad + (size_t)p * 3 * n_orb : NULL;
+        double *l = lap ? lap + (size_t)p * n_orb : NULL;
+        for (int m = 0; m < n_orb; ++m) {
+            v[m] = 0;
+            if (g) g[m] = g[n_orb + m] = g[2 * n_orb + m] = 0;
+            if (l) l[m] = 0;
+        }
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n2; ++j)
+                for (int k = 0; k < n3; ++k) {
+                    int idx[3] = {i, j, k};
+                    double off[3], th[3][3];
+                    int inside = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        off[d] = x[d] - idx[d];
+                        off[d] -= nn[d] * floor(off[d] / nn[d] + 0.5); /* nearest periodic image */
+                        if (fabs(off[d]) >= 2.0) inside = 0;
+                        for (int q = 0; q < 3; ++q) th[d][q] = blip_th(off[d], q);
+                    }
+                    if (!inside) continue;
+                    double b = th[0][0] * th[1][0] * th[2][0];
+                    /* derivatives of the product in x */
+                    double dx[3] = {th[0][1] * th[1][0] * th[2][0], th[0][0] * th[1][1] * th[2][0],
+                                    th[0][0] * th[1][0] * th[2][1]};
+                    double hx[9];
+                    for (int d = 0; d < 3; ++d)
+                        for (int d2 = 0; d2 < 3; ++d2) {
+                            double prod = 1;
+                            for (int c = 0; c < 3; ++c) {
+                                int order = (c == d) + (c == d2);
+                                prod *= th[c][order];
+                            }
+                            hx[3 * d + d2] = prod;
+                        }
+                    double gr[3] = {0, 0, 0}, lp = 0;
+                    for (int e = 0; e < 3; ++e) {
+                        for (int d = 0; d < 3; ++d) gr[e] += J[3 * e + d] * dx[d];
+                        for (int d = 0; d < 3; ++d)
+                            for (int d2 = 0; d2 < 3; ++d2) lp += J[3 * e + d] * J[3 * e + d2] * hx[3 * d + d2];
+                    }
+                    const double *a = coef + (((size_t)i * n2 + j) * n3 + k) * (size_t)n_orb;
+                    for (int m = 0; m < n_orb; ++m) {
+                        v[m] += a[m] * b;
+                        if (g)
+                            for (int e = 0; e < 3; ++e) g[e * n_orb + m] += a[m] * gr[e];
+                        if (l) l[m] += a[m] * lp;
+                    }
+                }
+    }
+    return 0;
+}

@@ -59,6 +59,7 @@ def _load(path: str = _LIB):
         lib.oracle_run_batch.argtypes = [P(_OSys), i, i, i, P(d), P(d), i, P(ctypes.c_int32),
                                          P(d), P(ctypes.c_uint8), P(d), P(d), P(d), P(d), i]
         lib.oracle_run_batch.restype = i
+        lib.oracle_blip_eval.argtypes = [P(d), i, i, i, i, P(d), i, P(d), P(d), P(d), P(d)]
         _libs[path] = lib
     return _libs[path]
 
@@ -252,6 +253,28 @@ def run_batch(system, mobile_pos, k, new_pos, accept, jastrow_a=None, n_threads=
     return dict(e0=e0, j0=j0, delta=delta, djas=djas, threads=used)
 
 
+def blip_eval(lattice, grid, coef, pos, derivs=True, _path=_LIB):
+    """Blip orbitals at Cartesian points: coef [n1][n2][n3][n_orb], pos [P][3].
+    Returns (val [P][n_orb], grad [P][3][n_orb], lap [P][n_orb]) (the last two
+    None without derivs)."""
+    lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64)[:3, :3]).reshape(-1)
+    n1, n2, n3 = (int(x) for x in grid)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    n_orb = int(coef.shape[-1])
+    assert coef.shape == (n1, n2, n3, n_orb)
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    P = int(pos.shape[0])
+    val = np.zeros((P, n_orb))
+    grad = np.zeros((P, 3, n_orb)) if derivs else None
+    lap = np.zeros((P, n_orb)) if derivs else None
+    null = ctypes.POINTER(ctypes.c_double)()
+    _load(_path).oracle_blip_eval(_ptr(lat, ctypes.c_double), n1, n2, n3, n_orb, _ptr(coef, ctypes.c_double), P,
+                                  _ptr(pos, ctypes.c_double), _ptr(val, ctypes.c_double),
+                                  null if grad is None else _ptr(grad, ctypes.c_double),
+                                  null if lap is None else _ptr(lap, ctypes.c_double))
+    return val, grad, lap
+
+
 class Variant:
     """The same front end bound to another build of oracle.c (used by the
     mutation tests, which compile deliberately broken copies)."""
@@ -279,5 +302,8 @@ class Variant:
 
     def run_batch(self, system, mobile_pos, k, new_pos, accept, jastrow_a=None, n_threads=0):
         return run_batch(system, mobile_pos, k, new_pos, accept, jastrow_a, n_threads, self.path)
+
+    def blip_eval(self, lattice, grid, coef, pos, derivs=True):
+        return blip_eval(lattice, grid, coef, pos, derivs, self.path)
 
     particles = staticmethod(particles)

@@ -11,6 +11,7 @@ import oracle
 from oracle.oracle import Variant, build
 from tests import test_oracle_pins as pins
 from tests import test_oracle_pins_u as upins
+from tests import test_oracle_pins_blip as bpins
 
 SRC = os.path.join(os.path.dirname(oracle.lib_path()), "oracle.c")
 
@@ -50,6 +51,16 @@ MUTATIONS = [
     ("u_lap_dim", "l += d2u + (dim - 1) * du / rho;", "l += d2u + dim * du / rho;"),
     ("u_grad_sign", "g[e] += du * r[e] / rho;", "g[e] -= du * r[e] / rho;"),
     ("u_delta_old_sign", "dj += un - uo;", "dj += un + uo;"),
+    ("blip_inner_cubic", "return 1.0 - 1.5 * x * x + 0.75 * ax * ax * ax;", "return 1.0 - 1.5 * x * x + 0.5 * ax * ax * ax;"),
+    ("blip_outer_power", "return 0.25 * t * t * t;", "return 0.25 * t * t;"),
+    ("blip_d1_sign", "return -0.75 * sg * t * t;", "return 0.75 * sg * t * t;"),
+    ("blip_d2_inner", "return -3.0 + 4.5 * ax;", "return -3.0 + 3.0 * ax;"),
+    ("blip_jacobian_transposed", "J[3 * e + d] = ainv[3 * e + d] * nn[d];", "J[3 * e + d] = ainv[3 * d + e] * nn[d];"),
+    ("blip_lap_diagonal_only", "lp += J[3 * e + d] * J[3 * e + d2] * hx[3 * d + d2];",
+     "lp += (d == d2) * J[3 * e + d] * J[3 * e + d2] * hx[3 * d + d2];"),
+    ("blip_no_wrap", "off[d] -= nn[d] * floor(off[d] / nn[d] + 0.5);", "off[d] -= 0.0;"),
+    ("blip_grid_scale", "x[d] = nn[d] * s;", "x[d] = (nn[d] - 1) * s;"),
+    ("blip_coef_index", "(((size_t)i * n2 + j) * n3 + k)", "(((size_t)i * n3 + j) * n2 + k)"),
 ]
 
 CHECKS = [
@@ -72,6 +83,12 @@ CHECKS = [
     lambda o: upins.test_u_order_c_zero_at_cutoff(o),
     lambda o: [upins.test_u_derivs_finite_differences(o, d) for d in (3, 2)],
     lambda o: [upins.test_u_incremental_moves_and_invariance(o, c) for c in (1, 3)],
+    lambda o: bpins.test_blip_partition_of_unity(o),
+    lambda o: bpins.test_blip_linear_reproduction(o),
+    lambda o: [bpins.test_blip_plane_wave_at_nodes(o, m) for m in ((1, 0, 0), (2, -3, 1), (0, 4, 5))],
+    lambda o: bpins.test_blip_lattice_periodicity(o),
+    lambda o: bpins.test_blip_derivs_finite_differences(o),
+    lambda o: bpins.test_blip_function_values(o),
 ]
 
 

@@ -12,9 +12,11 @@ tests/test_oracle_pins_u.py for the Jastrow u term (hand-evaluated values,
 the Kato cusp, the order-C zero at the cutoff, finite differences, images)
 and by tests/test_oracle_pins_blip.py for the blip orbitals (partition of
 unity, reproduction of linear functions, plane waves at grid nodes, lattice
-periodicity, finite differences).
+periodicity, finite differences) and by tests/test_oracle_pins_layers.py
+for layered 2D systems (the z = 0 limit, alpha independence at z != 0, the
+charged-sheet limit, symmetries, incremental moves).
 """
 from .oracle import (  # noqa: F401
     build, lib_path, count_g, gvectors, rho_at, energy, jastrow_derivs, run, run_batch, particles, Variant,
-    blip_eval, spins,
+    blip_eval, spins, heights,
 )

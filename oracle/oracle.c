@@ -56,6 +56,18 @@
  *   lap_k J  = 2 q_k sum_{j != k} q_j lap P(r_k - r_j),   lap P(r)  = -1/2 sum_G a |G|^2 cos(G.r)
  * evaluated by direct pair and G loops (no structure factor).
  *
+ * Layered two-dimensional systems (2D cell, particles at heights z_i): the
+ * energy is taken straight from the pair potential of Eq. (5) and the
+ * Madelung term of Eq. (6) (gamma = alpha^2),
+ *   E = sum_{i<j} q_i q_j v_E(r_i - r_j, z_i - z_j) + 1/2 sum_i q_i^2 v_M,
+ *   v_E = (pi/A) sum_{G != 0} [e^{zG} erfc(G/2a + z a) + e^{-zG} erfc(G/2a - z a)]/G cos(G.r)
+ *       + sum_R erfc(a d_R)/d_R  (d_R = sqrt(|r - R|^2 + z^2) < r_cut, R in the plane)
+ *       - (2 pi/A) [z erf(z a) + exp(-a^2 z^2)/(a sqrt(pi))],
+ * pair by pair over the full G set (no structure factors), reported in the
+ * same four parts (the z-dependent constant as the background part).  Moves
+ * are in the plane (a particle keeps its height); the delta is the change of
+ * the pair sum over the moved particle's partners.
+ *
  * Jastrow two-body polynomial term (paper Sec. 2.3, Eq. (8)), optional:
  *   u_c(r) = sum_{l=0}^{N_u} alpha_{c,l} r^l (r - L_u)^C   for r < L_u, else 0,
  * with a coefficient set c per spin channel (c = 0 for a pair of equal spin
@@ -92,6 +104,7 @@ typedef struct {
     double u_cut;            /* L_u */
     const double *u_alpha;   /* [2][n_u]: channel 0 equal spin labels, 1 unequal */
     const int *spin;         /* [n] per particle: spin label, negative = no u term */
+    const double *z;         /* 2D: [n] heights of the particles (layered systems), or NULL (z = 0) */
 } osys;
 
 /* ---- small helpers (plain, written out) -------------------------------- */
@@ -252,6 +265,100 @@ static double real_image_sum(const osys *s, const double *bm, const double *dv, 
     return sum;
 }
 
+/* ---- layered 2D systems (Eq. (5) with z != 0) ------------------------------------ */
+
+/* sum over in-plane lattice vectors R of erfc(a d)/d, d = sqrt(|dv - R|^2 + z^2) < r_cut */
+static double real_image_sum_z(const osys *s, const double *bm, const double *dv, double z) {
+    double rc = s->r_cut, a = s->alpha;
+    int lo[2], hi[2];
+    for (int d = 0; d < 2; ++d) {
+        double f = (dv[0] * bm[3 * d] + dv[1] * bm[3 * d + 1]) / (2 * O_PI);
+        double ext = rc * vnorm(bm + 3 * d, 2) / (2 * O_PI);
+        lo[d] = (int)floor(f - ext);
+        hi[d] = (int)ceil(f + ext);
+    }
+    double sum = 0;
+    for (int i = lo[0]; i <= hi[0]; ++i)
+        for (int j = lo[1]; j <= hi[1]; ++j) {
+            double r0 = dv[0] - (i * s->lat[0] + j * s->lat[3]);
+            double r1 = dv[1] - (i * s->lat[1] + j * s->lat[4]);
+            double dist = sqrt(r0 * r0 + r1 * r1 + z * z);
+            if (dist < rc) sum += erfc(a * dist) / dist;
+        }
+    return sum;
+}
+
+/* (pi/A) sum_{G != 0} [e^{zG} erfc(G/2a + za) + e^{-zG} erfc(G/2a - za)]/G cos(G.r) */
+static double recip_pair_2d(const osys *s, const gset *g, const double *dv, double z, double area) {
+    double a = s->alpha, sum = 0;
+    for (int t = 0; t < g->n; ++t) {
+        double gg = sqrt(g->g2[t]);
+        double f = exp(z * gg) * erfc(gg / (2 * a) + z * a) + exp(-z * gg) * erfc(gg / (2 * a) - z * a);
+        sum += f / gg * cos(g->g[3 * t] * dv[0] + g->g[3 * t + 1] * dv[1]);
+    }
+    return O_PI / area * sum;
+}
+
+/* the z-dependent constant of v_E: -(2 pi/A) [z erf(z a) + exp(-a^2 z^2)/(a sqrt(pi))] */
+static double const_pair_2d(const osys *s, double z, double area) {
+    double a = s->alpha;
+    return -2 * O_PI / area * (z * erf(z * a) + exp(-a * a * z * z) / (a * sqrt(O_PI)));
+}
+
+/* Energy parts of a layered 2D configuration, pair by pair. */
+static void energy_layered(const osys *s, int n, const double *pos, const double *q, double *parts) {
+    double bm[9];
+    recip_vectors(s, bm);
+    double area = cell_measure(s), a = s->alpha;
+    gset g;
+    gset_build(s, &g);
+    double e_real = 0, e_recip = 0, e_bg = 0, q2 = 0;
+    for (int i = 0; i < n; ++i) {
+        q2 += q[i] * q[i];
+        for (int j = i + 1; j < n; ++j) {
+            double dv[2] = {pos[2 * i] - pos[2 * j], pos[2 * i + 1] - pos[2 * j + 1]};
+            double z = s->z[i] - s->z[j];
+            double qq = q[i] * q[j];
+            e_real += qq * real_image_sum_z(s, bm, dv, z);
+            e_recip += qq * recip_pair_2d(s, &g, dv, z, area);
+            e_bg += qq * const_pair_2d(s, z, area);
+        }
+    }
+    /* 1/2 sum_i q_i^2 v_M: own images, the G sum at z = 0, and the constants */
+    double zero[3] = {0, 0, 0};
+    e_real += 0.5 * q2 * real_image_sum(s, bm, zero, 1);
+    double vm_recip = 0;
+    for (int t = 0; t < g.n; ++t) {
+        double gg = sqrt(g.g2[t]);
+        vm_recip += erfc(gg / (2 * a)) / gg;
+    }
+    e_recip += 0.5 * q2 * 2 * O_PI / area * vm_recip;
+    e_bg += 0.5 * q2 * (-2 * sqrt(O_PI) / (area * a));
+    gset_free(&g);
+    parts[0] = e_real;
+    parts[1] = e_recip;
+    parts[2] = -a / sqrt(O_PI) * q2;
+    parts[3] = e_bg;
+    parts[4] = parts[0] + parts[1] + parts[2] + parts[3];
+}
+
+/* Change of the layered energy when particle k moves in its plane to rn:
+ * q_k sum_{j != k} q_j [V(rn - r_j) - V(r_k - r_j)] (the constant cancels). */
+static double delta_layered(const osys *s, const double *bm, const gset *g, int n, const double *pos,
+                            const double *q, int k, const double *rn) {
+    double area = cell_measure(s), sum = 0;
+    for (int j = 0; j < n; ++j) {
+        if (j == k) continue;
+        double z = s->z[k] - s->z[j];
+        double dn[2] = {rn[0] - pos[2 * j], rn[1] - pos[2 * j + 1]};
+        double dold[2] = {pos[2 * k] - pos[2 * j], pos[2 * k + 1] - pos[2 * j + 1]};
+        double vn = real_image_sum_z(s, bm, dn, z) + recip_pair_2d(s, g, dn, z, area);
+        double vo = real_image_sum_z(s, bm, dold, z) + recip_pair_2d(s, g, dold, z, area);
+        sum += q[j] * (vn - vo);
+    }
+    return q[k] * sum;
+}
+
 /* ---- Jastrow u term ------------------------------------------------------------ */
 
 /* u_c(r), u_c'(r), u_c''(r) of Eq. (8), for 0 <= r < L_u. */
@@ -376,6 +483,11 @@ int oracle_rho_at(const osys *s, int n, const double *pos, const double *q, int 
 int oracle_energy(const osys *s, int n, const double *pos, const double *q, double *parts,
                   double *jastrow) {
     int dim = s->dim;
+    if (dim == 2 && s->z) { /* layered: no Jastrow terms */
+        energy_layered(s, n, pos, q, parts);
+        if (jastrow) *jastrow = 0.0;
+        return 0;
+    }
     double bm[9];
     recip_vectors(s, bm);
     double meas = cell_measure(s);
@@ -509,6 +621,13 @@ int oracle_run(const osys *s, int n, int n_mobile, const double *pos0, const dou
         int kk = k[m];
         const double *rn = new_pos + (size_t)dim * (size_t)m;
         const double *ro = pos + dim * kk;
+        if (dim == 2 && s->z) { /* layered: pair form */
+            delta[m] = delta_layered(s, bm, &g, n, pos, q, kk, rn);
+            djas[m] = 0.0;
+            if (accept[m])
+                for (int e = 0; e < dim; ++e) pos[dim * kk + e] = rn[e];
+            continue;
+        }
         /* real space */
         double dr = 0;
         for (int j = 0; j < n; ++j) {

@@ -36,7 +36,8 @@ class _OSys(ctypes.Structure):
                 ("g_cut", ctypes.c_double), ("n_jastrow", ctypes.c_int),
                 ("jastrow_a", ctypes.POINTER(ctypes.c_double)),
                 ("n_u", ctypes.c_int), ("u_c", ctypes.c_int), ("u_cut", ctypes.c_double),
-                ("u_alpha", ctypes.POINTER(ctypes.c_double)), ("spin", ctypes.POINTER(ctypes.c_int))]
+                ("u_alpha", ctypes.POINTER(ctypes.c_double)), ("spin", ctypes.POINTER(ctypes.c_int)),
+                ("z", ctypes.POINTER(ctypes.c_double))]
 
 
 _libs = {}
@@ -72,7 +73,8 @@ class _Sys:
     """Keeps the ctypes struct and the arrays it points to alive together."""
 
     def __init__(self, dim, lattice, alpha, r_cut, g_cut, jastrow_a=None, u_alpha=None, u_C=3, u_cut=0.0,
-                 spin=None):
+                 spin=None, z=None):
+        self.z = None if z is None else np.ascontiguousarray(z, dtype=np.float64)
         self.ja = None if jastrow_a is None else np.ascontiguousarray(jastrow_a, dtype=np.float64)
         self.ua = None if u_alpha is None else np.ascontiguousarray(u_alpha, dtype=np.float64).reshape(2, -1)
         self.spin = None if spin is None else np.ascontiguousarray(spin, dtype=np.int32)
@@ -97,6 +99,7 @@ class _Sys:
             s.n_u, s.u_c, s.u_cut = int(self.ua.shape[1]), int(u_C), float(u_cut)
             s.u_alpha = _ptr(self.ua, ctypes.c_double)
             s.spin = _ptr(self.spin, ctypes.c_int)
+        s.z = ctypes.POINTER(ctypes.c_double)() if self.z is None else _ptr(self.z, ctypes.c_double)
         self.s = s
 
     def ref(self):
@@ -113,9 +116,24 @@ def spins(system) -> Optional[np.ndarray]:
     return np.concatenate([ms, -np.ones(system.n_fixed, dtype=np.int32)])
 
 
+def heights(system) -> Optional[np.ndarray]:
+    """Heights of all particles of a layered 2D system (mobile first, then the
+    fixed ions), or None for a strictly two- or three-dimensional one."""
+    lz = getattr(system, "layer_z", None)
+    if lz is None:
+        return None
+    lz = np.asarray(lz, dtype=np.float64)
+    ml = np.asarray(system.mobile_layer, dtype=np.int64)
+    fl = getattr(system, "fixed_layer", None)
+    fl = np.zeros(system.n_fixed, dtype=np.int64) if fl is None else np.asarray(fl, dtype=np.int64)
+    return np.concatenate([lz[ml], lz[fl]])
+
+
 def _mk(system, jastrow_a=None, spin=None, **over):
     kw = dict(dim=system.dim, lattice=system.lattice, alpha=system.alpha,
               r_cut=system.r_cut, g_cut=system.g_cut)
+    if getattr(system, "layer_z", None) is not None:
+        kw.update(z=heights(system))
     if getattr(system, "u_alpha", None) is not None:
         kw.update(u_alpha=system.u_alpha, u_C=system.u_C, u_cut=system.u_cut,
                   spin=spins(system) if spin is None else spin)
@@ -169,6 +187,7 @@ def energy(system, pos, q, jastrow_a: Optional[np.ndarray] = None, _path=_LIB, *
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     q = np.ascontiguousarray(q, dtype=np.float64)
     assert s.spin is None or s.spin.shape[0] == q.shape[0], "one spin label per particle"
+    assert s.z is None or s.z.shape[0] == q.shape[0], "one height per particle"
     parts = np.zeros(5)
     jas = ctypes.c_double(0.0)
     _load(_path).oracle_energy(s.ref(), int(q.shape[0]), _ptr(pos, ctypes.c_double),

@@ -105,6 +105,11 @@ class System:
     u_C: int = 3
     u_cut: float = 0.0
     mobile_spin: Optional[np.ndarray] = None
+    # optional layered 2D system (Eq. (5) with z != 0): heights of the planes
+    # and the plane of each mobile particle (ascending) and fixed ion
+    layer_z: Optional[np.ndarray] = None
+    mobile_layer: Optional[np.ndarray] = None
+    fixed_layer: Optional[np.ndarray] = None
 
     @property
     def n_fixed(self) -> int:
@@ -308,3 +313,44 @@ def with_u_term(system: System, cfg_id: int) -> System:
     n = system.n_mobile
     spin = np.concatenate([np.zeros(n // 2, dtype=np.int32), np.ones(n - n // 2, dtype=np.int32)])
     return dataclasses.replace(system, u_alpha=a, u_C=U_C, u_cut=Lu, mobile_spin=spin)
+
+
+# Blip orbitals (Sec. 2.4): the N = 1024 bcc electron-gas cell with N/2 = 512
+# orbitals per spin on a 40^3 grid (0.41 bohr spacing, about eight points per
+# Fermi wavelength at r_s = 1), coefficients U(-1, 1) from stream 6 (no
+# trained orbitals are available), evaluated at the workload's seeded
+# proposals (one proposed position per walker and move).
+BLIP_GRID = (40, 40, 40)
+BLIP_ORBITALS = 512
+
+
+def blip_coefficients(grid=BLIP_GRID, n_orb: int = BLIP_ORBITALS, seed_cfg: int = 5) -> np.ndarray:
+    """Seeded blip coefficients [n1][n2][n3][n_orb] (float64)."""
+    return rng(seed_cfg, 6).uniform(-1.0, 1.0, size=tuple(grid) + (int(n_orb),))
+
+
+def blip_points(walkers: int, moves: int) -> np.ndarray:
+    """Cartesian evaluation points [moves * walkers][3]: the proposals of the
+    N = 1024 workload's first walkers and moves."""
+    b = make_batch(config(5), walkers=walkers, moves=moves)
+    return np.ascontiguousarray(b.new_pos.reshape(-1, 3))
+
+
+def bilayer(n_each: int = 150, d: float = 5.0, rs: float = 5.0) -> System:
+    """Electron-hole bilayer (Eq. (5) with z != 0): the hexagonal cell of the
+    2D workload (area pi r_s^2 N for N = 2 n_each), n_each electrons
+    (charge -1) in the plane z = 0 and n_each holes (charge +1) in the plane
+    z = d; alpha = 5/L, r_c = L/2, |G| <= 8 (2 pi / L) as for the 2D gas."""
+    n = 2 * n_each
+    s = _heg(f"bilayer{n}", 2, hex_cell(math.pi * rs * rs * n), n, 8.0)
+    q = np.concatenate([-np.ones(n_each), np.ones(n_each)])
+    layer = np.concatenate([np.zeros(n_each, dtype=np.int32), np.ones(n_each, dtype=np.int32)])
+    return dataclasses.replace(s, mobile_q=q, layer_z=np.array([0.0, float(d)]), mobile_layer=layer,
+                               fixed_layer=np.zeros(0, dtype=np.int32))
+
+
+def bilayer_config() -> Config:
+    """The bilayer as a workload: 2048 walkers x 512 moves, p = 0.5, K = 64
+    (seeds of the 2D gas, cfg 3, so positions and proposals are its draws)."""
+    return Config(3, "electron-hole bilayer, hexagonal cell, 150 + 150 particles, d = r_s = 5",
+                  [bilayer()], 2048, 512, 0.5, 64)

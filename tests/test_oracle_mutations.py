@@ -12,6 +12,7 @@ from oracle.oracle import Variant, build
 from tests import test_oracle_pins as pins
 from tests import test_oracle_pins_u as upins
 from tests import test_oracle_pins_blip as bpins
+from tests import test_oracle_pins_layers as lpins
 
 SRC = os.path.join(os.path.dirname(oracle.lib_path()), "oracle.c")
 
@@ -61,6 +62,15 @@ MUTATIONS = [
     ("blip_no_wrap", "off[d] -= nn[d] * floor(off[d] / nn[d] + 0.5);", "off[d] -= 0.0;"),
     ("blip_grid_scale", "x[d] = nn[d] * s;", "x[d] = (nn[d] - 1) * s;"),
     ("blip_coef_index", "(((size_t)i * n2 + j) * n3 + k)", "(((size_t)i * n3 + j) * n2 + k)"),
+    ("layer_exp_sign", "double f = exp(z * gg) * erfc(gg / (2 * a) + z * a)",
+     "double f = exp(-z * gg) * erfc(gg / (2 * a) + z * a)"),
+    ("layer_const_erf", "return -2 * O_PI / area * (z * erf(z * a)", "return -2 * O_PI / area * (z * erfc(z * a)"),
+    ("layer_const_gauss", "exp(-a * a * z * z) / (a * sqrt(O_PI))", "exp(-a * z * z) / (a * sqrt(O_PI))"),
+    ("layer_real_z_dropped", "double dist = sqrt(r0 * r0 + r1 * r1 + z * z);", "double dist = sqrt(r0 * r0 + r1 * r1);"),
+    ("layer_recip_prefactor", "return O_PI / area * sum;", "return 2 * O_PI / area * sum;"),
+    ("layer_delta_same_plane", "double z = s->z[k] - s->z[j];", "double z = 0.0;"),
+    ("layer_madelung_factor", "e_recip += 0.5 * q2 * 2 * O_PI / area * vm_recip;",
+     "e_recip += 0.5 * q2 * O_PI / area * vm_recip;"),
 ]
 
 CHECKS = [
@@ -89,6 +99,11 @@ CHECKS = [
     lambda o: bpins.test_blip_lattice_periodicity(o),
     lambda o: bpins.test_blip_derivs_finite_differences(o),
     lambda o: bpins.test_blip_function_values(o),
+    lambda o: lpins.test_layers_zero_height_equals_2d(o),
+    lambda o: [lpins.test_layers_alpha_independence(o, d) for d in (0.7, 2.5)],
+    lambda o: lpins.test_layers_charged_sheets(o),
+    lambda o: lpins.test_layers_invariances(o),
+    lambda o: lpins.test_layers_incremental_moves(o),
 ]
 
 

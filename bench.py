@@ -35,6 +35,15 @@ FLOP_PER_G_DELTA = 36        # two table phases (old/new), delta, t(G), weighted
 FLOP_PER_PAIR_DELTA = 55     # FP64 geometry, erfc, 1/r per pair evaluation
 FLOP_PER_G_PARTICLE = 10     # one phase product and one complex accumulate when rebuilding rho
 FLOP_PER_PAIR_ENERGY = 55
+# Jastrow p-term derivatives per G and move: rho' (2 FMA), Im/Re of conj(rho') e' (2 FMA + 2 MUL),
+# a Im z (1), the three running sums (1 ADD + 2 FMA)
+FLOP_PER_G_DERIV = 16
+# Jastrow u term: one evaluation of the product form sum_l alpha_l r^l (r - L_u)^C costs
+# N_u + C multiply-adds; a move evaluates it at the old and new distance of every partner
+U_TERMS, U_C = 9, 3
+FLOP_PER_U_EVAL = 2 * (U_TERMS - 1 + U_C)
+# blip orbitals: 5 FMAs (value, gradient, Laplacian) per coefficient read
+BLIP_WINDOW = 64
 
 
 def algorithmic_flops_per_delta(n_g: int, n_part: int) -> float:
@@ -227,6 +236,155 @@ def other_workload(cfg_id: int, precision: int, steps: int = 2, threads: int = 0
     return out
 
 
+def timed_sweep(batch, t, delta, djas, jgrad=None, jlap=None, reps: int = 2):
+    """Mean time (ms) of the fused sweep over the workload's proposals, each
+    repetition from the same initial state (energy call first, untimed)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    W = delta.shape[1]
+    energy = torch.zeros(W, dtype=torch.float64, device=delta.device)
+    jas = None if djas is None else torch.zeros(W, dtype=torch.float64, device=delta.device)
+    times = []
+    for it in range(reps + 1):
+        batch.energy(t["pos"], energy, jas)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if jgrad is None:
+            batch.run_moves(t["k"], t["new_pos"], t["accept"], delta, djas)  # djas may be None
+        else:
+            batch.run_moves_grad(t["k"], t["new_pos"], t["accept"], delta, djas, jgrad, jlap)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it:  # the first pass warms up
+            times.append(e0.elapsed_time(e1))
+    return float(np.mean(times))
+
+
+def next_rows(cfg, b, t, K: int, forms=("mixed", "fp64")):
+    """The rows built beyond the Ewald path, on the N=1024 workload: the
+    fused sweep with the Jastrow gradient and Laplacian of every proposed
+    move, and the sweep with the Jastrow two-body u term; deltas/s and the
+    fused kernel's VALU fraction by the algorithmic counts above."""
+    import torch
+    from paper_2507_02888_amd import ewald as ew
+    from paper_2507_02888_amd import workloads as wl
+    sysm = cfg.systems[0]
+    W, S = b.walkers, b.steps
+    dev = "cuda"
+    out = {}
+    for form in forms:
+        prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
+        kk = K if prec == ew.EWALD_FP32_MIXED else 0
+        n_ref = int(np.sum(b.accept.sum(axis=0) // kk)) if kk else 0
+        for row in ("jastrow_derivs", "u_term"):
+            sm = wl.with_u_term(sysm, 5) if row == "u_term" else sysm
+            s = ew.System(sm, precision=prec, refresh_every=kk, jastrow_a=b.jastrow_a)
+            batch = ew.Batch([s], b.walker_sys, device=dev)
+            batch.energy(t["pos"], torch.zeros(W, dtype=torch.float64, device=dev))
+            batch.autotune(n_moves=max(64, 2 * kk) if kk else 64)
+            delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
+            djas = torch.zeros_like(delta)
+            n_g, n = s.info["n_g"], sm.n_mobile
+            flops = W * S * algorithmic_flops_per_delta(n_g, n) + n_ref * algorithmic_flops_per_rebuild(n_g, n)
+            if row == "jastrow_derivs":
+                jg = torch.zeros((S, W, 3), dtype=torch.float64, device=dev)
+                jl = torch.zeros((S, W), dtype=torch.float64, device=dev)
+                ms = timed_sweep(batch, t, delta, djas, jg, jl)
+                flops += W * S * n_g * FLOP_PER_G_DERIV
+                del jg, jl
+            else:
+                ms = timed_sweep(batch, t, delta, djas)
+                flops += W * S * 2 * (n - 1) * FLOP_PER_U_EVAL
+            out.setdefault(row, {})[form] = dict(
+                run_deltas_per_s=round(W * S / (ms * 1e-3), 1), launch_ms=round(ms, 4),
+                achieved_tflops=round(flops / (ms * 1e-3) / 1e12, 3),
+                frac=round(flops / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4), launch_shape=batch.tuning())
+            batch.close()
+            s.close()
+    out["jastrow_derivs"]["call"] = "ewald_run_moves_grad_batch (gradient and Laplacian of J per proposed move)"
+    out["u_term"]["call"] = "ewald_run_moves_batch with the two-body u term (N_u = 8, C = 3, L_u = r_inscribed)"
+    return out
+
+
+def layers_row(forms=("mixed", "fp64"), steps: int = 2):
+    """The electron-hole bilayer (two planes, Eq. (5) with z != 0; 2048
+    walkers x 512 moves): ewald_run_moves_batch, which runs the per-step
+    delta and accept kernels for layered batches.  deltas/s and the per-step
+    kernels' fraction of HBM bandwidth by their algorithmic bytes per move
+    (both planes' rho and the positions read by the delta, the moved plane's
+    rho read and written by an accepted move)."""
+    import torch
+    from paper_2507_02888_amd import ewald as ew
+    from paper_2507_02888_amd import workloads as wl
+    cfg = wl.bilayer_config()
+    b = wl.make_batch(cfg)
+    sm = cfg.systems[0]
+    dev = "cuda"
+    t = dict(pos=torch.tensor(b.pos, device=dev), k=torch.tensor(b.k, device=dev),
+             new_pos=torch.tensor(b.new_pos, device=dev), accept=torch.tensor(b.accept, device=dev))
+    W, S = b.walkers, b.steps
+    out = {}
+    for form in forms:
+        prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
+        h = ew.System(sm, precision=prec, refresh_every=cfg.refresh_every if form == "mixed" else 0)
+        batch = ew.Batch([h], b.walker_sys, device=dev)
+        delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
+        ms = timed_sweep(batch, t, delta, None, reps=steps)
+        slots = h.info["n_slots"]
+        p_acc = float(b.accept.mean())
+        bytes_per_move = 2 * 16 * slots + 8 * 2 * sm.n_mobile + p_acc * 2 * 16 * slots
+        gbs = W * S * bytes_per_move / (ms * 1e-3) / 1e9
+        out[form] = dict(run_deltas_per_s=round(W * S / (ms * 1e-3), 1), launch_ms=round(ms, 4),
+                         roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                                       frac=round(gbs / PEAK_HBM_GBS, 4), bytes_per_move=round(bytes_per_move, 1)),
+                         fused=batch.tuning()["fused"])
+        batch.close()
+        h.close()
+    out["call"] = ("ewald_run_moves_batch on the electron-hole bilayer (150 + 150 particles, d = 5 bohr), "
+                   "per-step kernels; the state (17 MB) stays in the last-level cache")
+    return out
+
+
+def blip_row(reps: int = 5):
+    """Batched blip orbitals: 512 orbitals on a 40^3 grid over the N=1024
+    cell at 65536 proposal points per call, values, gradients and
+    Laplacians; points/s and the kernel's fraction of HBM bandwidth by the
+    algorithmic bytes (64 coefficient rows read, 5 outputs written per
+    orbital and point)."""
+    import torch
+    from paper_2507_02888_amd import ewald as ew
+    from paper_2507_02888_amd import workloads as wl
+    dev = "cuda"
+    lat = wl.config(5).systems[0].lattice
+    M = wl.BLIP_ORBITALS
+    coef = torch.tensor(wl.blip_coefficients(), device=dev)
+    pts = torch.tensor(wl.blip_points(8192, 8), device=dev)
+    P = int(pts.shape[0])
+    val = torch.zeros((P, M), dtype=torch.float64, device=dev)
+    grad = torch.zeros((P, 3, M), dtype=torch.float64, device=dev)
+    lap = torch.zeros_like(val)
+    b = ew.Blips(lat, wl.BLIP_GRID, M)
+    stream = torch.cuda.current_stream()
+    b.eval(coef, pts, val, grad, lap)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.eval(coef, pts, val, grad, lap)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bytes_per_point = BLIP_WINDOW * M * 8 + 5 * M * 8 + 24
+    gbs = P * bytes_per_point / (ms * 1e-3) / 1e9
+    coef_mb = coef.numel() * 8 / 1e6
+    b.close()
+    return dict(points_per_s=round(P / (ms * 1e-3), 1), launch_ms=round(ms, 4), points=P, orbitals=M,
+                grid=list(wl.BLIP_GRID), coefficient_mb=round(coef_mb, 1),
+                roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                              frac=round(gbs / PEAK_HBM_GBS, 4), bytes_per_point=bytes_per_point),
+                call="ewald_blip_eval_batch (values, gradients, Laplacians; FP64)")
+
+
 def host_threads() -> int:
     """Threads for the oracle: the OpenMP setting where the host sets one (the
     GPU host's share of its cores), else every core this process may use."""
@@ -342,6 +500,8 @@ def main():
                     help="further refresh intervals K timed for the mixed form (0 = no rebuild); empty to skip")
     ap.add_argument("--other", default="2,3,4",
                     help="smaller configurations also timed (both forms), reported under other_workloads")
+    ap.add_argument("--next", default="derivs,u,blips,layers",
+                    help="rows beyond the Ewald path also timed (jastrow derivatives, u term, blips); empty to skip")
     ap.add_argument("--skip-main", action="store_true",
                     help="time only the smaller configurations (--other); prints their results, not the bench line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -422,6 +582,15 @@ def main():
                               frac=round(flops_run / (r["run_ms"] * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4),
                               drift_max=r["drift_max"] if k_alt > 0 else None))
 
+    nxt = {}
+    want = set(x for x in args.next.split(",") if x)
+    if want & {"derivs", "u"}:
+        nxt.update(next_rows(cfg, b, tensors, K, forms=tuple(f for f in args.forms.split(","))))
+    if "blips" in want:
+        nxt["blips"] = blip_row()
+    if "layers" in want:
+        nxt["layers"] = layers_row(forms=tuple(f for f in args.forms.split(",")))
+
     others = []
     if args.other:
         for cid in [int(x) for x in args.other.split(",")]:
@@ -469,6 +638,8 @@ def main():
                                             frac=k_main["roofline"]["frac"], drift_max=k_main["drift_max"])] + sweep
     if others:
         line["other_workloads"] = others
+    if nxt:
+        line["next_rows"] = nxt
     if "fp64" in results and "mixed" in results:
         f = results["fp64"]
         line["fp64"] = {"value": round(f["value"], 1), "unit": "deltas/s", "ms_per_step": round(f["ms_per_step"], 3),

@@ -21,10 +21,20 @@
  *   E_self       = -(alpha/sqrt(pi)) sum_i q_i^2
  *   E_background = -(pi/(2 Omega alpha^2)) Q^2 (3D),  -(sqrt(pi)/(A alpha)) Q^2 (2D)
  *
- * and, optionally, the long-range plane-wave Jastrow value of Sec. 2.3
- * (Eq. (9) expressed through the same structure factor)
+ * Layered 2D systems (two planes at heights z_0, z_1, d = z_1 - z_0; the
+ * z-dependent terms of Eq. (5)): rho_l(G) per plane,
+ *   E_recip = sum_{G in H} [w (|rho_0|^2 + |rho_1|^2) + 2 w_x Re(rho_0 conj(rho_1))],
+ *   w_x = (pi/A) [e^{dG} erfc(G/2alpha + d alpha) + e^{-dG} erfc(G/2alpha - d alpha)]/G,
+ * real-space pairs of different planes at distance sqrt(r^2 + d^2), and
+ *   E_background = 1/2 sum_{l,m} Q_l Q_m c(z_l - z_m),
+ *   c(z) = -(2 pi/A) [z erf(z alpha) + exp(-alpha^2 z^2)/(alpha sqrt(pi))].
  *
- *   J = sum_{G in H} a_{s(G)} |rho(G)|^2,  s(G) = shell of equal |G|, ascending.
+ * and, optionally, the Jastrow value of Sec. 2.3: the long-range plane-wave
+ * term (Eq. (9) expressed through the same structure factor) plus, when the
+ * system has one, the two-body polynomial term u of Eq. (8)
+ *
+ *   J = sum_{G in H} a_{s(G)} |rho(G)|^2 + sum_{i<j mobile} u_{c(i,j)}(r_ij),
+ *   s(G) = shell of equal |G|, ascending.
  *
  * A single-particle move (Sec. 2.1: propose a move of one particle, decide,
  * update) changes particle k from r_k to r'; the library returns
@@ -115,6 +125,25 @@ typedef struct {
     int n_jastrow;             /* number of shell coefficients a_s (0: no Jastrow);    */
                                /* coefficients past the last shell are ignored         */
     const double *jastrow_a;   /* host [n_jastrow]                                     */
+    /* Optional Jastrow two-body polynomial term (Sec. 2.3, Eq. (8)) over pairs  */
+    /* of mobile particles at their minimum-image distance r:                     */
+    /*   u_c(r) = sum_{l < u_terms} u_alpha[c][l] r^l (r - u_cutoff)^u_C, r < L_u  */
+    /* c = 0 for equal spin labels, 1 for unequal ones (parallel and antiparallel */
+    /* spins); the fixed ions take no part.                                       */
+    int u_terms;               /* N_u + 1 coefficients per channel (0: no u term);     */
+                               /* u_terms - 1 + u_C <= 15                               */
+    int u_C;                   /* C >= 1                                               */
+    double u_cutoff;           /* L_u, 0 < L_u <= r_inscribed                          */
+    const double *u_alpha;     /* host [2][u_terms]                                    */
+    const int32_t *mobile_spin; /* host [n_mobile] labels 0 or 1 (NULL: all 0)        */
+    /* Optional layered two-dimensional system (dim = 2; Sec. 2.2, Eq. (5) with  */
+    /* z != 0): particles in two parallel planes at heights layer_z[0..1];       */
+    /* moves stay in their plane.  Not combined with Jastrow terms.              */
+    int n_layers;              /* 0 or 1: one plane (z = 0); 2: two planes             */
+    double layer_z[2];         /* heights of the planes (bohr)                         */
+    int n_mobile_layer0;       /* mobile particles 0..n0-1 lie in plane 0, the rest    */
+                               /* in plane 1                                           */
+    const int32_t *fixed_layer; /* host [n_fixed] plane (0/1) of each ion (NULL: 0)    */
 } ewald_sys_desc;
 
 /* Build the cell's tables on the host in FP64 (reciprocal lattice, G set,
@@ -231,13 +260,18 @@ ewald_status ewald_run_moves_batch(ewald_batch *b, void *state, int n_steps, con
  *   grad_k J = -2 q_k sum_{G in H} a_s(G) G Im(conj(rho') exp(iG.r'))
  *   lap_k J  = -2 q_k sum_{G in H} a_s(G) |G|^2 [Re(conj(rho') exp(iG.r')) - q_k]
  *   rho' = rho + q_k (exp(iG.r') - exp(iG.r_k))
- * (for unit charges these are the derivatives of 2 sum_{j != k} p(r_k - r_j)).
+ * (for unit charges these are the derivatives of 2 sum_{j != k} p(r_k - r_j)),
+ * plus, with a u term (Eq. (8)), over the mobile j != k with r = |d| < L_u,
+ * d the minimum-image displacement r' - r_j:
+ *   grad_k U = sum_j u'(r) d / r,   lap_k U = sum_j [u''(r) + (dim - 1) u'(r) / r].
+ * The u term is evaluated in FP64 in both precision forms.
  *   jgrad  device out, Cartesian: [n_walkers][dim] (move_delta) or
  *          [n_steps][n_walkers][dim] (run_moves)
  *   jlap   device out: [n_walkers] or [n_steps][n_walkers]
  * Both NULL: exactly ewald_move_delta_batch / ewald_run_moves_batch.  An
  * invalid k gives NaN derivatives.  Status as for those calls, plus E_ARG if
- * only one of jgrad/jlap is given or the batch has no Jastrow coefficients.
+ * only one of jgrad/jlap is given or the batch has neither Jastrow
+ * coefficients nor a u term.
  * The FP32-mixed form computes z = conj(rho') exp(iG.r') in FP32 and sums
  * in FP64 across segments. */
 ewald_status ewald_move_delta_grad_batch(ewald_batch *b, void *state, const int32_t *k,
@@ -288,6 +322,35 @@ ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, in
  * E_HIP. */
 ewald_status ewald_autotune(ewald_batch *b, void *state, int n_moves, const char *cache_path,
                             void *stream);
+
+/* ---- Blip orbitals (Sec. 2.4) ------------------------------------------------
+ * Orbitals re-represented on a periodic grid of n1 x n2 x n3 points along the
+ * lattice vectors.  With fractional coordinates s = r A^-1 and x_d = n_d s_d,
+ *   psi_m(r) = sum_{i,j,k} a[i][j][k][m] Th(x_1 - i) Th(x_2 - j) Th(x_3 - k)
+ * (grid indices periodic), with the cubic B-spline blip function
+ *   Th(x) = 1 - 3/2 x^2 + 3/4 |x|^3 (|x| <= 1),  1/4 (2 - |x|)^3 (1 < |x| < 2),
+ * zero beyond, so 4 x 4 x 4 grid points take part at each point.  The
+ * evaluation after a move (the paper's 64-element products of blip functions
+ * with each orbital's coefficients, Sec. 5.3) is batched over many points. */
+typedef struct ewald_blip ewald_blip;
+
+/* A grid over the cell with rows a_i = lattice[i] (3D, bohr), grid[d] in
+ * [4, 4096] points along a_d, n_orb >= 1 orbitals.  Host only; the handle
+ * holds no device memory.  Status: E_ARG, E_LATTICE, E_NOMEM. */
+ewald_status ewald_blip_create(const double lattice[3][3], const int grid[3], int n_orb, ewald_blip **out);
+void ewald_blip_destroy(ewald_blip *b);
+
+/* Orbitals at n_points Cartesian points (any position; wrapped into the cell):
+ *   coef  device [n1][n2][n3][n_orb] FP64, caller-owned (orbital index
+ *         fastest; 16-byte aligned with even n_orb for the paired loads)
+ *   pos   device [n_points][3]
+ *   val   device out [n_points][n_orb]
+ *   grad  device out [n_points][3][n_orb] (Cartesian), or NULL
+ *   lap   device out [n_points][n_orb], or NULL (both or neither)
+ * FP64 throughout.  Enqueues one kernel on `stream`; no allocation, no
+ * synchronisation (graph-capturable).  Status: E_ARG, E_HIP. */
+ewald_status ewald_blip_eval_batch(const ewald_blip *b, const double *coef, int n_points, const double *pos,
+                                   double *val, double *grad, double *lap, void *stream);
 
 /* Thread-local message for the last non-OK status of this thread. */
 const char *ewald_last_error(void);

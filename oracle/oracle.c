@@ -283,7 +283,7 @@ static double real_image_sum_z(const osys *s, const double *bm, const double *dv
             double r0 = dv[0] - (i * s->lat[0] + j * s->lat[3]);
             double r1 = dv[1] - (i * s->lat[1] + j * s->lat[4]);
             double dist = sqrt(r0 * r0 + r1 * r1 + z * z);
-            if (dist < rc) sum += erfc(a * dist) / dist;
+            sum += dist < rc ? erfc(a * dist) / dist : 0.0;
         }
     return sum;
 }

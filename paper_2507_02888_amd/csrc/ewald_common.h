@@ -114,7 +114,7 @@ __device__ __forceinline__ double min_r2(const double* a, const double* b, const
   }
   const double* L = S->Lrot;
   double r[DIM];
-  if (DIM == 3) {
+  if constexpr (DIM == 3) {
     r[0] = fma(f[2], L[6], fma(f[1], L[3], f[0] * L[0]));
     r[1] = fma(f[2], L[7], f[1] * L[4]);
     r[DIM - 1] = f[DIM - 1] * L[8];
@@ -274,11 +274,18 @@ struct PairAcc<false, PD> {
   __device__ __forceinline__ PairAcc(const double* c64, const float*, const FrameK& k) : c(c64), K(k) {}
   template <int NE>
   __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE]) {
-    double ir[NE], t[NE], p[NE];
+    double ir[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) ir[e] = rsqrt_pos(r2[e]);
+    add_ir<NE>(q, r2, ir);
+  }
+  // the same with 1/sqrt(r2) already formed (shared with the Jastrow u term)
+  template <int NE>
+  __device__ __forceinline__ void add_ir(const double (&q)[NE], const double (&r2)[NE], const double (&ir)[NE]) {
+    double t[NE], p[NE];
     const double scale = K.scale;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      ir[e] = rsqrt_pos(r2[e]);
       t[e] = fma(r2[e], scale, -1.0);
       p[e] = c[PD];
     }
@@ -308,12 +315,17 @@ struct PairAcc<true, PD> {
   __device__ __forceinline__ PairAcc(const double*, const float* c32, const FrameK& k) : c(c32), K(k) {}
   template <int NE>
   __device__ __forceinline__ void add(const double (&q)[NE], const double (&r2)[NE]) {
-    float t[NE], p[NE];
     double ir[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) ir[e] = rsqrt_pos(r2[e]);
+    add_ir<NE>(q, r2, ir);
+  }
+  template <int NE>
+  __device__ __forceinline__ void add_ir(const double (&q)[NE], const double (&r2)[NE], const double (&ir)[NE]) {
+    float t[NE], p[NE];
     const float scale = float(K.scale);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      ir[e] = rsqrt_pos(r2[e]);
       t[e] = fmaf(float(r2[e]), scale, -1.0f);
       p[e] = c[PF];
     }
@@ -335,38 +347,229 @@ struct PairAcc<true, PD> {
   __device__ __forceinline__ double value() const { return inv - erfpart.value(); }
 };
 
+// ---------------------------------------------------------------------------
+// Jastrow two-body polynomial term u (Sec. 2.3, Eq. (8)), in powers of
+// t = r / L_u with the coefficients of the pair's spin channel,
+// c_m = u_c0[m] + s u_dc[m] (s = 0 for equal labels, 1 for unequal ones).
+// FP64 in both precision forms.
+
+// u at two arguments (a moved particle's new and old position against one
+// partner), sharing the channel blend.
+__device__ __forceinline__ void u_two(const DevSys* __restrict__ S, double s, double ta, double tb, double& ua,
+                                      double& ub) {
+  double pa = 0.0, pb = 0.0;
+#pragma unroll
+  for (int m = UDEG; m >= 0; --m) {
+    const double c = fma(s, S->u_dc[m], S->u_c0[m]);
+    pa = fma(pa, ta, c);
+    pb = fma(pb, tb, c);
+  }
+  ua = pa;
+  ub = pb;
+}
+
+// u and its first and second derivatives with respect to t at one argument,
+// and u at a second one (Horner with derivative chains).
+__device__ __forceinline__ void u_der_two(const DevSys* __restrict__ S, double s, double ta, double tb, double& ua,
+                                          double& d1, double& d2, double& ub) {
+  double p = 0.0, p1 = 0.0, p2 = 0.0, pb = 0.0;
+#pragma unroll
+  for (int m = UDEG; m >= 0; --m) {
+    const double c = fma(s, S->u_dc[m], S->u_c0[m]);
+    p2 = fma(p2, ta, p1);
+    p1 = fma(p1, ta, p);
+    p = fma(p, ta, c);
+    pb = fma(pb, tb, c);
+  }
+  ua = p;
+  d1 = p1;
+  d2 = 2.0 * p2;
+  ub = pb;
+}
+
+// u of one pair at r^2 with 1/r given (energy sums); 0 beyond L_u or when
+// the pair does not take part.
+__device__ __forceinline__ double u_pair(const DevSys* __restrict__ S, bool take, bool unequal, double r2,
+                                         double ir) {
+  double u, unused;
+  u_two(S, unequal ? 1.0 : 0.0, r2 * ir * S->u_icut, 0.0, u, unused);
+  return (take && r2 < S->u_cut2) ? u : 0.0;
+}
+
+// Change of U in a move against one partner (new minus old), and for UD the
+// partner's share of grad_k U (in the geometry's frame axes: x is the
+// minimum-image displacement of the new position from the partner) and of
+// lap_k U at the new position.
+template <int DIM>
+struct UOut {
+  double d = 0.0;
+  double g[DIM] = {};
+  double l = 0.0;
+};
+
+template <int DIM, bool UD>
+__device__ __forceinline__ void u_move_term(const DevSys* __restrict__ S, bool ok, bool unequal, double r2n,
+                                            double irn, double r2o, double iro, const double* xn, UOut<DIM>& out) {
+  const double s = unequal ? 1.0 : 0.0, ic = S->u_icut, uc2 = S->u_cut2;
+  const double tn = r2n * irn * ic, to = r2o * iro * ic;
+  const bool inn = ok && r2n < uc2, ino = ok && r2o < uc2;
+  double un, uo;
+  if (UD) {
+    double d1, d2;
+    u_der_two(S, s, tn, to, un, d1, d2, uo);
+    const double dur = inn ? d1 * ic * irn : 0.0;  // u'(r) / r
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) out.g[d] = fma(dur, xn[d], out.g[d]);
+    out.l += inn ? fma(d2, ic * ic, double(DIM - 1) * dur) : 0.0;
+  } else {
+    u_two(S, s, tn, to, un, uo);
+  }
+  out.d += (inn ? un : 0.0) - (ino ? uo : 0.0);
+}
+
+// A vector in a frame's axes (rows of E) in Cartesian axes.
+template <int DIM>
+__device__ __forceinline__ void frame_to_cart(const double* x, const double* E, double* out) {
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    double v = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) v = fma(x[d], E[d * 3 + e], v);
+    out[e] = v;
+  }
+}
+
+// Minimum-image displacement a - b (as min_r2, which gives the same r^2) in
+// the lower-triangular frame's axes; returns r^2.
+template <int DIM>
+__device__ __forceinline__ double min_disp(const double* a, const double* b, const DevSys* __restrict__ S,
+                                           int n_cand, double* x) {
+  double f[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    f[d] = a[d] - b[d];
+    f[d] -= rint(f[d]);
+  }
+  const double* L = S->Lrot;
+  double r[DIM];
+  if constexpr (DIM == 3) {
+    r[0] = fma(f[2], L[6], fma(f[1], L[3], f[0] * L[0]));
+    r[1] = fma(f[2], L[7], f[1] * L[4]);
+    r[DIM - 1] = f[DIM - 1] * L[8];
+  } else {
+    r[0] = fma(f[1], L[3], f[0] * L[0]);
+    r[DIM - 1] = f[DIM - 1] * L[4];
+  }
+  double r0sq = 0.0;
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) r0sq = fma(r[e], r[e], r0sq);
+  double r2 = r0sq;
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) x[e] = r[e];
+  for (int c = 0; c < n_cand; ++c) {
+    double dot = 0.0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) dot = fma(r[e], S->cand[c][e], dot);
+    const double t = fma(-2.0, fabs(dot), r0sq + S->cand[c][3]);
+    if (t < r2) {
+      r2 = t;
+      const double sg = dot >= 0.0 ? 1.0 : -1.0;
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) x[e] = fma(-sg, S->cand[c][e], r[e]);
+    }
+  }
+  return r2;
+}
+
+// The same in the orthogonal-sublattice frame (as min_r2_ortho): the coset
+// image moves each masked axis by half a box side towards zero.
+template <int DIM>
+__device__ __forceinline__ double min_disp_ortho(const double* a, const double* b, const FrameK& K, double* x) {
+  double r0sq = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    x[d] = a[d] - b[d];
+    x[d] = fma(-K.box[d], rint(x[d] * K.ibox[d]), x[d]);
+    r0sq = fma(x[d], x[d], r0sq);
+  }
+  double t = r0sq + K.cc;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) t = fma(-K.cw[d], fabs(x[d]), t);
+  if (t < r0sq) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) x[d] -= copysign(0.5 * K.cw[d], x[d]);
+    return t;
+  }
+  return r0sq;
+}
+
+template <int DIM, bool ORTHO>
+__device__ __forceinline__ double image_disp(const double* a, const double* b, const DevSys* __restrict__ S,
+                                             int n_cand, const FrameK& K, double* x) {
+  if (ORTHO) return min_disp_ortho<DIM>(a, b, K, x);
+  return min_disp<DIM>(a, b, S, n_cand, x);
+}
+
 // Real-space part of a move of particle k from so to sn, summed over the
 // mobile particles j != k (positions pos, charges q) and the fixed ions:
 // sum_j q_j [phi(sn - s_j) - phi(so - s_j)].  Threads take j = tid, tid + NT, ...
 // PPR particles (2 PPR pair terms) per round: 2 for workgroups of up to 512
 // threads, 1 for 1024 (one particle per thread at N = 1024).  Indices are
 // clamped rather than branched on, so every load is in bounds and the loop
-// body has no divergent control flow.
-template <int DIM, bool MIXED, int PD, int NT>
+// body has no divergent control flow.  UJ: also the Jastrow u term of the
+// mobile pairs into uo (UD: with its gradient, in the lower-triangular
+// frame's axes, and Laplacian at the new position).
+// A layered 2D system (S->n_layers = 2) adds (z_1 - z_0)^2 to r^2 for the
+// partners in the other plane.
+template <int DIM, bool MIXED, int PD, int NT, bool UJ = false, bool UD = false>
 __device__ __forceinline__ double real_move(const double* sn, const double* so, int k, const double* pos,
-                                            const double* q, int n, const DevSys* __restrict__ S) {
+                                            const double* q, int n, const DevSys* __restrict__ S,
+                                            UOut<DIM>* uo = nullptr) {
   constexpr int PPR = NT >= 1024 ? 1 : 2;
   const FrameK K = frame_k(S);
   PairAcc<MIXED, PD> pr(S->p64, S->p32, K);
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
+  const int sk = UJ ? S->spin[k] : 0;
+  const bool lay = DIM == 2 && S->n_layers > 1;
+  const int n0 = S->n0, lk = k >= n0 ? 1 : 0;
+  const double dz2 = S->dz2;
   for (int j0 = threadIdx.x; j0 < n; j0 += PPR * NT) {
-    double qq[2 * PPR], r2[2 * PPR];
+    double qq[2 * PPR], r2[2 * PPR], ir[2 * PPR];
+    double xn[UD ? PPR : 1][DIM];
+    bool okc[PPR];
+    int sj[PPR];
 #pragma unroll
     for (int c = 0; c < PPR; ++c) {
       const int j = j0 + c * NT;
       const bool ok = j < n && j != k;
       const int jj = j < n ? j : n - 1;
-      double sj[DIM];
+      double pj[DIM];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) sj[d] = pos[jj * DIM + d];
+      for (int d = 0; d < DIM; ++d) pj[d] = pos[jj * DIM + d];
       const double qj = ok ? q[jj] : 0.0;
-      r2[2 * c] = ok ? min_r2<DIM>(sn, sj, S, n_cand) : rc2;
-      r2[2 * c + 1] = ok ? min_r2<DIM>(so, sj, S, n_cand) : rc2;
+      if (UD)
+        r2[2 * c] = ok ? min_disp<DIM>(sn, pj, S, n_cand, xn[UD ? c : 0]) : rc2;
+      else
+        r2[2 * c] = ok ? min_r2<DIM>(sn, pj, S, n_cand) : rc2;
+      r2[2 * c + 1] = ok ? min_r2<DIM>(so, pj, S, n_cand) : rc2;
+      if (lay && ok && (jj >= n0 ? 1 : 0) != lk) {
+        r2[2 * c] += dz2;
+        r2[2 * c + 1] += dz2;
+      }
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
+      okc[c] = ok;
+      if (UJ) sj[c] = S->spin[jj];
     }
-    pr.template add<2 * PPR>(qq, r2);
+#pragma unroll
+    for (int e = 0; e < 2 * PPR; ++e) ir[e] = rsqrt_pos(r2[e]);
+    pr.template add_ir<2 * PPR>(qq, r2, ir);
+    if (UJ)
+#pragma unroll
+      for (int c = 0; c < PPR; ++c)
+        u_move_term<DIM, UD>(S, okc[c], sj[c] != sk, r2[2 * c], ir[2 * c], r2[2 * c + 1], ir[2 * c + 1],
+                             xn[UD ? c : 0], *uo);
   }
   const int nfix = S->n_fixed;
   for (int j0 = threadIdx.x; j0 < nfix; j0 += PPR * NT) {
@@ -382,6 +585,10 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
       const double qj = ok ? S->fixed_q[jj] : 0.0;
       r2[2 * c] = ok ? min_r2<DIM>(sn, sj, S, n_cand) : rc2;
       r2[2 * c + 1] = ok ? min_r2<DIM>(so, sj, S, n_cand) : rc2;
+      if (lay && ok && S->fixed_layer[jj] != lk) {
+        r2[2 * c] += dz2;
+        r2[2 * c + 1] += dz2;
+      }
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
     }
@@ -398,39 +605,65 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
 // copy, again only by their owner t = j mod NT.  XTRA = false: the batch has
 // no such particles and no fixed ions, and those loops are left out (at 1024
 // threads their mere presence costs scalar-register reloads on every move).
-template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO, bool XTRA>
+// UJ: also the Jastrow u term of the mobile pairs into uo (psp: the spin
+// labels of the thread's own particles, sk: the moved particle's); UD: with
+// its gradient (in the geometry's frame axes) and Laplacian at the new
+// position.
+template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO, bool XTRA, bool UJ = false, bool UD = false>
 __device__ __forceinline__ double real_move_own(const double* sn, const double* so, int k,
                                                 const double (&ps)[PPR][DIM], const double (&pq)[PPR],
                                                 const double* lpos, const double* lq, int n,
                                                 const DevSys* __restrict__ S, const double* c64,
-                                                const float* c32, const FrameK& K) {
+                                                const float* c32, const FrameK& K,
+                                                const int* psp = nullptr, int sk = 0,
+                                                UOut<DIM>* uo = nullptr) {
   PairAcc<MIXED, PD> pr(c64, c32, K);
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
   {
-    double qq[2 * PPR], r2[2 * PPR];
+    double qq[2 * PPR], r2[2 * PPR], ir[2 * PPR];
+    double xn[UD ? PPR : 1][DIM];
+    bool okc[PPR];
 #pragma unroll
     for (int c = 0; c < PPR; ++c) {
       const int j = threadIdx.x + c * NT;
       const bool ok = j < n && j != k;
-      r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, ps[c], S, n_cand, K) : rc2;
+      if (UD)
+        r2[2 * c] = ok ? image_disp<DIM, ORTHO>(sn, ps[c], S, n_cand, K, xn[UD ? c : 0]) : rc2;
+      else
+        r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, ps[c], S, n_cand, K) : rc2;
       r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, ps[c], S, n_cand, K) : rc2;
       qq[2 * c] = pq[c];
       qq[2 * c + 1] = -pq[c];
+      okc[c] = ok;
     }
-    pr.template add<2 * PPR>(qq, r2);
+#pragma unroll
+    for (int e = 0; e < 2 * PPR; ++e) ir[e] = rsqrt_pos(r2[e]);
+    pr.template add_ir<2 * PPR>(qq, r2, ir);
+    if (UJ)
+#pragma unroll
+      for (int c = 0; c < PPR; ++c)
+        u_move_term<DIM, UD>(S, okc[c], psp[c] != sk, r2[2 * c], ir[2 * c], r2[2 * c + 1], ir[2 * c + 1],
+                             xn[UD ? c : 0], *uo);
   }
   if (!XTRA) return pr.value();
   for (int j = threadIdx.x + PPR * NT; j < n; j += NT) {
-    double qq[2], r2[2];
+    double qq[2], r2[2], ir[2];
+    double xn[DIM];
     const bool ok = j != k;
     double xj[DIM];
     geo_pos<DIM, ORTHO>(lpos + j * DIM, S, xj);
-    r2[0] = ok ? image_r2<DIM, ORTHO>(sn, xj, S, n_cand, K) : rc2;
+    if (UD)
+      r2[0] = ok ? image_disp<DIM, ORTHO>(sn, xj, S, n_cand, K, xn) : rc2;
+    else
+      r2[0] = ok ? image_r2<DIM, ORTHO>(sn, xj, S, n_cand, K) : rc2;
     r2[1] = ok ? image_r2<DIM, ORTHO>(so, xj, S, n_cand, K) : rc2;
     qq[0] = lq[j];
     qq[1] = -lq[j];
-    pr.template add<2>(qq, r2);
+    ir[0] = rsqrt_pos(r2[0]);
+    ir[1] = rsqrt_pos(r2[1]);
+    pr.template add_ir<2>(qq, r2, ir);
+    if (UJ) u_move_term<DIM, UD>(S, ok, S->spin[j] != sk, r2[0], ir[0], r2[1], ir[1], xn, *uo);
   }
   const int nfix = S->n_fixed;
   for (int j0 = threadIdx.x; j0 < nfix; j0 += 2 * NT) {
@@ -632,10 +865,12 @@ struct SegWalk {
 // independent chains; a pass reads all its table entries before its
 // arithmetic.  `pos` and `q` may point to global or LDS memory.  All NT
 // threads must call it.
+// rfix: the fixed ions' part to start from (NULL: S->rho_fix; a layered
+// system's second plane passes S->rho_fix1).
 template <int DIM, int NS, int NT = BLOCK>
 __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[NS], int seg0,
                             const DevSys* __restrict__ S, const double* pos, const double* q, int n,
-                            cplx<double>* tabs, int tile = TILE_P) {
+                            cplx<double>* tabs, int tile = TILE_P, const double* rfix = nullptr) {
   const int nseg = S->n_seg, nm = S->nm, tbl = 2 * nm + 1, pstride = DIM * tbl;
   // tile layout: the tables of particles 2k and 2k + 1 interleaved entry by
   // entry, so that a pass reads both particles' entries at one address and
@@ -649,7 +884,7 @@ __device__ void rebuild_rho(cplx<double> (&acc)[NS][SEG], const uint32_t (&an)[N
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
       if (s < nseg) {
-        const double* rf = S->rho_fix + 2 * (size_t(j) * nseg + s);
+        const double* rf = (rfix ? rfix : S->rho_fix) + 2 * (size_t(j) * nseg + s);
         acc[i][j] = {rf[0], rf[1]};
       } else {
         acc[i][j] = {0.0, 0.0};

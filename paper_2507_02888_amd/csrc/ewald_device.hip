@@ -35,7 +35,9 @@ namespace ewald {
 // and new terms.  The pair loop works in the orthogonal-sublattice frame when
 // the cell has one (ORTHO); rho is built from the fractional positions just
 // stored in the walker state.
-template <int DIM, int SPT, int PD, bool ORTHO>
+// UJ: the Jastrow value also takes the two-body polynomial term u over the
+// mobile pairs (Sec. 2.3, Eq. (8)).
+template <int DIM, int SPT, int PD, bool ORTHO, bool UJ>
 __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ systems,
                                                   const DevWalker* __restrict__ walkers,
                                                   const double* __restrict__ pos, char* __restrict__ state,
@@ -83,8 +85,13 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
     const int s = tid + i * BLOCK;
     an[i] = s < nseg ? S->seg_n[s] : 0u;
   }
+  // a layered 2D system (two planes): rho of each plane, with the
+  // cross-plane term 2 w_x Re(rho_0 conj(rho_1)); the second plane's rho
+  // follows the first in the state
+  const bool lay = DIM == 2 && S->n_layers > 1;
+  const int n0 = lay ? S->n0 : n;
   cplx<double> acc[SPT][SEG];
-  rebuild_rho<DIM, SPT>(acc, an, tid, S, spos, S->mobile_q, n, tabs, tile);
+  rebuild_rho<DIM, SPT>(acc, an, tid, S, spos, S->mobile_q, n0, tabs, tile);
   double er = 0.0, ej = 0.0;
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
@@ -98,6 +105,28 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
         if (S->ja) ej = fma(S->ja[g], m2, ej);
         rho[2 * g] = acc[i][j].x;
         rho[2 * g + 1] = acc[i][j].y;
+      }
+    }
+  }
+  if (lay) {
+    cplx<double> acc1[SPT][SEG];
+    rebuild_rho<DIM, SPT>(acc1, an, tid, S, spos + size_t(n0) * DIM, S->mobile_q + n0, n - n0, tabs, tile,
+                          S->rho_fix1);
+    double* rho1 = rho + 2 * size_t(SEG) * nseg;
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      const int s = tid + i * BLOCK;
+      if (s < nseg) {
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) {
+          const size_t g = size_t(j) * nseg + s;
+          const double m2 = acc1[i][j].x * acc1[i][j].x + acc1[i][j].y * acc1[i][j].y;
+          const double x = acc[i][j].x * acc1[i][j].x + acc[i][j].y * acc1[i][j].y;
+          er = fma(S->w[g], m2, er);
+          er = fma(2.0 * S->wx[g], x, er);
+          rho1[2 * g] = acc1[i][j].x;
+          rho1[2 * g + 1] = acc1[i][j].y;
+        }
       }
     }
   }
@@ -128,15 +157,19 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
   PairAcc<false, PD> pr(cf64, S->p32, K);
   const double rc2 = S->rc2;
   const int half = (n - 1) / 2;
+  double eu = 0.0;  // UJ: this thread's share of sum_{i<j} u(r_ij)
   for (int i = tid; i < n; i += BLOCK) {
     double si[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) si[d] = lpos[i * DIM + d];
     const double qi = lq[i];
+    const int spi = UJ ? S->spin[i] : 0;
+    const int li = i >= n0 ? 1 : 0;  // plane of particle i (layered systems)
     const int n_mob = half + (((n & 1) == 0 && i < n / 2) ? 1 : 0);
     const int n_part = n_mob + nfix;
     for (int m0 = 0; m0 < n_part; m0 += 4) {
-      double qq[4], r2[4];
+      double qq[4], r2[4], ir[4];
+      bool mobc[4], uneq[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int m = m0 + c;
@@ -152,11 +185,22 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
         }
         qq[c] = mob ? qi * lq[j] : fix ? qi * S->fixed_q[m - n_mob] : 0.0;
         r2[c] = (mob || fix) ? image_r2<DIM, ORTHO>(si, sj, S, n_cand, K) : rc2;
+        if (lay && (mob || fix)) {
+          const int lj = mob ? (j >= n0 ? 1 : 0) : S->fixed_layer[m - n_mob];
+          r2[c] += lj != li ? S->dz2 : 0.0;
+        }
+        mobc[c] = mob;
+        uneq[c] = UJ && mob && S->spin[j] != spi;
       }
-      pr.template add<4>(qq, r2);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ir[c] = rsqrt_pos(r2[c]);
+      pr.template add_ir<4>(qq, r2, ir);
+      if (UJ)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) eu += u_pair(S, mobc[c], uneq[c], r2[c], ir[c]);
     }
   }
-  double v[3] = {pr.value(), er, ej};
+  double v[3] = {pr.value(), er, ej + eu};
   block_sum<3>(v, red);
   if (tid == 0) {
     energy[w] = v[0] + v[1] + S->e_const;
@@ -177,7 +221,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
 // S_d = sum_H a n_d Im z (per segment: the last index runs n_last + j), and
 // turned into Cartesian components once per move; |G|^2 is constant on a
 // shell and comes with a from the shell table.
-template <int DIM, bool MIXED, int PD, bool DER>
+// UJ: dJ also takes the two-body polynomial term u of the mobile pairs (and,
+// with DER, its gradient and Laplacian at the new position).
+constexpr int RED_DELTA = 48;  // LDS doubles for k_delta's reduction: up to 12 sums x 4 waves
+template <int DIM, bool MIXED, int PD, bool DER, bool UJ>
 __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ systems,
                                                  const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                                  const int32_t* __restrict__ kk, const double* __restrict__ new_pos,
@@ -195,10 +242,16 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
   const double* spos = reinterpret_cast<const double*>(st + HDR_BYTES);
   const double* rho = reinterpret_cast<const double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
-  double* red = smem;  // [NV][4]
-  cplx<R>* to = reinterpret_cast<cplx<R>*>(smem + 32);
+  // layered 2D system: the moved particle's plane and the other plane's rho
+  const bool lay = DIM == 2 && S->n_layers > 1;
+  const int lk = kk[w] >= S->n0 ? 1 : 0;
+  if (lay && lk) rho += 2 * size_t(SEG) * nseg;
+  const double2* __restrict__ rhoo2 =
+      reinterpret_cast<const double2*>(lay ? (lk ? rho - 2 * size_t(SEG) * nseg : rho + 2 * size_t(SEG) * nseg) : rho);
+  double* red = smem;  // [NV][4], NV <= RED_DELTA / 4
+  cplx<R>* to = reinterpret_cast<cplx<R>*>(smem + RED_DELTA);
   cplx<R>* tn = to + DIM * tbl;
-  WT2* ltab = reinterpret_cast<WT2*>(smem + 32 + lds_tab);  // shell table (when it fits)
+  WT2* ltab = reinterpret_cast<WT2*>(smem + RED_DELTA + lds_tab);  // shell table (when it fits)
   R* ltab2 = reinterpret_cast<R*>(ltab + S->n_wtab);      // a |G|^2 per shell (DER)
   const double2* __restrict__ rho2 = reinterpret_cast<const double2*>(rho);
 
@@ -249,8 +302,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
   const double* __restrict__ ja = S->ja;
   // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)]: q^2 is applied
   // once to the sums, and a neutral particle's move changes nothing
-  double accE64 = 0.0, accJ64 = 0.0;
-  Kahan accE32, accJ32;
+  double accE64 = 0.0, accJ64 = 0.0, accX64 = 0.0;
+  Kahan accE32, accJ32, accX32;  // X: the cross-plane sum of a layered system, sum_H w_x Re(conj(rho_o) d)
   double dS[DIM], dL = 0.0;  // DER: S_d and sum_H a |G|^2 Re z
 #pragma unroll
   for (int d = 0; d < DIM; ++d) dS[d] = 0.0;
@@ -269,7 +322,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
     }
     const uint32_t pn = S->seg_n[s];
     SegWalk<R> wo(anchor<DIM, R>(to, pn, nm), uo), wn(anchor<DIM, R>(tn, pn, nm), un);
-    float segE = 0.f, segJ = 0.f;  // mixed form: FP32 sums per segment, compensated across segments
+    float segE = 0.f, segJ = 0.f, segX = 0.f;  // mixed form: FP32 sums per segment, compensated across segments
     R sT = R(0), sT2 = R(0), sL = R(0);  // DER: per-segment sums of a Im z, j a Im z, a |G|^2 Re z
 #pragma unroll
     for (int j = 0; j < SEG; ++j) {
@@ -296,6 +349,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
         accE64 = fma(double(wg), double(t), accE64);
         if (ja) accJ64 = fma(double(aj), double(t), accJ64);
       }
+      if (lay) {  // other plane: w_x (rho_o . d)
+        const double2 ro = rhoo2[g];
+        const R xo = fma(R(ro.x), dx, R(ro.y) * dy);
+        if (MIXED)
+          segX = fmaf(float(S->wx[g]), float(xo), segX);
+        else
+          accX64 = fma(S->wx[g], double(xo), accX64);
+      }
       if (DER) {
         const R px = fma(qr, dx, R(rcur[j].x)), py = fma(qr, dy, R(rcur[j].y));  // rho'
         const R im = fma(px, en.y, -(py * en.x)), re = fma(px, en.x, py * en.y);
@@ -312,6 +373,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
     if (MIXED) {
       accE32.add(segE);
       if (ja) accJ32.add(segJ);
+      if (lay) accX32.add(segX);
     }
     if (DER) {
 #pragma unroll
@@ -326,30 +388,41 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
     }
   }
   // real space
-  const double er = real_move<DIM, MIXED, PD, BLOCK>(sn, so, k, spos, S->mobile_q, n, S);
+  UOut<DIM> ut;
+  const double er = real_move<DIM, MIXED, PD, BLOCK, UJ, UJ && DER>(sn, so, k, spos, S->mobile_q, n, S, &ut);
   const double q2 = qk * qk;
-  constexpr int NV = DER ? 3 + DIM : 2;
+  constexpr int NP = DER ? 3 + DIM : 2;         // energy, J, and the p-term derivative sums
+  constexpr int NV = NP + (UJ && DER ? DIM + 1 : 0);  // and the u term's gradient (frame axes) and Laplacian
+  static_assert(NV * (BLOCK / 64) <= RED_DELTA, "reduction area too small");
   double v[NV];
   v[0] = q2 * (MIXED ? accE32.value() : accE64) + qk * er;
-  v[1] = q2 * (MIXED ? accJ32.value() : accJ64);
+  if (lay) v[0] += 2.0 * qk * (MIXED ? accX32.value() : accX64);
+  v[1] = q2 * (MIXED ? accJ32.value() : accJ64) + (UJ ? ut.d : 0.0);
   if (DER) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) v[2 + d] = dS[d];
-    v[NV - 1] = dL;
+    v[NP - 1] = dL;
+  }
+  if (UJ && DER) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) v[NP + d] = ut.g[d];
+    v[NV - 1] = ut.l;
   }
   block_sum<NV>(v, red);
   if (tid == 0) {
     delta[w] = v[0];
     if (djas) djas[w] = v[1];
     if (DER) {
+      double ug[DIM];  // u term gradient in Cartesian axes (its sums are in the lower-triangular frame's)
+      if (UJ) frame_to_cart<DIM>(v + NP, S->El, ug);
 #pragma unroll
       for (int e = 0; e < DIM; ++e) {
         double gx = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) gx = fma(v[2 + d], S->B[d * 3 + e], gx);
-        jgrad[size_t(w) * DIM + e] = -2.0 * qk * gx;
+        jgrad[size_t(w) * DIM + e] = -2.0 * qk * gx + (UJ ? ug[e] : 0.0);
       }
-      jlap[w] = -2.0 * qk * v[NV - 1] + 2.0 * q2 * S->jlap_c;
+      jlap[w] = -2.0 * qk * v[NP - 1] + 2.0 * q2 * S->jlap_c + (UJ ? v[NV - 1] : 0.0);
     }
     hdr->pending_k = k;
 #pragma unroll
@@ -394,6 +467,8 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
   if (acc) {
     const R q = R(S->mobile_q[pk]);
     const cplx<R> uo = tab_at(to, DIM - 1, nm + 1, tbl), un = tab_at(tn, DIM - 1, nm + 1, tbl);
+    // a layered system's second plane keeps its rho after the first's
+    if (DIM == 2 && S->n_layers > 1 && pk >= S->n0) rho += 2 * size_t(SEG) * nseg;
     double2* rho2 = reinterpret_cast<double2*>(rho);
     for (int s = tid; s < nseg; s += BLOCK) {
       double2 r[SEG];
@@ -447,21 +522,28 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
   cplx<double>* tabs = reinterpret_cast<cplx<double>*>(smem);
   const int s = chunk * BLOCK + tid;
   uint32_t an[1] = {s < nseg ? S->seg_n[s] : 0u};
-  cplx<double> acc[1][SEG];
-  rebuild_rho<DIM, 1>(acc, an, chunk * BLOCK + tid, S, spos, S->mobile_q, n, tabs);
-  if (s < nseg) {
-    double drift = 0.0;
+  // a layered system: each plane from its own particles and ions
+  const int n_planes = (DIM == 2 && S->n_layers > 1) ? 2 : 1;
+  for (int l = 0; l < n_planes; ++l) {  // uniform
+    const int p0 = l == 0 ? 0 : S->n0, p1 = n_planes == 1 ? n : (l == 0 ? S->n0 : n);
+    double* rl = rho + 2 * size_t(SEG) * nseg * l;
+    cplx<double> acc[1][SEG];
+    rebuild_rho<DIM, 1>(acc, an, chunk * BLOCK + tid, S, spos + size_t(p0) * DIM, S->mobile_q + p0, p1 - p0,
+                        tabs, TILE_P, l == 0 ? S->rho_fix : S->rho_fix1);
+    if (s < nseg) {
+      double drift = 0.0;
 #pragma unroll
-    for (int j = 0; j < SEG; ++j) {
-      const size_t g = size_t(j) * nseg + s;
-      drift = fmax(drift, fmax(fabs(acc[0][j].x - rho[2 * g]), fabs(acc[0][j].y - rho[2 * g + 1])));
-      rho[2 * g] = acc[0][j].x;
-      rho[2 * g + 1] = acc[0][j].y;
+      for (int j = 0; j < SEG; ++j) {
+        const size_t g = size_t(j) * nseg + s;
+        drift = fmax(drift, fmax(fabs(acc[0][j].x - rl[2 * g]), fabs(acc[0][j].y - rl[2 * g + 1])));
+        rl[2 * g] = acc[0][j].x;
+        rl[2 * g + 1] = acc[0][j].y;
+      }
+      for (int off = 32; off > 0; off >>= 1) drift = fmax(drift, __shfl_xor(drift, off, 64));
+      if ((tid & 63) == 0)
+        atomicMax(reinterpret_cast<unsigned long long*>(&hdr->drift_max),
+                  static_cast<unsigned long long>(__double_as_longlong(drift)));
     }
-    for (int off = 32; off > 0; off >>= 1) drift = fmax(drift, __shfl_xor(drift, off, 64));
-    if ((tid & 63) == 0)
-      atomicMax(reinterpret_cast<unsigned long long*>(&hdr->drift_max),
-                static_cast<unsigned long long>(__double_as_longlong(drift)));
   }
   if (chunk == 0 && tid == 0) hdr->n_refresh += 1;
 }
@@ -471,13 +553,13 @@ __global__ __launch_bounds__(BLOCK) void k_rebuild(const DevSys* __restrict__ sy
 
 namespace {
 
-template <int DIM, int SPT, int PD, bool ORTHO>
+template <int DIM, int SPT, int PD, bool ORTHO, bool UJ>
 int energy_inst(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
                 void* stream) {
   const int lds_pos = even(b.max_particles);
   const size_t rpart = size_t(DIM) * (2 * b.max_nm + 1) * sizeof(cplx<double>);
   const size_t head = 16 * 8, pairs = size_t(lds_pos) * (DIM + 1) * 8;
-  auto* kern = k_energy<DIM, SPT, PD, ORTHO>;
+  auto* kern = k_energy<DIM, SPT, PD, ORTHO, UJ>;
   // rebuild tiles (sharing their LDS with the pair loop's positions) as
   // large as LDS allows without lowering the workgroups per CU that
   // registers allow (four: the kernel is bounded to four waves per SIMD),
@@ -493,15 +575,22 @@ int energy_inst(const LaunchBatch& b, const double* pos, char* state, double* en
   return last_launch();
 }
 
+template <int DIM, int PD, bool ORTHO, bool UJ>
+int energy_spt(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
+               void* stream) {
+  switch (spt_for(b.max_n_seg)) {
+    case 1: return energy_inst<DIM, 1, PD, ORTHO, UJ>(b, pos, state, energy, jastrow, stream);
+    case 2: return energy_inst<DIM, 2, PD, ORTHO, UJ>(b, pos, state, energy, jastrow, stream);
+    case 4: return energy_inst<DIM, 4, PD, ORTHO, UJ>(b, pos, state, energy, jastrow, stream);
+    default: return energy_inst<DIM, 8, PD, ORTHO, UJ>(b, pos, state, energy, jastrow, stream);
+  }
+}
+
 template <int DIM, int PD, bool ORTHO>
 int energy_pd(const LaunchBatch& b, const double* pos, char* state, double* energy, double* jastrow,
               void* stream) {
-  switch (spt_for(b.max_n_seg)) {
-    case 1: return energy_inst<DIM, 1, PD, ORTHO>(b, pos, state, energy, jastrow, stream);
-    case 2: return energy_inst<DIM, 2, PD, ORTHO>(b, pos, state, energy, jastrow, stream);
-    case 4: return energy_inst<DIM, 4, PD, ORTHO>(b, pos, state, energy, jastrow, stream);
-    default: return energy_inst<DIM, 8, PD, ORTHO>(b, pos, state, energy, jastrow, stream);
-  }
+  return b.has_u ? energy_spt<DIM, PD, ORTHO, true>(b, pos, state, energy, jastrow, stream)
+                 : energy_spt<DIM, PD, ORTHO, false>(b, pos, state, energy, jastrow, stream);
 }
 
 template <int DIM>
@@ -522,21 +611,29 @@ int delta_dim(const LaunchBatch& b, char* state, const int32_t* k, const double*
   const size_t mtab = size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
   const int lds_tab = even(int((mtab + 7) / 8));  // in doubles
   const bool der = jgrad != nullptr;
-  const size_t lds = 32 * 8 + size_t(lds_tab) * 8 + size_t(b.max_wtab) * (sizeof(cplx<R>) + (der ? sizeof(R) : 0));
-#define EW_DELTA(PD, DER)                                                                                     \
-  hipLaunchKernelGGL((k_delta<DIM, MIXED, PD, DER>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), \
+  const size_t lds = RED_DELTA * 8 + size_t(lds_tab) * 8 + size_t(b.max_wtab) * (sizeof(cplx<R>) + (der ? sizeof(R) : 0));
+#define EW_DELTA(PD, DER, UJ)                                                                                     \
+  hipLaunchKernelGGL((k_delta<DIM, MIXED, PD, DER, UJ>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), \
                      b.d_sys, b.d_walk, state, k, new_pos, delta, djas, jgrad, jlap, lds_tab)
+#define EW_DELTA_U(PD, DER) \
+  if (b.has_u)              \
+    EW_DELTA(PD, DER, true); \
+  else                      \
+    EW_DELTA(PD, DER, false)
   if (b.poly_deg <= 16) {
-    if (der)
-      EW_DELTA(16, true);
-    else
-      EW_DELTA(16, false);
+    if (der) {
+      EW_DELTA_U(16, true);
+    } else {
+      EW_DELTA_U(16, false);
+    }
   } else {
-    if (der)
-      EW_DELTA(32, true);
-    else
-      EW_DELTA(32, false);
+    if (der) {
+      EW_DELTA_U(32, true);
+    } else {
+      EW_DELTA_U(32, false);
+    }
   }
+#undef EW_DELTA_U
 #undef EW_DELTA
   return last_launch();
 }
@@ -558,8 +655,17 @@ int accept_dim(const LaunchBatch& b, char* state, const uint8_t* accept, void* s
 
 
 int run_any(const LaunchBatch& b, const RunArgs& a) {
-  if (!b.all_wtab_lds) return RUN_NO_FIT;
+  // layered systems run their sweeps through the per-step kernels
+  if (!b.all_wtab_lds || b.layered) return RUN_NO_FIT;
   const int jm = b.has_jastrow == 0 ? 0 : a.jgrad ? 2 : 1;
+  if (b.has_u) {  // the u term comes with Jastrow outputs (JM 3, 4)
+    if (b.dim == 3) {
+      if (b.mixed) return jm == 2 ? run_d3_mixed_j4(b, a) : run_d3_mixed_j3(b, a);
+      return jm == 2 ? run_d3_fp64_j4(b, a) : run_d3_fp64_j3(b, a);
+    }
+    if (b.mixed) return jm == 2 ? run_d2_mixed_j4(b, a) : run_d2_mixed_j3(b, a);
+    return jm == 2 ? run_d2_fp64_j4(b, a) : run_d2_fp64_j3(b, a);
+  }
   if (b.dim == 3) {
     if (b.mixed) return jm == 2 ? run_d3_mixed_j2(b, a) : jm ? run_d3_mixed_j1(b, a) : run_d3_mixed_j0(b, a);
     return jm == 2 ? run_d3_fp64_j2(b, a) : jm ? run_d3_fp64_j1(b, a) : run_d3_fp64_j0(b, a);

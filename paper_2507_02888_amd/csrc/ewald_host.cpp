@@ -35,6 +35,15 @@ ewald_status fail(ewald_status s, const std::string& msg) {
 
 constexpr double kPi = 3.14159265358979323846;
 
+}  // namespace
+
+namespace ewald {
+// the message for ewald_last_error, from the library's other translation units
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace ewald
+
+namespace {
+
 bool is_fin(double x) { return std::isfinite(x); }
 
 // 3x3 helpers on row-major arrays; a 2D cell lives in the upper-left 2x2
@@ -81,6 +90,7 @@ double wrap01(double x) {
 // then use the general reduction with candidate images).
 struct OrthoFrame {
   double F[9] = {0};    // x = s F (frame coordinates from fractional ones)
+  double E[9] = {0};    // rows: the frame's axes as Cartesian unit vectors
   double box[3] = {0};
   int n_coset = 0;
   double cw[MAX_COSET][3] = {{0}};
@@ -149,6 +159,8 @@ bool ortho_frame(const double* A, int dim, OrthoFrame& out) {
   for (int i = 0; i < dim; ++i)
     for (int d = 0; d < dim; ++d)
       out.F[i * 3 + d] = A[i * 3] * e[d][0] + A[i * 3 + 1] * e[d][1] + A[i * 3 + 2] * e[d][2];
+  for (int d = 0; d < 3; ++d)
+    for (int x = 0; x < 3; ++x) out.E[d * 3 + x] = e[d][x];
   // cosets: lattice points k A, k in [0, index)^dim, reduced into the box
   std::vector<std::array<double, 3>> reps;
   const int m = best_index;
@@ -329,6 +341,9 @@ struct ewald_sys {
   std::vector<double> shell_g2;      // |G|^2 of each shell
   std::vector<double> rho_fix;       // slot-planar [n_slots][2]
   std::vector<double> fixed_s, fixed_q, mobile_q;
+  std::vector<int32_t> spin;         // [n_mobile] spin labels (u term)
+  std::vector<double> wx, rho_fix1;  // layered: cross-plane weights, second plane's ions (slot-planar)
+  std::vector<int32_t> fixed_layer;  // layered: plane of each ion
   std::vector<double> cand_cart;     // [n_cand][3] candidate offsets, caller's frame
   int device = -1;
   void* d_block = nullptr;
@@ -389,6 +404,19 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   }
   for (int i = 0; i < desc->n_jastrow; ++i)
     if (!is_fin(desc->jastrow_a[i])) return fail(EWALD_E_ARG, "non-finite Jastrow coefficient");
+  const int u_terms = desc->u_terms;
+  if (u_terms < 0) return fail(EWALD_E_ARG, "u_terms must be >= 0");
+  if (u_terms > 0) {
+    if (!desc->u_alpha) return fail(EWALD_E_ARG, "u_alpha is NULL");
+    if (desc->u_C < 1) return fail(EWALD_E_ARG, "u_C must be >= 1");
+    if (u_terms - 1 + desc->u_C > UDEG) return fail(EWALD_E_ARG, "u_terms - 1 + u_C exceeds 15");
+    for (int i = 0; i < 2 * u_terms; ++i)
+      if (!is_fin(desc->u_alpha[i])) return fail(EWALD_E_ARG, "non-finite u coefficient");
+    if (desc->mobile_spin)
+      for (int i = 0; i < desc->n_mobile; ++i)
+        if (desc->mobile_spin[i] != 0 && desc->mobile_spin[i] != 1)
+          return fail(EWALD_E_ARG, "spin labels must be 0 or 1");
+  }
 
   // ---- lattice ----
   double A[9] = {0};
@@ -447,6 +475,25 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   if (!is_fin(r_cut) || !(r_cut > 0)) return fail(EWALD_E_RCUT, "r_cut must be > 0");
   if (r_cut > r_ins) return fail(EWALD_E_RCUT, "r_cut exceeds the inscribed radius (half the shortest lattice vector)");
   if (!is_fin(g_cut) || !(g_cut > 0)) return fail(EWALD_E_GCUT, "g_cut must be > 0");
+  const int n_layers = desc->n_layers;
+  if (n_layers < 0 || n_layers > 2) return fail(EWALD_E_ARG, "n_layers must be 0, 1 or 2");
+  const bool layered = n_layers == 2;
+  if (layered) {
+    if (dim != 2) return fail(EWALD_E_ARG, "layers need a two-dimensional cell");
+    if (desc->n_jastrow > 0 || u_terms > 0) return fail(EWALD_E_ARG, "layered systems take no Jastrow terms");
+    if (desc->n_mobile_layer0 < 0 || desc->n_mobile_layer0 > desc->n_mobile)
+      return fail(EWALD_E_ARG, "n_mobile_layer0 must be in [0, n_mobile]");
+    if (!is_fin(desc->layer_z[0]) || !is_fin(desc->layer_z[1])) return fail(EWALD_E_ARG, "non-finite layer height");
+    if (desc->fixed_layer)
+      for (int i = 0; i < desc->n_fixed; ++i)
+        if (desc->fixed_layer[i] != 0 && desc->fixed_layer[i] != 1)
+          return fail(EWALD_E_ARG, "fixed_layer entries must be 0 or 1");
+  }
+  const double u_cut = u_terms > 0 ? desc->u_cutoff : 0.0;
+  if (u_terms > 0 && (!is_fin(u_cut) || !(u_cut > 0) || u_cut > r_ins * (1.0 + 1e-12)))
+    return fail(EWALD_E_RCUT, "u_cutoff must be in (0, r_inscribed]");
+  // minimum images are resolved exactly up to this distance
+  const double r_img = std::max(r_cut, u_cut);
   // the pair potential's erf part is one polynomial on [0, r_cut]; it is
   // built for alpha r_cut <= 5.5, where erfc(alpha r_cut) < 1e-14 already
   if (alpha * r_cut > 5.5)
@@ -534,7 +581,7 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   S->n_shells = int(shells.size());
   S->precision = desc->precision;
   S->refresh_every = desc->refresh_every;
-  S->has_jastrow = desc->n_jastrow > 0;
+  S->has_jastrow = desc->n_jastrow > 0 || u_terms > 0;
   S->r_ins = r_ins;
   S->seg_n.resize(n_seg);
   S->slot_n.assign(size_t(n_slots) * 3, 0);
@@ -542,6 +589,12 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   S->ja.assign(n_slots, 0.0);
   S->shell.assign(n_slots, -1);
   S->rho_fix.assign(size_t(n_slots) * 2, 0.0);
+  if (layered) {
+    S->wx.assign(n_slots, 0.0);
+    S->rho_fix1.assign(size_t(n_slots) * 2, 0.0);
+    S->fixed_layer.assign(size_t(desc->n_fixed), 0);
+    if (desc->fixed_layer) std::copy(desc->fixed_layer, desc->fixed_layer + desc->n_fixed, S->fixed_layer.begin());
+  }
   int nmax[3] = {0, 0, 0};
   for (auto& g : half)
     for (int d = 0; d < dim; ++d) nmax[d] = std::max(nmax[d], std::abs(g.n[d]));
@@ -559,6 +612,13 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
       const double g = std::sqrt(g2);
       S->w[slot] = (dim == 3) ? 4 * kPi / measure * std::exp(-g2 / (4 * alpha * alpha)) / g2
                               : 2 * kPi / measure * std::erfc(g / (2 * alpha)) / g;
+      if (layered) {  // (pi/A) [e^{dG} erfc(G/2a + da) + e^{-dG} erfc(G/2a - da)] / G, in long double
+        const long double d = std::fabs((long double)desc->layer_z[1] - (long double)desc->layer_z[0]);
+        const long double gl = g, al = alpha;
+        const long double f = std::exp(d * gl) * std::erfc(gl / (2 * al) + d * al) +
+                              std::exp(-d * gl) * std::erfc(gl / (2 * al) - d * al);
+        S->wx[slot] = double((long double)kPi / measure * f / gl);
+      }
       int sh = int(std::lower_bound(shells.begin(), shells.end(), g2 * (1.0 - 1e-9)) - shells.begin());
       S->shell[slot] = sh;
       S->ja[slot] = (sh < desc->n_jastrow) ? desc->jastrow_a[sh] : 0.0;
@@ -582,13 +642,14 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
       double x = 0;
       for (int d = 0; d < dim; ++d) x += S->slot_n[slot * 3 + d] * S->fixed_s[I * dim + d];
       x -= std::nearbyint(x);
-      S->rho_fix[2 * slot] += S->fixed_q[I] * std::cos(2 * kPi * x);
-      S->rho_fix[2 * slot + 1] += S->fixed_q[I] * std::sin(2 * kPi * x);
+      std::vector<double>& rf = (layered && S->fixed_layer[I] == 1) ? S->rho_fix1 : S->rho_fix;
+      rf[2 * slot] += S->fixed_q[I] * std::cos(2 * kPi * x);
+      rf[2 * slot + 1] += S->fixed_q[I] * std::sin(2 * kPi * x);
     }
   }
 
   // ---- minimum-image candidates: lattice points c != 0 whose cell-shaped box
-  // comes within r_cut of the origin (one of each +-pair) ----
+  // comes within r_img = max(r_cut, L_u) of the origin (one of each +-pair) ----
   std::vector<double> cand;
   const int cr = 3;
   for (int i = -cr; i <= cr; ++i)
@@ -602,7 +663,7 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
         // a box that only touches the cutoff sphere holds no point strictly
         // inside it (the real-space test is |r| < r_cut)
         double d2 = box_min_dist2(M, dim, c);
-        if (d2 < r_cut * r_cut * (1.0 - 1e-12)) {
+        if (d2 < r_img * r_img * (1.0 - 1e-12)) {
           bool edge = false;
           for (int d = 0; d < dim; ++d) edge = edge || std::abs(c[d]) == cr;
           if (edge) return fail(EWALD_E_RCUT, "internal: candidate search range too small");
@@ -622,8 +683,18 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   for (double q : S->mobile_q) { q2 += q * q; qt += q; }
   for (double q : S->fixed_q) { q2 += q * q; qt += q; }
   const double e_self = -alpha / std::sqrt(kPi) * q2;
-  const double e_bg = (dim == 3) ? -kPi / (2 * measure * alpha * alpha) * qt * qt
-                                 : -std::sqrt(kPi) / (measure * alpha) * qt * qt;
+  double e_bg = (dim == 3) ? -kPi / (2 * measure * alpha * alpha) * qt * qt
+                           : -std::sqrt(kPi) / (measure * alpha) * qt * qt;
+  const double dz = layered ? desc->layer_z[1] - desc->layer_z[0] : 0.0;
+  if (layered) {  // 1/2 sum_{l,m} Q_l Q_m c(z_l - z_m)
+    double Q[2] = {0, 0};
+    for (int i = 0; i < desc->n_mobile; ++i) Q[i >= desc->n_mobile_layer0 ? 1 : 0] += S->mobile_q[i];
+    for (int I = 0; I < desc->n_fixed; ++I) Q[S->fixed_layer[I]] += S->fixed_q[I];
+    auto c = [&](double z) {
+      return -2 * kPi / measure * (z * std::erf(z * alpha) + std::exp(-alpha * alpha * z * z) / (alpha * std::sqrt(kPi)));
+    };
+    e_bg = 0.5 * (Q[0] * Q[0] + Q[1] * Q[1]) * c(0.0) + Q[0] * Q[1] * c(dz);
+  }
   // ion-ion real-space pairs (the ions never move); images by brute force
   double e_ii = 0;
   for (int I = 0; I < desc->n_fixed; ++I)
@@ -646,6 +717,7 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
             }
             best = std::min(best, r2);
           }
+      if (layered && S->fixed_layer[I] != S->fixed_layer[J]) best += dz * dz;
       if (best < r_cut * r_cut) {
         double r = std::sqrt(best);
         e_ii += S->fixed_q[I] * S->fixed_q[J] * std::erfc(alpha * r) / r;
@@ -678,6 +750,8 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
     for (int i = 0; i < dim; ++i)
       for (int j = 0; j <= i; ++j)
         Lrot[i * 3 + j] = A[i * 3] * e[j][0] + A[i * 3 + 1] * e[j][1] + A[i * 3 + 2] * e[j][2];
+    for (int i = 0; i < 3; ++i)
+      for (int x = 0; x < 3; ++x) S->dev.El[i * 3 + x] = e[i][x];
   }
 
   for (int c = 0; c < n_cand; ++c)
@@ -724,10 +798,40 @@ ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
     }
     D.cand[c][3] = v2;
   }
+  // Jastrow u term: sum_l alpha_l r^l (r - L)^C = L^C sum_l alpha_l L^l t^l (t - 1)^C
+  // in powers of t = r / L (long double), per channel; channel 1 stored as
+  // its difference from channel 0
+  D.n_layers = layered ? 2 : 1;
+  D.n0 = layered ? desc->n_mobile_layer0 : S->n_mobile;
+  D.dz2 = dz * dz;
+  D.has_u = u_terms > 0 ? 1 : 0;
+  if (u_terms > 0) {
+    const int C = desc->u_C;
+    long double beta[2][UDEG + 1] = {{0}};
+    for (int c = 0; c < 2; ++c)
+      for (int l = 0; l < u_terms; ++l) {
+        long double binom = 1.0L;  // C choose k
+        for (int k = 0; k <= C; ++k) {
+          const long double sgn = ((C - k) & 1) ? -1.0L : 1.0L;
+          beta[c][l + k] += (long double)desc->u_alpha[c * u_terms + l] * std::pow((long double)u_cut, l + C) *
+                            binom * sgn;
+          binom = binom * (C - k) / (k + 1);
+        }
+      }
+    for (int m = 0; m <= UDEG; ++m) {
+      D.u_c0[m] = double(beta[0][m]);
+      D.u_dc[m] = double(beta[1][m] - beta[0][m]);
+    }
+    D.u_cut2 = u_cut * u_cut;
+    D.u_icut = 1.0 / u_cut;
+    S->spin.assign(size_t(desc->n_mobile), 0);
+    if (desc->mobile_spin) std::copy(desc->mobile_spin, desc->mobile_spin + desc->n_mobile, S->spin.begin());
+  }
   OrthoFrame of;
   D.ortho = ortho_frame(A, dim, of) ? 1 : 0;
   if (D.ortho) {
     std::copy(of.F, of.F + 9, D.F);
+    std::copy(of.E, of.E + 9, D.Eo);
     for (int d = 0; d < 3; ++d) {
       D.box[d] = of.box[d];
       D.ibox[d] = of.box[d] > 0 ? 1.0 / of.box[d] : 0.0;
@@ -813,6 +917,10 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   const size_t o_fs = take(std::max<size_t>(1, s->fixed_s.size()) * 8);
   const size_t o_fq = take(std::max<size_t>(1, s->fixed_q.size()) * 8);
   const size_t o_mq = take(s->mobile_q.size() * 8);
+  const size_t o_sp = take(std::max<size_t>(1, s->spin.size()) * 4);
+  const size_t o_wx = take(s->wx.size() * 8);
+  const size_t o_rf1 = take(s->rho_fix1.size() * 8);
+  const size_t o_fl = take(std::max<size_t>(1, s->fixed_layer.size()) * 4);
   // shell table: (w, a) per shell and a zero entry for padding slots
   const int n_wtab = s->n_shells + 1;
   std::vector<double> wa(size_t(n_wtab) * 2, 0.0);
@@ -842,6 +950,10 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   if (!s->fixed_s.empty()) std::memcpy(host.data() + o_fs, s->fixed_s.data(), s->fixed_s.size() * 8);
   if (!s->fixed_q.empty()) std::memcpy(host.data() + o_fq, s->fixed_q.data(), s->fixed_q.size() * 8);
   std::memcpy(host.data() + o_mq, s->mobile_q.data(), s->mobile_q.size() * 8);
+  if (!s->spin.empty()) std::memcpy(host.data() + o_sp, s->spin.data(), s->spin.size() * 4);
+  if (!s->wx.empty()) std::memcpy(host.data() + o_wx, s->wx.data(), s->wx.size() * 8);
+  if (!s->rho_fix1.empty()) std::memcpy(host.data() + o_rf1, s->rho_fix1.data(), s->rho_fix1.size() * 8);
+  if (!s->fixed_layer.empty()) std::memcpy(host.data() + o_fl, s->fixed_layer.data(), s->fixed_layer.size() * 4);
   std::memcpy(host.data() + o_wa, wa.data(), wa.size() * 8);
   std::memcpy(host.data() + o_jg, jg2.data(), jg2.size() * 8);
   std::memcpy(host.data() + o_sl, sl.data(), sl.size() * 2);
@@ -862,6 +974,10 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   D.fixed_s = reinterpret_cast<const double*>(base + o_fs);
   D.fixed_q = reinterpret_cast<const double*>(base + o_fq);
   D.mobile_q = reinterpret_cast<const double*>(base + o_mq);
+  D.spin = s->spin.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + o_sp);
+  D.wx = s->wx.empty() ? nullptr : reinterpret_cast<const double*>(base + o_wx);
+  D.rho_fix1 = s->rho_fix1.empty() ? nullptr : reinterpret_cast<const double*>(base + o_rf1);
+  D.fixed_layer = s->fixed_layer.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + o_fl);
   D.wa_tab = reinterpret_cast<const double*>(base + o_wa);
   D.jg2_tab = reinterpret_cast<const double*>(base + o_jg);
   D.slot_shell = reinterpret_cast<const uint16_t*>(base + o_sl);
@@ -934,7 +1050,7 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
     dw.pad_ = 0;
     B->walkers.push_back(dw);
     B->pos_offsets[w + 1] = B->pos_offsets[w] + size_t(s->n_mobile);
-    off += walker_state_bytes(s->n_mobile, dim, s->n_seg);
+    off += walker_state_bytes(s->n_mobile, dim, s->n_seg, s->dev.n_layers);
   }
   B->state_bytes = off;
   std::vector<DevSys> ds;
@@ -947,6 +1063,8 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
   for (int i = 0; i < n_sys; ++i) {
     ds.push_back(sys[i]->dev_uploaded);
     L.has_jastrow |= sys[i]->has_jastrow ? 1 : 0;
+    L.has_u |= sys[i]->dev.has_u;
+    L.layered |= sys[i]->dev.n_layers > 1 ? 1 : 0;
     L.max_n_seg = std::max(L.max_n_seg, sys[i]->n_seg);
     L.max_nm = std::max(L.max_nm, sys[i]->dev.nm);
     L.max_particles = std::max(L.max_particles, sys[i]->n_mobile);
@@ -1019,7 +1137,7 @@ ewald_status ewald_move_delta_grad_batch(ewald_batch* b, void* state, const int3
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (!state || !k || !new_pos || !delta) return fail(EWALD_E_ARG, "state, k, new_pos and delta must be non-NULL");
   if ((jgrad == nullptr) != (jlap == nullptr)) return fail(EWALD_E_ARG, "jgrad and jlap must both be given or both NULL");
-  if (jgrad && !b->lb.has_jastrow) return fail(EWALD_E_ARG, "Jastrow derivatives need Jastrow coefficients");
+  if (jgrad && !b->lb.has_jastrow) return fail(EWALD_E_ARG, "Jastrow derivatives need Jastrow coefficients or a u term");
   ewald_status st = check_state(b, state, 1, -1);
   if (st != EWALD_OK) return st;
   int rc = launch_delta(b->lb, static_cast<char*>(state), k, new_pos, delta, djastrow, jgrad, jlap, stream);
@@ -1050,7 +1168,7 @@ ewald_status ewald_run_moves_grad_batch(ewald_batch* b, void* state, int n_steps
   if (n_steps < 0) return fail(EWALD_E_ARG, "n_steps must be >= 0");
   if (!state) return fail(EWALD_E_ARG, "state must be non-NULL");
   if ((jgrad == nullptr) != (jlap == nullptr)) return fail(EWALD_E_ARG, "jgrad and jlap must both be given or both NULL");
-  if (jgrad && !b->lb.has_jastrow) return fail(EWALD_E_ARG, "Jastrow derivatives need Jastrow coefficients");
+  if (jgrad && !b->lb.has_jastrow) return fail(EWALD_E_ARG, "Jastrow derivatives need Jastrow coefficients or a u term");
   ewald_status st = check_state(b, state, 3, -1);
   if (st != EWALD_OK) return st;
   if (n_steps == 0) return EWALD_OK;
@@ -1104,8 +1222,8 @@ std::string tune_key(const ewald_batch* b) {
   dev_arch(arch, sizeof(arch));
   const LaunchBatch& L = b->lb;
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "arch=%s dim=%d mixed=%d jastrow=%d segs=%d nm=%d particles=%d fixed=%d "
-                "poly=%d wtab=%d ortho=%d walkers=%d", arch, L.dim, L.mixed, L.has_jastrow, L.max_n_seg, L.max_nm,
+  std::snprintf(buf, sizeof(buf), "arch=%s dim=%d mixed=%d jastrow=%d u=%d segs=%d nm=%d particles=%d fixed=%d "
+                "poly=%d wtab=%d ortho=%d walkers=%d", arch, L.dim, L.mixed, L.has_jastrow, L.has_u, L.max_n_seg, L.max_nm,
                 L.max_particles, L.max_fixed, L.poly_deg, L.max_wtab, L.all_ortho, L.n_walkers);
   return buf;
 }

@@ -25,6 +25,7 @@ constexpr int RUN_CHUNK = 64;     // proposals staged in LDS per chunk by the fu
 constexpr int WTAB_MAX = 1024;    // largest shell table kept in LDS by the fused kernel
 constexpr int POLY_MAX = 32;      // largest degree of the pair-potential polynomial (FP64)
 constexpr int POLY32_MAX = 22;    // largest degree of its FP32 counterpart
+constexpr int UDEG = 15;          // degree of the Jastrow u polynomial in t = r / L_u (N_u + C <= UDEG)
 
 // Per-walker state header (first bytes of the walker's state block).
 struct WalkerHdr {
@@ -75,6 +76,32 @@ struct DevSys {
   // jlap_c = sum_{G in H} a_s(G) |G|^2
   double B[9];
   double jlap_c;
+  // Jastrow two-body polynomial term u (has_u): u(r) = sum_m c_m t^m for
+  // t = r / L_u < 1, with c = u_c0 for a pair of equal spin labels and
+  // u_c0 + u_dc for unequal ones (the set-up expands the product form of the
+  // term into powers of t); mobile particles only.
+  int has_u;
+  double u_cut2;          // L_u^2
+  double u_icut;          // 1 / L_u
+  double u_c0[UDEG + 1];
+  double u_dc[UDEG + 1];
+  const int32_t* spin;    // [n_mobile] spin labels (0/1)
+  // frame axes as rows (Cartesian unit vectors): Eo of the orthogonal
+  // sublattice frame (x = s F), El of the lower-triangular frame (Lrot), so
+  // that a displacement x in a frame is sum_d x_d E[d] in Cartesian axes
+  double Eo[9];
+  double El[9];
+  // Layered 2D system (n_layers = 2): mobile particles j >= n0 and the ions
+  // with fixed_layer 1 lie in the second plane, dz2 = (z_1 - z_0)^2 apart;
+  // rho of the second plane follows the first in the walker state
+  // (SEG n_seg slots later); wx: the cross-plane weight per slot,
+  // rho_fix1: the second plane's ions.
+  int n_layers;
+  int n0;
+  double dz2;
+  const double* wx;
+  const double* rho_fix1;
+  const int32_t* fixed_layer;
   // erf(alpha r)/(alpha r) = sum_i p64[i] t^i for r < r_cut (p32: FP32 copy of lower accuracy)
   double p64[POLY_MAX + 1];
   float p32[POLY32_MAX + 1];
@@ -110,8 +137,12 @@ struct DevWalker {
 EW_HD inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 EW_HD inline size_t walker_pos_bytes(int n_mobile, int dim) { return align256(size_t(n_mobile) * dim * 8); }
-EW_HD inline size_t walker_state_bytes(int n_mobile, int dim, int n_seg) {
-  return HDR_BYTES + walker_pos_bytes(n_mobile, dim) + align256(size_t(n_seg) * SEG * 16);
+// rho of a layered system holds one block of n_seg SEG slots per plane
+EW_HD inline size_t walker_rho_bytes(int n_seg, int n_layers) {
+  return align256(size_t(n_seg) * SEG * 16 * size_t(n_layers > 1 ? n_layers : 1));
+}
+EW_HD inline size_t walker_state_bytes(int n_mobile, int dim, int n_seg, int n_layers = 1) {
+  return HDR_BYTES + walker_pos_bytes(n_mobile, dim) + walker_rho_bytes(n_seg, n_layers);
 }
 
 inline uint32_t pack_n(int a, int b, int c) {
@@ -126,7 +157,9 @@ struct LaunchBatch {
   int n_walkers;
   int dim;
   int mixed;
-  int has_jastrow;          // any system with Jastrow coefficients
+  int has_jastrow;          // any system with Jastrow coefficients or a u term
+  int has_u;                // any system with a Jastrow u term
+  int layered;              // any layered 2D system (the per-step kernels serve the sweep)
   int max_n_seg;
   int max_nm;
   int max_particles;        // max n_mobile over systems

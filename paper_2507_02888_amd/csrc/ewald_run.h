@@ -45,7 +45,9 @@ struct RunLds {
 // JM: Jastrow mode, 0 = none, 1 = J and dJ, 2 = also the gradient and the
 // Laplacian of J with respect to the moved particle at each proposed
 // configuration (as in k_delta: accumulated as S_d = sum_H a n_d Im z and
-// sum_H a |G|^2 Re z, z = conj(rho') e').
+// sum_H a |G|^2 Re z, z = conj(rho') e'); 3 and 4 = 1 and 2 with the
+// two-body polynomial term u of the mobile pairs added (its gradient summed
+// in the geometry's frame axes, turned Cartesian once per move).
 template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA>
 __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
@@ -53,8 +55,9 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
                                             const double* __restrict__ new_pos, const uint8_t* __restrict__ accept,
                                             double* __restrict__ delta, double* __restrict__ djas,
                                             double* __restrict__ jgrad, double* __restrict__ jlap, RunLds L) {
-  constexpr bool JAS = JM > 0, DER = JM == 2;
-  constexpr int NDV = DIM + 1;  // derivative partial sums per move: S_0 .. S_{DIM-1}, L
+  constexpr bool JAS = JM > 0, DER = JM == 2 || JM == 4, UJ = JM >= 3;
+  constexpr int NDP = DIM + 1;               // p-term derivative sums per move: S_0 .. S_{DIM-1}, L
+  constexpr int NDV = UJ ? 2 * NDP : NDP;    // plus the u term's gradient (frame axes) and Laplacian
   using R = typename std::conditional<MIXED, float, double>::type;
   using WT = R;          // the mixed form multiplies weights with FP32 terms
   using WT2 = cplx<WT>;  // (weight, Jastrow coefficient)
@@ -103,6 +106,7 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
   if (K > 0 && counter >= K) counter = 0;
 
   double ps[PPR][DIM], pq[PPR];
+  int psp[PPR];  // UJ: spin labels of the thread's own particles
 #pragma unroll
   for (int c = 0; c < PPR; ++c) {
     const int j = tid + c * NT;
@@ -111,6 +115,7 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
     for (int d = 0; d < DIM; ++d) sj[d] = j < n ? spos[j * DIM + d] : 0.0;
     geo_pos<DIM, ORTHO>(sj, S, ps[c]);
     pq[c] = j < n ? S->mobile_q[j] : 0.0;
+    psp[c] = (UJ && j < n) ? S->spin[j] : 0;
   }
   // Workgroups of up to 512 threads (256 vector registers per lane) hold the
   // pair-polynomial coefficients in vector registers for the whole sweep
@@ -291,8 +296,21 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
           if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
-          v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO, XTRA>(xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32,
-                                                                CV ? fk : frame_k(S));
+          if (!UJ)
+            v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO, XTRA>(xn, xo, k, ps, pq, lpos, lq, n, S, c64,
+                                                                       c32, CV ? fk : frame_k(S));
+        }
+        if (UJ) {  // the u term moves with a neutral particle too
+          UOut<DIM> uo;
+          const double er = real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO, XTRA, UJ, DER>(
+              xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32, CV ? fk : frame_k(S), psp, S->spin[k], &uo);
+          v0 += qk * er;
+          v1 += uo.d;
+          if (DER) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) dv[NDP + d] = uo.g[d];
+            dv[NDV - 1] = uo.l;
+          }
         }
         if (acc) {
           if ((k % NT) == tid) {  // the owner moves its particle
@@ -354,14 +372,16 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
             for (int d = 0; d < NDV; ++d) sv[d] += p2[v * NDV + d];
         }
         const double qk = kq >= 0 ? lq[kq] : 0.0;
+        double ug[DIM];  // u term gradient in Cartesian axes
+        if (UJ) frame_to_cart<DIM>(sv + NDP, ORTHO ? S->Eo : S->El, ug);
 #pragma unroll
         for (int e2 = 0; e2 < DIM; ++e2) {
           double gx = 0.0;
 #pragma unroll
           for (int d = 0; d < DIM; ++d) gx = fma(sv[d], S->B[d * 3 + e2], gx);
-          jgrad[idx * DIM + e2] = kq < 0 ? NAN : -2.0 * qk * gx;
+          jgrad[idx * DIM + e2] = kq < 0 ? NAN : -2.0 * qk * gx + (UJ ? ug[e2] : 0.0);
         }
-        jlap[idx] = kq < 0 ? NAN : -2.0 * qk * sv[DIM] + 2.0 * qk * qk * S->jlap_c;
+        jlap[idx] = kq < 0 ? NAN : -2.0 * qk * sv[DIM] + 2.0 * qk * qk * S->jlap_c + (UJ ? sv[NDV - 1] : 0.0);
       }
     }
     if (MIXED && K > 0 && counter >= K) {  // uniform: rebuild rho in FP64 between chunks
@@ -440,7 +460,7 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
 
 
 // LDS layout of the fused kernel for a chunk of ch moves; returns the total bytes.
-template <int DIM, bool MIXED, int NT, int SPT, bool DER>
+template <int DIM, bool MIXED, int NT, int SPT, bool DER, bool UJ = false>
 size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int NW = NT / 64;
@@ -480,7 +500,7 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
     L.wtab2 = uint32_t(o);
     o = up16(o + size_t(b.max_wtab) * sizeof(R));
     L.part2 = uint32_t(o);
-    o = up16(o + size_t(ch) * NW * 4 * (DIM + 1) * 8);
+    o = up16(o + size_t(ch) * NW * 4 * (DIM + 1) * (UJ ? 2 : 1) * 8);
   }
   L.ch = ch;
   L.rtile = int(std::min<size_t>(ctab / rpart, 64)) & ~1;  // even (the tiles interleave particle pairs)
@@ -516,15 +536,15 @@ struct RunArgs {
 template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA>
 int run_inst(const LaunchBatch& b, const RunArgs& a) {
   auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, XTRA>;
-  constexpr bool DER = JM == 2;
+  constexpr bool DER = JM == 2 || JM == 4, UJ = JM >= 3;
   static const int per_cu = blocks_per_cu(kern, NT);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
   RunLds L{};
   int ch = b.run_chunk > 0 ? std::min(b.run_chunk, RUN_CHUNK) : RUN_CHUNK;
-  size_t lds = run_layout<DIM, MIXED, NT, SPT, DER>(b, ch, L);
+  size_t lds = run_layout<DIM, MIXED, NT, SPT, DER, UJ>(b, ch, L);
   if (b.run_chunk <= 0)
-    while (lds > budget && ch > 8) lds = run_layout<DIM, MIXED, NT, SPT, DER>(b, --ch, L);
-  while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT, SPT, DER>(b, --ch, L);
+    while (lds > budget && ch > 8) lds = run_layout<DIM, MIXED, NT, SPT, DER, UJ>(b, --ch, L);
+  while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT, SPT, DER, UJ>(b, --ch, L);
   if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
   if (a.plan) {
     *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu};
@@ -620,5 +640,14 @@ int run_d2_fp64_j2(const LaunchBatch& b, const RunArgs& a);
 int run_d2_mixed_j0(const LaunchBatch& b, const RunArgs& a);
 int run_d2_mixed_j1(const LaunchBatch& b, const RunArgs& a);
 int run_d2_mixed_j2(const LaunchBatch& b, const RunArgs& a);
+// the same with the Jastrow u term (JM = 3: J and dJ; 4: also derivatives)
+int run_d3_fp64_j3(const LaunchBatch& b, const RunArgs& a);
+int run_d3_fp64_j4(const LaunchBatch& b, const RunArgs& a);
+int run_d3_mixed_j3(const LaunchBatch& b, const RunArgs& a);
+int run_d3_mixed_j4(const LaunchBatch& b, const RunArgs& a);
+int run_d2_fp64_j3(const LaunchBatch& b, const RunArgs& a);
+int run_d2_fp64_j4(const LaunchBatch& b, const RunArgs& a);
+int run_d2_mixed_j3(const LaunchBatch& b, const RunArgs& a);
+int run_d2_mixed_j4(const LaunchBatch& b, const RunArgs& a);
 
 }  // namespace ewald

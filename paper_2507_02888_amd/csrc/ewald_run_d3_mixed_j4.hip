@@ -1,0 +1,6 @@
+// Fused multi-move kernels: 3D, FP32-mixed form, with the Jastrow value, the two-body u term and their derivatives.
+#include "ewald_run.h"
+
+namespace ewald {
+int run_d3_mixed_j4(const LaunchBatch& b, const RunArgs& a) { return run_entry<3, true, 4>(b, a); }
+}  // namespace ewald

@@ -31,7 +31,8 @@ EXPORTS = ("ewald_setup", "ewald_sys_query", "ewald_sys_tables", "ewald_sys_cand
            "ewald_batch_destroy", "ewald_energy_batch", "ewald_move_delta_batch",
            "ewald_accept_batch", "ewald_run_moves_batch", "ewald_move_delta_grad_batch",
            "ewald_run_moves_grad_batch", "ewald_batch_set_tuning",
-           "ewald_batch_get_tuning", "ewald_autotune", "ewald_last_error")
+           "ewald_batch_get_tuning", "ewald_autotune", "ewald_blip_create", "ewald_blip_destroy",
+           "ewald_blip_eval_batch", "ewald_last_error")
 
 
 class EwaldError(RuntimeError):
@@ -47,7 +48,11 @@ class SysDesc(ctypes.Structure):
                 ("mobile_q", ctypes.POINTER(ctypes.c_double)), ("alpha", ctypes.c_double),
                 ("g_cut", ctypes.c_double), ("r_cut", ctypes.c_double),
                 ("precision", ctypes.c_int), ("refresh_every", ctypes.c_int),
-                ("n_jastrow", ctypes.c_int), ("jastrow_a", ctypes.POINTER(ctypes.c_double))]
+                ("n_jastrow", ctypes.c_int), ("jastrow_a", ctypes.POINTER(ctypes.c_double)),
+                ("u_terms", ctypes.c_int), ("u_C", ctypes.c_int), ("u_cutoff", ctypes.c_double),
+                ("u_alpha", ctypes.POINTER(ctypes.c_double)), ("mobile_spin", ctypes.POINTER(ctypes.c_int32)),
+                ("n_layers", ctypes.c_int), ("layer_z", ctypes.c_double * 2), ("n_mobile_layer0", ctypes.c_int),
+                ("fixed_layer", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -84,10 +89,14 @@ def load() -> ctypes.CDLL:
     lib.ewald_batch_set_tuning.argtypes = [vp, c_int, c_int, c_int]
     lib.ewald_batch_get_tuning.argtypes = [vp, P(c_int), P(c_int), P(c_int), P(c_int)]
     lib.ewald_autotune.argtypes = [vp, vp, c_int, ctypes.c_char_p, vp]
+    lib.ewald_blip_create.argtypes = [P((ctypes.c_double * 3) * 3), P(c_int * 3), c_int, P(vp)]
+    lib.ewald_blip_destroy.argtypes = [vp]
+    lib.ewald_blip_destroy.restype = None
+    lib.ewald_blip_eval_batch.argtypes = [vp, vp, c_int, vp, vp, vp, vp, vp]
     lib.ewald_last_error.argtypes = []
     lib.ewald_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("ewald_sys_destroy", "ewald_batch_destroy", "ewald_last_error"):
+        if name not in ("ewald_sys_destroy", "ewald_batch_destroy", "ewald_blip_destroy", "ewald_last_error"):
             getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -106,8 +115,11 @@ def _dp(a: np.ndarray):
 
 def ewald_setup(dim: int, lattice, mobile_q, alpha: float, g_cut: float, r_cut: float,
                 fixed_pos=None, fixed_q=None, precision: int = EWALD_FP64,
-                refresh_every: int = 0, jastrow_a=None) -> int:
-    """Returns the ewald_sys* handle as an int."""
+                refresh_every: int = 0, jastrow_a=None, u_alpha=None, u_C: int = 0, u_cutoff: float = 0.0,
+                mobile_spin=None, layer_z=None, n_mobile_layer0: int = 0, fixed_layer=None) -> int:
+    """Returns the ewald_sys* handle as an int.  u_alpha [2][N_u + 1] (with
+    u_C, u_cutoff and the mobile particles' spin labels) adds the Jastrow
+    two-body polynomial term."""
     lib = load()
     keep = []
     d = SysDesc()
@@ -139,6 +151,25 @@ def ewald_setup(dim: int, lattice, mobile_q, alpha: float, g_cut: float, r_cut: 
         d.jastrow_a = _dp(ja)
     else:
         d.n_jastrow = 0
+    if u_alpha is not None:
+        ua = np.ascontiguousarray(u_alpha, dtype=np.float64).reshape(2, -1)
+        keep.append(ua)
+        d.u_terms, d.u_C, d.u_cutoff = int(ua.shape[1]), int(u_C), float(u_cutoff)
+        d.u_alpha = _dp(ua)
+        if mobile_spin is not None:
+            sp = np.ascontiguousarray(mobile_spin, dtype=np.int32)
+            keep.append(sp)
+            d.mobile_spin = sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    else:
+        d.u_terms = 0
+    if layer_z is not None:
+        d.n_layers = 2
+        d.layer_z[0], d.layer_z[1] = float(layer_z[0]), float(layer_z[1])
+        d.n_mobile_layer0 = int(n_mobile_layer0)
+        if fixed_layer is not None and len(fixed_layer) > 0:
+            fl = np.ascontiguousarray(fixed_layer, dtype=np.int32)
+            keep.append(fl)
+            d.fixed_layer = fl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     h = ctypes.c_void_p()
     _check(lib.ewald_setup(ctypes.byref(d), ctypes.byref(h)))
     return int(h.value)
@@ -287,9 +318,19 @@ class System:
         kw = dict(alpha=system.alpha, g_cut=system.g_cut, r_cut=system.r_cut)
         kw.update(override)
         self.system = system
+        u = {}
+        if getattr(system, "u_alpha", None) is not None:
+            u = dict(u_alpha=system.u_alpha, u_C=system.u_C, u_cutoff=system.u_cut,
+                     mobile_spin=system.mobile_spin)
+        if getattr(system, "layer_z", None) is not None:
+            ml = np.asarray(system.mobile_layer)
+            n0 = int(np.sum(ml == 0))
+            if not (np.all(ml[:n0] == 0) and np.all(ml[n0:] == 1)):
+                raise ValueError("mobile particles must be ordered by plane (plane 0 first)")
+            u.update(layer_z=system.layer_z, n_mobile_layer0=n0, fixed_layer=system.fixed_layer)
         self.handle = ewald_setup(system.dim, system.lattice, system.mobile_q, kw["alpha"], kw["g_cut"],
                                   kw["r_cut"], fixed_pos=system.fixed_pos, fixed_q=system.fixed_q,
-                                  precision=precision, refresh_every=refresh_every, jastrow_a=jastrow_a)
+                                  precision=precision, refresh_every=refresh_every, jastrow_a=jastrow_a, **u)
         self.info = ewald_sys_query(self.handle)
 
     def tables(self):
@@ -385,6 +426,58 @@ class Batch:
     def close(self):
         if self.handle:
             ewald_batch_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- blip orbitals -------------------------------------------------------------
+
+def ewald_blip_create(lattice, grid, n_orb: int) -> int:
+    lat = ((ctypes.c_double * 3) * 3)()
+    a = np.asarray(lattice, dtype=np.float64)
+    for i in range(3):
+        for j in range(3):
+            lat[i][j] = float(a[i, j])
+    g = (ctypes.c_int * 3)(*[int(x) for x in grid])
+    h = ctypes.c_void_p()
+    _check(load().ewald_blip_create(ctypes.byref(lat), ctypes.byref(g), int(n_orb), ctypes.byref(h)))
+    return int(h.value)
+
+
+def ewald_blip_destroy(h: int) -> None:
+    load().ewald_blip_destroy(ctypes.c_void_p(h))
+
+
+def ewald_blip_eval_batch(h: int, coef: int, n_points: int, pos: int, val: int, grad: int = 0, lap: int = 0,
+                          stream: int = 0) -> None:
+    _check(load().ewald_blip_eval_batch(ctypes.c_void_p(h), ctypes.c_void_p(coef), int(n_points),
+                                        ctypes.c_void_p(pos), ctypes.c_void_p(val), ctypes.c_void_p(grad or None),
+                                        ctypes.c_void_p(lap or None), ctypes.c_void_p(stream or None)))
+
+
+class Blips:
+    """Owns an ewald_blip handle; evaluates orbitals from torch device tensors."""
+
+    def __init__(self, lattice, grid, n_orb: int):
+        self.grid = tuple(int(x) for x in grid)
+        self.n_orb = int(n_orb)
+        self.handle = ewald_blip_create(lattice, self.grid, self.n_orb)
+
+    def eval(self, coef, pos, val, grad=None, lap=None):
+        import torch
+        n = int(pos.shape[0])
+        ewald_blip_eval_batch(self.handle, coef.data_ptr(), n, pos.data_ptr(), val.data_ptr(),
+                              0 if grad is None else grad.data_ptr(), 0 if lap is None else lap.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+
+    def close(self):
+        if self.handle:
+            ewald_blip_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

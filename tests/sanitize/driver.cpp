@@ -22,6 +22,7 @@ typedef struct {
   double u_cut;
   const double* u_alpha;
   const int* spin;
+  const double* z;
 } osys;
 int oracle_energy(const osys* s, int n, const double* pos, const double* q, double* parts, double* jastrow);
 int oracle_run(const osys* s, int n, int n_mobile, const double* pos0, const double* q, int n_steps,
@@ -148,6 +149,11 @@ static void run_cell(const Cell& c, int n, int n_ions) {
     d.refresh_every = prec ? 8 : 0;
     d.n_jastrow = int(ja.size());
     d.jastrow_a = ja.data();
+    d.u_terms = s.n_u;
+    d.u_C = s.u_c;
+    d.u_cutoff = s.u_cut;
+    d.u_alpha = ua.data();
+    d.mobile_spin = spin.data();  // the first n labels are the mobile particles'
     ewald_sys* sys = nullptr;
     CHECK(ewald_setup(&d, &sys) == EWALD_OK && sys);
     if (!sys) continue;
@@ -166,7 +172,41 @@ static void run_cell(const Cell& c, int n, int n_ions) {
     ewald_batch* b = nullptr;
     CHECK(ewald_batch_create(&sys, 1, &ws, 1, &b) == EWALD_E_HIP && b == nullptr);
     ewald_sys_destroy(sys);
+    if (dim == 2) {  // a layered system: two planes, no Jastrow terms; and the oracle's layered energy
+      ewald_sys_desc dl = d;
+      dl.n_jastrow = 0;
+      dl.u_terms = 0;
+      dl.n_layers = 2;
+      dl.layer_z[0] = 0.0;
+      dl.layer_z[1] = 0.8;
+      dl.n_mobile_layer0 = n / 2;
+      std::vector<int32_t> fl(n_ions, 1);
+      dl.fixed_layer = fl.data();
+      ewald_sys* ls = nullptr;
+      CHECK(ewald_setup(&dl, &ls) == EWALD_OK && ls);
+      ewald_sys_destroy(ls);
+      dl.n_jastrow = int(ja.size());
+      CHECK(ewald_setup(&dl, &ls) == EWALD_E_ARG);
+      if (prec == 0) {
+        std::vector<double> zz(nt, 0.0);
+        for (int i = n / 2; i < nt; ++i) zz[i] = 0.8;
+        osys sl = s;
+        sl.n_jastrow = 0;
+        sl.n_u = 0;
+        sl.z = zz.data();
+        double pl[5], jl0 = 0;
+        CHECK(oracle_energy(&sl, nt, pos.data(), q.data(), pl, &jl0) == 0 && std::isfinite(pl[4]));
+        CHECK(oracle_run(&sl, nt, n, pos.data(), q.data(), S, k.data(), newp.data(), acc.data(), e0, &j0,
+                         delta.data(), djas.data(), pf.data(), nullptr, nullptr) == 0);
+      }
+    }
     // argument checks
+    d.u_cutoff = 10 * L;
+    CHECK(ewald_setup(&d, &sys) == EWALD_E_RCUT);
+    d.u_cutoff = s.u_cut;
+    d.u_C = 20;
+    CHECK(ewald_setup(&d, &sys) == EWALD_E_ARG);
+    d.u_C = s.u_c;
     d.r_cut = 10 * L;
     CHECK(ewald_setup(&d, &sys) == EWALD_E_RCUT);
     d.r_cut = s.r_cut;

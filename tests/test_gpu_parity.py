@@ -4,6 +4,7 @@ Tolerances (relative to E_ref = max(|E_oracle|, (alpha/sqrt(pi)) sum q^2)):
   FP64 form   energies and move deltas within 1e-10 E_ref;
   FP32-mixed  energies within 1e-6 E_ref, each move delta within 1e-5 Ha.
 """
+import dataclasses
 import math
 import os
 import sys
@@ -47,8 +48,11 @@ def e_scale(system):
 class Case:
     """Seeded inputs of a workload subset, uploaded, with a library batch."""
 
-    def __init__(self, cfg_id, walkers, moves, precision, walker_start=0, refresh_every=None, jastrow=True):
-        self.cfg = wl.config(cfg_id)
+    def __init__(self, cfg_id, walkers, moves, precision, walker_start=0, refresh_every=None, jastrow=True,
+                 u_term=False, cfg=None):
+        self.cfg = wl.config(cfg_id) if cfg is None else cfg
+        if u_term:  # the same workload with the Jastrow two-body polynomial term
+            self.cfg.systems = [wl.with_u_term(s, cfg_id) for s in self.cfg.systems]
         self.b = wl.make_batch(self.cfg, walkers=walkers, moves=moves, walker_start=walker_start)
         K = self.cfg.refresh_every if refresh_every is None else refresh_every
         self.ja = self.b.jastrow_a if jastrow else None
@@ -838,3 +842,212 @@ def test_jastrow_derivs_argument_errors():
         ew.ewald_move_delta_grad_batch(c.batch.handle, c.batch.state.data_ptr(), c.k[0].data_ptr(),
                                        c.new_pos[0].data_ptr(), d.data_ptr(), 0, g.data_ptr(), 0)
     assert e.value.status == ew.EWALD_E_ARG
+
+
+# Jastrow two-body polynomial term u (Eq. (8)) added to the Jastrow outputs:
+# value, move deltas (per-step and fused) and derivatives against the oracle.
+# The u term is FP64 in both forms, so the mixed form keeps its bounds.
+U_SUBSETS = {1: (1, 20), 2: (2, 12), 3: (2, 16), 5: (2, 6)}
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [1, 2, 3, 5])
+def test_u_term_energy_and_moves(oracle_lib, cfg_id, precision):
+    W, S = U_SUBSETS[cfg_id]
+    say(f"[u term] cfg={cfg_id} precision={precision}")
+    results = {}
+    for path in ("per-step", "fused"):
+        c = Case(cfg_id, W, S, precision, refresh_every=4, u_term=True)
+        e0, j0 = c.run_energy()
+        results[path] = (e0, j0) + (c.per_step() if path == "per-step" else c.fused())
+    for w in range(W):
+        sysw = c.system(w)
+        assert sysw.u_alpha is not None
+        r = c.oracle(oracle_lib, w)
+        scale = max(abs(r["energy0"]), e_scale(sysw))
+        jscale = max(1.0, abs(r["j0"]))
+        for path, (e0, j0, d, dj) in results.items():
+            if precision == FP64:
+                assert abs(e0[w] - r["energy0"]) <= 1e-10 * scale
+                assert abs(j0[w] - r["j0"]) <= 1e-10 * jscale, (path, j0[w], r["j0"])
+                assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale, path
+                assert np.max(np.abs(dj[:, w] - r["djas"])) <= 1e-10 * jscale, path
+            else:
+                assert abs(j0[w] - r["j0"]) <= 1e-6 * jscale, (path, j0[w], r["j0"])
+                assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5, path
+                assert np.max(np.abs(dj[:, w] - r["djas"])) <= djas_bound(c, w), path
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [1, 3, 5])
+def test_u_term_derivs(oracle_lib, cfg_id, precision):
+    """Jastrow gradient and Laplacian with the u term, per-step and fused
+    (orthogonal-sublattice and general frames), against the oracle."""
+    W, S = U_SUBSETS[cfg_id]
+    for path in ("per-step", "fused", "fused-general"):
+        say(f"[u term derivs] cfg={cfg_id} precision={precision} path={path}")
+        c = Case(cfg_id, W, S, precision, u_term=True)
+        if path == "fused-general":
+            c.batch.set_tuning(general_frame=1)
+        c.run_energy()
+        d = torch.zeros((S, W), dtype=torch.float64, device="cuda")
+        dj = torch.zeros_like(d)
+        g = torch.zeros((S, W, c.dim), dtype=torch.float64, device="cuda")
+        l = torch.zeros((S, W), dtype=torch.float64, device="cuda")
+        if path == "per-step":
+            for m in range(S):
+                c.batch.move_delta_grad(c.k[m], c.new_pos[m], d[m], dj[m], g[m], l[m])
+                c.batch.accept(c.accept[m])
+        else:
+            c.batch.run_moves_grad(c.k, c.new_pos, c.accept, d, dj, g, l)
+        torch.cuda.synchronize()
+        check_derivs(c, oracle_lib, g.cpu().numpy(), l.cpu().numpy(), precision, path)
+
+
+# Blip orbitals (Sec. 2.4) against the oracle's plain sum over the grid.
+SKEW = np.array([[6.0, 0.4, 0.1], [0.7, 5.5, -0.3], [0.2, -0.5, 6.4]])
+
+
+@pytest.mark.parametrize("n_orb", [6, 5, 130])
+def test_blips_small_grid(oracle_lib, n_orb):
+    """A skewed cell, an 8 x 9 x 10 grid, even (paired loads), odd and
+    more-than-one-chunk orbital counts; points inside, outside and on the
+    cell's faces; values, gradients and Laplacians within 1e-12 relative."""
+    say(f"[blips small] n_orb={n_orb}")
+    grid = (8, 9, 10)
+    rng = np.random.default_rng([17, n_orb])
+    coef = rng.uniform(-1, 1, grid + (n_orb,))
+    s = rng.uniform(-1.5, 2.5, (37, 3))
+    s[:4] = [[0, 0, 0], [1, 0.5, 0.25], [0.125, 1.0 / 9, 0.1], [0.999999999, 0, 1]]
+    pts = s @ SKEW
+    b = ew.Blips(SKEW, grid, n_orb)
+    dev = "cuda"
+    c_t = torch.tensor(coef, device=dev)
+    p_t = torch.tensor(pts, device=dev)
+    val = torch.zeros((len(pts), n_orb), dtype=torch.float64, device=dev)
+    grad = torch.zeros((len(pts), 3, n_orb), dtype=torch.float64, device=dev)
+    lap = torch.zeros_like(val)
+    b.eval(c_t, p_t, val, grad, lap)
+    v_only = torch.zeros_like(val)
+    b.eval(c_t, p_t, v_only)
+    torch.cuda.synchronize()
+    rv, rg, rl = oracle_lib.blip_eval(SKEW, grid, coef, pts)
+    sv = max(1.0, float(np.max(np.abs(rv))))
+    sg = max(1.0, float(np.max(np.abs(rg))))
+    sl = max(1.0, float(np.max(np.abs(rl))))
+    assert np.max(np.abs(val.cpu().numpy() - rv)) <= 1e-12 * sv
+    assert np.array_equal(v_only.cpu().numpy(), val.cpu().numpy())
+    assert np.max(np.abs(grad.cpu().numpy() - rg)) <= 1e-12 * sg
+    assert np.max(np.abs(lap.cpu().numpy() - rl)) <= 1e-12 * sl
+    with pytest.raises(ew.EwaldError):
+        ew.ewald_blip_eval_batch(b.handle, c_t.data_ptr(), len(pts), p_t.data_ptr(), val.data_ptr(),
+                                 grad.data_ptr(), 0)
+    with pytest.raises(ew.EwaldError):
+        ew.Blips(SKEW, (3, 9, 10), 4)
+
+
+def test_blips_full_size_sampled(oracle_lib):
+    """The benchmarked blip workload (bcc N=1024 cell, 40^3 grid, 512
+    orbitals, 65536 proposal points in one call): sampled points against the
+    oracle."""
+    say("[blips full size]")
+    cfg = wl.config(5)
+    lat = cfg.systems[0].lattice
+    coef = wl.blip_coefficients()
+    pts = wl.blip_points(8192, 8)
+    dev = "cuda"
+    c_t = torch.tensor(coef, device=dev)
+    p_t = torch.tensor(pts, device=dev)
+    P, M = pts.shape[0], wl.BLIP_ORBITALS
+    val = torch.zeros((P, M), dtype=torch.float64, device=dev)
+    grad = torch.zeros((P, 3, M), dtype=torch.float64, device=dev)
+    lap = torch.zeros_like(val)
+    b = ew.Blips(lat, wl.BLIP_GRID, M)
+    b.eval(c_t, p_t, val, grad, lap)
+    torch.cuda.synchronize()
+    sample = np.array([0, 1, 4097, 32768, 65535, 12345])
+    rv, rg, rl = oracle_lib.blip_eval(lat, wl.BLIP_GRID, coef, pts[sample])
+    assert np.max(np.abs(val[sample].cpu().numpy() - rv)) <= 1e-12 * max(1.0, float(np.max(np.abs(rv))))
+    assert np.max(np.abs(grad[sample].cpu().numpy() - rg)) <= 1e-12 * max(1.0, float(np.max(np.abs(rg))))
+    assert np.max(np.abs(lap[sample].cpu().numpy() - rl)) <= 1e-12 * max(1.0, float(np.max(np.abs(rl))))
+    assert bool(torch.isfinite(val).all()) and bool(torch.isfinite(lap).all())
+
+
+
+# Layered two-dimensional systems (Eq. (5) with z != 0): the electron-hole
+# bilayer against the oracle's pair-by-pair energy; the fused call runs the
+# per-step kernels for such batches.
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_bilayer_energy_and_moves(oracle_lib, precision):
+    W, S, K = 3, 24, 4
+    say(f"[bilayer] precision={precision}")
+    out = {}
+    for path in ("per-step", "run_moves"):
+        c = Case(3, W, S, precision, refresh_every=K, jastrow=False, cfg=wl.bilayer_config())
+        e0, _ = c.run_energy()
+        if path == "run_moves":
+            assert c.batch.tuning()["fused"] == 0
+        out[path] = (e0,) + (c.per_step() if path == "per-step" else c.fused())
+        for w in range(W):
+            h = c.batch.walker_header(w)
+            acc = int(c.b.accept[:, w].sum())
+            assert h["n_accepts"] == acc
+            if precision == MIXED:
+                assert h["n_refresh"] == acc // K
+    for w in range(W):
+        sysw = c.system(w)
+        r = c.oracle(oracle_lib, w)
+        scale = max(abs(r["energy0"]), e_scale(sysw))
+        for path, (e0, d, _) in out.items():
+            if precision == FP64:
+                assert abs(e0[w] - r["energy0"]) <= 1e-10 * scale, (path, e0[w], r["energy0"])
+                assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale, path
+            else:
+                assert abs(e0[w] - r["energy0"]) <= 1e-6 * scale, path
+                assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5, path
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_layers_with_ions_and_telescoping(oracle_lib, precision):
+    """Two planes with fixed ions in the second one and unequal plane
+    populations (different plane charges, so the cross-plane background
+    term counts): energies, deltas, and E0 + accepted deltas against a fresh
+    energy of the final positions."""
+    say(f"[layers ions] precision={precision}")
+    base = wl.bilayer(6, 2.2)
+    ions = np.array([[3.0, 4.0], [40.0, 17.0], [20.0, 60.0]])
+    sysm = dataclasses.replace(base, n_mobile=9, mobile_q=np.array([-1.0] * 5 + [1.0] * 4),
+                               mobile_layer=np.array([0] * 5 + [1] * 4, dtype=np.int32),
+                               fixed_pos=ions, fixed_q=np.array([1.0, -0.5, 2.0]),
+                               fixed_layer=np.array([1, 1, 0], dtype=np.int32))
+    rng = np.random.default_rng(77)
+    lat = sysm.lattice[:2, :2]
+    W, S = 2, 16
+    pos = [rng.random((9, 2)) @ lat for _ in range(W)]
+    k = rng.integers(0, 9, (S, W)).astype(np.int32)
+    newp = np.stack([[pos[w][k[m, w]] + rng.normal(0, 4.0, 2) for w in range(W)] for m in range(S)])
+    acc = (rng.random((S, W)) < 0.6).astype(np.uint8)
+    h = ew.System(sysm, precision=precision, refresh_every=3 if precision == MIXED else 0)
+    b = ew.Batch([h], np.zeros(W, dtype=np.int32))
+    dev = "cuda"
+    e = torch.zeros(W, dtype=torch.float64, device=dev)
+    b.energy(torch.tensor(np.concatenate(pos), device=dev), e)
+    kt, nt, at = (torch.tensor(x, device=dev) for x in (k, newp, acc))
+    d = torch.zeros((S, W), dtype=torch.float64, device=dev)
+    for m in range(S):
+        b.move_delta(kt[m], nt[m], d[m])
+        b.accept(at[m])
+    torch.cuda.synchronize()
+    e0, dd = e.cpu().numpy(), d.cpu().numpy()
+    for w in range(W):
+        r = oracle_lib.run(sysm, pos[w], k[:, w], newp[:, w], acc[:, w])
+        scale = max(abs(r["energy0"]), e_scale(sysm))
+        tol_e = 1e-10 * scale if precision == FP64 else 1e-6 * scale
+        tol_d = 1e-10 * scale if precision == FP64 else 1e-5
+        assert abs(e0[w] - r["energy0"]) <= tol_e, (e0[w], r["energy0"])
+        assert np.max(np.abs(dd[:, w] - r["delta"])) <= tol_d
+        # telescoping against a fresh energy of the final positions
+        fin = b.walker_positions(w) @ lat
+        e_fin = oracle_lib.energy(sysm, *oracle_lib.particles(sysm, fin))["total"]
+        tel = e0[w] + float(np.sum(dd[acc[:, w].astype(bool), w]))
+        assert abs(tel - e_fin) <= (1e-10 * scale if precision == FP64 else 1e-6 * scale + 1e-5 * S)

@@ -503,7 +503,8 @@ def main():
     ap.add_argument("--next", default="derivs,u,blips,layers",
                     help="rows beyond the Ewald path also timed (jastrow derivatives, u term, blips); empty to skip")
     ap.add_argument("--skip-main", action="store_true",
-                    help="time only the smaller configurations (--other); prints their results, not the bench line")
+                    help="time only the smaller configurations (--other) and the blip and bilayer rows named in "
+                         "--next; prints their results, not the bench line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -531,6 +532,11 @@ def main():
             for form in args.forms.split(","):
                 prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
                 print(json.dumps(other_workload(cid, prec, threads=args.threads)), flush=True)
+        want = set(x for x in args.next.split(",") if x)
+        if "blips" in want:
+            print(json.dumps({"blips": blip_row()}), flush=True)
+        if "layers" in want:
+            print(json.dumps({"layers": layers_row(forms=tuple(args.forms.split(",")))}), flush=True)
         return
 
     cfg = wl.config(CFG_ID)

@@ -294,16 +294,22 @@ ewald_status ewald_run_moves_grad_batch(ewald_batch *b, void *state, int n_steps
  *   general_frame  1 = the general minimum-image reduction even when the
  *                  cell has an orthogonal-sublattice frame (ewald_sys_geometry);
  *                  applies to ewald_energy_batch as well
+ *   waves          waves per SIMD the 256-thread kernel is compiled for:
+ *                  0 or 2 = default (256 registers per lane, constants in
+ *                  vector registers), 3 or 4 = more workgroups per CU with the
+ *                  constants in scalar registers; 3 and 4 give E_ARG when the
+ *                  shape is not 256 threads
  * Results do not depend on the choice beyond rounding order.  Not to be
  * called concurrently with launches on the same batch. */
-ewald_status ewald_batch_set_tuning(ewald_batch *b, int threads, int chunk, int general_frame);
+ewald_status ewald_batch_set_tuning(ewald_batch *b, int threads, int chunk, int general_frame, int waves);
 
 /* The launch shape ewald_run_moves_batch will use: workgroup size, moves per
- * chunk, frame (1 = general), and fused = 0 when the walkers do not fit the
- * fused kernel's LDS layout (then it runs the per-step kernels in turn).
+ * chunk, frame (1 = general), fused = 0 when the walkers do not fit the
+ * fused kernel's LDS layout or are layered (then it runs the per-step
+ * kernels in turn), and the waves per SIMD of the kernel (0 when not fused).
  * Any output pointer may be NULL. */
 ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, int *general_frame,
-                                    int *fused);
+                                    int *fused, int *waves);
 
 /* The launch-shape choice that Sec. 3.3 makes by hand for each GPU (gang and
  * vector sizes), made by measurement: time every launch shape of

@@ -230,6 +230,15 @@ __device__ __forceinline__ void geo_pos(const double* s, const DevSys* __restric
   }
 }
 
+// A value every lane holds alike (read from LDS at a uniform address), made
+// visibly uniform for the compiler: scalar registers, and branches on it
+// stay branches (not per-lane selects).
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform_d(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+
 // Kahan-compensated FP32 accumulator.
 struct Kahan {
   float s = 0.f, c = 0.f;
@@ -536,7 +545,7 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
   const double dz2 = S->dz2;
   for (int j0 = threadIdx.x; j0 < n; j0 += PPR * NT) {
     double qq[2 * PPR], r2[2 * PPR], ir[2 * PPR];
-    double xn[UD ? PPR : 1][DIM];
+    double xn[UD ? PPR : 1][DIM] = {};  // zero for masked partners (their weight is zero too)
     bool okc[PPR];
     int sj[PPR];
 #pragma unroll
@@ -622,7 +631,7 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
   const double rc2 = S->rc2;
   {
     double qq[2 * PPR], r2[2 * PPR], ir[2 * PPR];
-    double xn[UD ? PPR : 1][DIM];
+    double xn[UD ? PPR : 1][DIM] = {};  // zero for masked partners (their weight is zero too)
     bool okc[PPR];
 #pragma unroll
     for (int c = 0; c < PPR; ++c) {
@@ -649,7 +658,7 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
   if (!XTRA) return pr.value();
   for (int j = threadIdx.x + PPR * NT; j < n; j += NT) {
     double qq[2], r2[2], ir[2];
-    double xn[DIM];
+    double xn[DIM] = {};
     const bool ok = j != k;
     double xj[DIM];
     geo_pos<DIM, ORTHO>(lpos + j * DIM, S, xj);

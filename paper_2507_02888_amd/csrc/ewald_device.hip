@@ -56,7 +56,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
   // pair loop's positions and charges
   double* red = smem;                        // [4 * 4]
   cplx<double>* tabs = reinterpret_cast<cplx<double>*>(smem + 16);
-  double* lpos = smem + 16;                  // [n][DIM] in the pair loop's geometry
+  double* lpos = smem + 16;                  // [DIM][lds_pos] in the pair loop's geometry (planar:
+                                             // lanes reading consecutive particles hit consecutive banks)
   double* lq = lpos + lds_pos * DIM;         // [n]
 
   const double* pw = pos + size_t(W.pos_off) * DIM;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
     for (int d = 0; d < DIM; ++d) sv[d] = spos[i * DIM + d];
     geo_pos<DIM, ORTHO>(sv, S, x);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) lpos[i * DIM + d] = x[d];
+    for (int d = 0; d < DIM; ++d) lpos[d * lds_pos + i] = x[d];
     lq[i] = S->mobile_q[i];
   }
   __syncthreads();
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
   for (int i = tid; i < n; i += BLOCK) {
     double si[DIM];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) si[d] = lpos[i * DIM + d];
+    for (int d = 0; d < DIM; ++d) si[d] = lpos[d * lds_pos + i];
     const double qi = lq[i];
     const int spi = UJ ? S->spin[i] : 0;
     const int li = i >= n0 ? 1 : 0;  // plane of particle i (layered systems)
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
         double sj[DIM];
         if (mob) {
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) sj[d] = lpos[j * DIM + d];
+          for (int d = 0; d < DIM; ++d) sj[d] = lpos[d * lds_pos + j];
         } else {
           geo_pos<DIM, ORTHO>(S->fixed_s + (fix ? m - n_mob : 0) * DIM, S, sj);
         }

@@ -1186,21 +1186,30 @@ ewald_status ewald_run_moves_batch(ewald_batch* b, void* state, int n_steps, con
   return ewald_run_moves_grad_batch(b, state, n_steps, k, new_pos, accept, delta, djastrow, nullptr, nullptr, stream);
 }
 
-ewald_status ewald_batch_set_tuning(ewald_batch* b, int threads, int chunk, int general_frame) {
+ewald_status ewald_batch_set_tuning(ewald_batch* b, int threads, int chunk, int general_frame, int waves) {
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (!run_threads_valid(b->lb.max_n_seg, threads))
     return fail(EWALD_E_ARG, "threads is not a fused-kernel workgroup size for this batch's segment count");
   if (chunk < 0 || chunk > RUN_CHUNK) return fail(EWALD_E_ARG, "chunk must be in [0, 64]");
   if (general_frame != 0 && general_frame != 1) return fail(EWALD_E_ARG, "general_frame must be 0 or 1");
+  if (waves != 0 && waves != 2 && waves != 3 && waves != 4) return fail(EWALD_E_ARG, "waves must be 0, 2, 3 or 4");
+  if (waves > 2) {  // only the 256-thread kernels come in these variants
+    LaunchBatch L = b->lb;
+    L.run_threads = threads;
+    RunPlan p{};
+    plan_run(L, &p);
+    if (p.threads != 256) return fail(EWALD_E_ARG, "waves 3 and 4 apply to 256-thread workgroups only");
+  }
   std::lock_guard<std::mutex> lk(b->mu);
   b->lb.run_threads = threads;
   b->lb.run_chunk = chunk;
   b->lb.general_frame = general_frame;
+  b->lb.run_waves = waves;
   return EWALD_OK;
 }
 
 ewald_status ewald_batch_get_tuning(ewald_batch* b, int* threads, int* chunk, int* general_frame,
-                                    int* fused) {
+                                    int* fused, int* waves) {
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   RunPlan p{};
   {
@@ -1211,6 +1220,7 @@ ewald_status ewald_batch_get_tuning(ewald_batch* b, int* threads, int* chunk, in
   if (chunk) *chunk = p.chunk;
   if (general_frame) *general_frame = p.fused ? p.general_frame : 1;
   if (fused) *fused = p.fused;
+  if (waves) *waves = p.fused ? p.waves : 0;
   return EWALD_OK;
 }
 
@@ -1228,7 +1238,7 @@ std::string tune_key(const ewald_batch* b) {
   return buf;
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* t, int* c, int* g) {
+bool cache_lookup(const char* path, const std::string& key, int* t, int* c, int* g, int* v) {
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char line[1024];
@@ -1237,7 +1247,7 @@ bool cache_lookup(const char* path, const std::string& key, int* t, int* c, int*
     std::string l(line);
     const size_t bar = l.find('|');
     if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-    found = std::sscanf(l.c_str() + bar + 1, "threads=%d chunk=%d general_frame=%d", t, c, g) == 3;
+    found = std::sscanf(l.c_str() + bar + 1, "threads=%d chunk=%d general_frame=%d waves=%d", t, c, g, v) == 4;
   }
   std::fclose(f);
   return found;
@@ -1252,8 +1262,8 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   ewald_status st = check_state(b, state, 3, -1);
   if (st != EWALD_OK) return st;
   const std::string key = tune_key(b);
-  int t = 0, c = 0, g = 0;
-  if (cache_path && cache_lookup(cache_path, key, &t, &c, &g)) return ewald_batch_set_tuning(b, t, c, g);
+  int t = 0, c = 0, g = 0, v = 0;
+  if (cache_path && cache_lookup(cache_path, key, &t, &c, &g, &v)) return ewald_batch_set_tuning(b, t, c, g, v);
   // probe: proposals spread over each cell, every other move accepted, run on
   // a copy of the walkers' state (which is left as it was)
   const int W = b->lb.n_walkers, dim = b->lb.dim;
@@ -1300,7 +1310,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   }
   // candidates: every workgroup shape for the segment count, chunk sizes, both frames
   struct Cand {
-    int threads, chunk, general;
+    int threads, chunk, general, waves;
     float ms;
   };
   std::vector<Cand> cands;
@@ -1310,6 +1320,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
     L.run_threads = c.threads;
     L.run_chunk = c.chunk;
     L.general_frame = c.general;
+    L.run_waves = c.waves;
     float ms = 0.f;
     const int r = time_run(L, static_cast<char*>(ds), n_moves, static_cast<int32_t*>(dk), static_cast<double*>(dp),
                            static_cast<uint8_t*>(da), static_cast<double*>(dd), stream, reps, &ms);
@@ -1318,6 +1329,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   };
   for (int threads : {256, 512, 1024}) {
     if (!run_threads_valid(b->lb.max_n_seg, threads)) continue;
+    for (int waves : {2, 3, 4})
     for (int chunk : {0, 32, 16})
       for (int general : {0, 1}) {
         if (general == 0 && !b->lb.all_ortho) continue;
@@ -1325,10 +1337,11 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
         L.run_threads = threads;
         L.run_chunk = chunk;
         L.general_frame = general;
+        L.run_waves = waves;
         RunPlan p{};
         plan_run(L, &p);
-        if (!p.fused) continue;
-        cands.push_back({threads, chunk, general, -1.f});
+        if (!p.fused || (waves > 2 && p.threads != 256)) continue;
+        cands.push_back({threads, chunk, general, waves, -1.f});
         rc = probe(cands.back(), 2);
         if (rc) {
           release();
@@ -1354,13 +1367,14 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   std::stable_sort(cands.begin(), cands.begin() + n_close, by_time);
   const float best = cands.empty() ? -1.f : cands[0].ms;
   const int bt = cands.empty() ? 0 : cands[0].threads, bc = cands.empty() ? 0 : cands[0].chunk,
-            bg = cands.empty() ? 0 : cands[0].general;
+            bg = cands.empty() ? 0 : cands[0].general, bv = cands.empty() ? 0 : cands[0].waves;
   release();
   if (best < 0.f) return EWALD_OK;  // the fused kernel does not fit: nothing to tune
-  st = ewald_batch_set_tuning(b, bt, bc, bg);
+  st = ewald_batch_set_tuning(b, bt, bc, bg, bv);
   if (st != EWALD_OK || !cache_path) return st;
   if (FILE* f = std::fopen(cache_path, "a")) {
-    std::fprintf(f, "%s|threads=%d chunk=%d general_frame=%d ms=%.4f\n", key.c_str(), bt, bc, bg, double(best));
+    std::fprintf(f, "%s|threads=%d chunk=%d general_frame=%d waves=%d ms=%.4f\n", key.c_str(), bt, bc, bg, bv,
+                 double(best));
     std::fclose(f);
   }
   return EWALD_OK;

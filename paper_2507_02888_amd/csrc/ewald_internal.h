@@ -170,6 +170,7 @@ struct LaunchBatch {
   int all_wtab_lds;         // every system's shell table fits in LDS
   int all_ortho;            // every system has an orthogonal-sublattice frame (DevSys::ortho)
   int run_threads;          // fused kernel: workgroup size (0: default for the segment count)
+  int run_waves;            // fused kernel, 256 threads: waves per SIMD it is compiled for (0: 2)
   int run_chunk;            // fused kernel: moves per chunk (0: as many as LDS allows, <= RUN_CHUNK)
   int general_frame;        // fused kernel: 1 = general minimum-image reduction even if all_ortho
 };
@@ -185,6 +186,7 @@ struct RunPlan {
   int general_frame;  // 1 = general minimum-image reduction
   int lds_bytes;
   int blocks_per_cu;  // workgroups per CU allowed by registers
+  int waves;          // waves per SIMD the kernel is compiled for (registers per lane = 512 / waves)
 };
 
 // Each returns 0 on success or the hipError_t of the failed launch.

@@ -42,14 +42,19 @@ struct RunLds {
 // At least two waves per SIMD for workgroups of up to 512 threads (the
 // register budget stays within 256 per lane; without the bound the compiler
 // may take accumulation registers as well, which leaves one wave per SIMD).
+// WV: the waves per SIMD a 256-thread kernel is bounded to (2, 3 or 4; 512 /
+// WV registers per lane): small walkers may run more workgroups per CU with
+// the pair-potential constants in scalar registers (WV > 2) than with them
+// in vector registers (WV = 2); which wins depends on the batch, so the
+// autotuner measures it.
 // JM: Jastrow mode, 0 = none, 1 = J and dJ, 2 = also the gradient and the
 // Laplacian of J with respect to the moved particle at each proposed
 // configuration (as in k_delta: accumulated as S_d = sum_H a n_d Im z and
 // sum_H a |G|^2 Re z, z = conj(rho') e'); 3 and 4 = 1 and 2 with the
 // two-body polynomial term u of the mobile pairs added (its gradient summed
 // in the geometry's frame axes, turned Cartesian once per move).
-template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA>
-__global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __restrict__ systems,
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA, int WV = 2>
+__global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
                                             const double* __restrict__ new_pos, const uint8_t* __restrict__ accept,
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
   // that leaves the scalar registers to the loop state, which otherwise
   // spills into vector-register lanes.  With 1024 threads they stay scalar.
   constexpr int PF = PD == 16 ? 12 : 22;
-  constexpr bool CV = NT <= 512;
+  constexpr bool CV = NT <= 512 && WV <= 2;
   double cf64[CV ? PD + 1 : 1];
   float cf32[CV ? PF + 1 : 1];
   if (CV) {
@@ -219,14 +224,14 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
 
     // ---- the chunk's moves, no barrier ----
     for (int mm = 0; mm < len; ++mm) {
-      const int k = st_k[mm];
+      const int k = uniform_i(st_k[mm]);  // the move's index, decision and charge are uniform
       double v0 = 0.0, v1 = 0.0;
       double dv[DER ? NDV : 1];  // DER: this thread's S_d and a |G|^2 Re z sums
 #pragma unroll
       for (int d = 0; d < (DER ? NDV : 1); ++d) dv[d] = 0.0;
       if (k >= 0) {  // uniform
-        const bool acc = st_acc[mm] != 0;
-        const double qk = lq[k];
+        const bool acc = uniform_i(st_acc[mm]) != 0;
+        const double qk = uniform_d(lq[k]);
         double sn[DIM], xn[DIM], xo[DIM];  // new (fractional), new and old in the real-space geometry
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -239,7 +244,8 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
           const cplx<R>* tn = to + DIM * tbl;
           const cplx<R> uo = tab_at(to, DIM - 1, nm + 1, tbl), un = tab_at(tn, DIM - 1, nm + 1, tbl);
           // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)], q^2 applied to the sums
-          const R q = R(qk), c2q = R(st_c2q[mm]);
+          const R q = R(qk), c2q = R(uniform_d(st_c2q[mm]));
+          const R qa = acc ? q : R(0);
           double accE64 = 0.0, accJ64 = 0.0;
           Kahan accE32, accJ32;  // mixed form: FP32 sums per segment, compensated across segments
 #pragma unroll
@@ -272,10 +278,11 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : 2) void k_run(const DevSys* __
                   sT2 = fma(R(j), ti, sT2);
                   sL = fma(R(ag2), re, sL);
                 }
-                if (acc) {
-                  rv[i][j].x += double(q * dx);
-                  rv[i][j].y += double(q * dy);
-                }
+                // rho += q d on an accepted move: the charge times the uniform
+                // decision (0 when rejected, which adds an exact zero) instead
+                // of a branch the compiler would turn into per-lane selects
+                rv[i][j].x += double(qa * dx);
+                rv[i][j].y += double(qa * dy);
                 if (j + 1 < SEG) {
                   wo.step(j);
                   wn.step(j);
@@ -533,9 +540,9 @@ struct RunArgs {
   RunPlan* plan;  // non-null: resolve the launch shape only, launch nothing
 };
 
-template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA>
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA, int WV = 2>
 int run_inst(const LaunchBatch& b, const RunArgs& a) {
-  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, XTRA>;
+  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, XTRA, WV>;
   constexpr bool DER = JM == 2 || JM == 4, UJ = JM >= 3;
   static const int per_cu = blocks_per_cu(kern, NT);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
@@ -547,7 +554,7 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
   while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT, SPT, DER, UJ>(b, --ch, L);
   if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
   if (a.plan) {
-    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu};
+    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu, NT >= 1024 ? 4 : WV};
     return 0;
   }
   if (int rc = allow_lds(kern, lds)) return rc;
@@ -597,8 +604,13 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   // 256-thread kernels keep them (without them the compiler spends more
   // registers there and runs slower).
   const bool xtra = b.max_particles > ppr * nt || b.max_fixed > 0;
-#define EW_RUN(NT, SPT, PPR) \
-  if (nt == NT && spt == SPT && ppr == PPR) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true>(b, a)
+  const int wv = b.run_waves > 0 ? b.run_waves : 2;
+#define EW_RUN(NT, SPT, PPR)                                                                             \
+  if (nt == NT && spt == SPT && ppr == PPR) {                                                           \
+    if (wv == 3) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 3>(b, a);               \
+    if (wv == 4) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 4>(b, a);               \
+    return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true>(b, a);                               \
+  }
 #define EW_RUN_X(NT, SPT, PPR)                                                                          \
   if (nt == NT && spt == SPT && ppr == PPR)                                                            \
     return xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true>(b, a)                       \

@@ -502,6 +502,8 @@ def test_tuning_shapes_agree(precision):
         ref.batch.set_tuning(threads=256)  # not a shape for 990 segments
     with pytest.raises(ew.EwaldError):
         ref.batch.set_tuning(chunk=65)
+    with pytest.raises(ew.EwaldError):
+        ref.batch.set_tuning(threads=512, waves=4)  # the wave variants are 256-thread kernels
 
 
 @pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
@@ -670,22 +672,23 @@ def test_uneven_batch_fused_vs_oracle(oracle_lib, precision):
 @pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("cfg_id", [2, 3, 4])
 def test_small_walker_shapes_vs_oracle(oracle_lib, cfg_id, precision):
-    """Both workgroup sizes available to the smaller workloads (308 or 28
+    """Every launch shape available to the smaller workloads (308 or 28
     segments; 250, 300 or 64/216/512 particles plus ions): 256 threads (two
-    particles per lane where needed, plus the ion loop) and 1024 threads
-    (most lanes idle), through the fused sweep against the oracle: deltas,
-    Jastrow deltas and the mixed form's rebuild counts at K=4."""
+    particles per lane where needed, plus the ion loop) compiled for 2, 3 and
+    4 waves per SIMD, and 1024 threads (most lanes idle), through the fused
+    sweep against the oracle: deltas, Jastrow deltas and the mixed form's
+    rebuild counts at K=4."""
     W = 6 if cfg_id == 4 else 3
     S, K = 16, 4
     refs = None
-    for threads in (256, 1024):
-        say(f"[small shapes] cfg={cfg_id} precision={precision} threads={threads}")
+    for threads, waves in ((256, 2), (256, 3), (256, 4), (1024, 0)):
+        say(f"[small shapes] cfg={cfg_id} precision={precision} threads={threads} waves={waves}")
         c = Case(cfg_id, W, S, precision, refresh_every=K)
         if refs is None:
             refs = [c.oracle(oracle_lib, w) for w in range(W)]
-        c.batch.set_tuning(threads=threads)
+        c.batch.set_tuning(threads=threads, waves=waves)
         t = c.batch.tuning()
-        assert t["fused"] == 1 and t["threads"] == threads
+        assert t["fused"] == 1 and t["threads"] == threads and t["waves"] == (waves or 4)
         e0, _ = c.run_energy()
         d, dj = c.fused()
         for w in range(W):

@@ -308,11 +308,14 @@ def next_rows(cfg, b, t, K: int, forms=("mixed", "fp64")):
 
 def layers_row(forms=("mixed", "fp64"), steps: int = 2):
     """The electron-hole bilayer (two planes, Eq. (5) with z != 0; 2048
-    walkers x 512 moves): ewald_run_moves_batch, which runs the per-step
-    delta and accept kernels for layered batches.  deltas/s and the per-step
-    kernels' fraction of HBM bandwidth by their algorithmic bytes per move
-    (both planes' rho and the positions read by the delta, the moved plane's
-    rho read and written by an accepted move)."""
+    walkers x 512 moves): ewald_run_moves_batch (the fused kernel with a
+    second plane in registers, autotuned), deltas/s and its VALU fraction by
+    the algorithmic count of the move (36 flops per G plus 5 for the
+    cross-plane term, a dot product and a weighted add; 55 per pair evaluation) and of the mixed form's
+    rebuilds; and the per-step path (move_delta + accept per call) for
+    comparison, with its HBM fraction by the bytes it streams per move (both
+    planes' rho and the positions read by the delta, the moved plane's rho
+    read and written by an accepted move)."""
     import torch
     from paper_2507_02888_amd import ewald as ew
     from paper_2507_02888_amd import workloads as wl
@@ -326,22 +329,44 @@ def layers_row(forms=("mixed", "fp64"), steps: int = 2):
     out = {}
     for form in forms:
         prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
-        h = ew.System(sm, precision=prec, refresh_every=cfg.refresh_every if form == "mixed" else 0)
+        K = cfg.refresh_every if form == "mixed" else 0
+        h = ew.System(sm, precision=prec, refresh_every=K)
         batch = ew.Batch([h], b.walker_sys, device=dev)
+        e = torch.zeros(W, dtype=torch.float64, device=dev)
+        batch.energy(t["pos"], e)
+        batch.autotune(n_moves=max(64, 2 * K) if K else 64)
         delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
         ms = timed_sweep(batch, t, delta, None, reps=steps)
+        n_g, n = h.info["n_g"], sm.n_mobile
+        n_ref = int(np.sum(b.accept.sum(axis=0) // K)) if K else 0
+        flops = W * S * (n_g * (FLOP_PER_G_DELTA + 5) + 2 * (n - 1) * FLOP_PER_PAIR_DELTA) + \
+            n_ref * algorithmic_flops_per_rebuild(n_g, n)
+        # per-step path over a few moves
+        batch.energy(t["pos"], e)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n_ps = 16
+        e0.record(stream)
+        for m in range(n_ps):
+            batch.move_delta(t["k"][m], t["new_pos"][m], delta[m])
+            batch.accept(t["accept"][m])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ps_ms = e0.elapsed_time(e1) / n_ps
         slots = h.info["n_slots"]
         p_acc = float(b.accept.mean())
-        bytes_per_move = 2 * 16 * slots + 8 * 2 * sm.n_mobile + p_acc * 2 * 16 * slots
-        gbs = W * S * bytes_per_move / (ms * 1e-3) / 1e9
+        bytes_per_move = 2 * 16 * slots + 8 * 2 * n + p_acc * 2 * 16 * slots
+        gbs = W * bytes_per_move / (ps_ms * 1e-3) / 1e9
         out[form] = dict(run_deltas_per_s=round(W * S / (ms * 1e-3), 1), launch_ms=round(ms, 4),
-                         roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                                       frac=round(gbs / PEAK_HBM_GBS, 4), bytes_per_move=round(bytes_per_move, 1)),
-                         fused=batch.tuning()["fused"])
+                         frac=round(flops / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4), launch_shape=batch.tuning(),
+                         per_step_deltas_per_s=round(W / (ps_ms * 1e-3), 1),
+                         per_step_roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                                                frac=round(gbs / PEAK_HBM_GBS, 4),
+                                                bytes_per_move=round(bytes_per_move, 1)))
         batch.close()
         h.close()
-    out["call"] = ("ewald_run_moves_batch on the electron-hole bilayer (150 + 150 particles, d = 5 bohr), "
-                   "per-step kernels; the state (17 MB) stays in the last-level cache")
+    out["call"] = ("ewald_run_moves_batch on the electron-hole bilayer (150 + 150 particles, d = 5 bohr), fused "
+                   "kernel with both planes' rho in registers; per-step path beside it")
     return out
 
 

@@ -305,8 +305,10 @@ ewald_status ewald_batch_set_tuning(ewald_batch *b, int threads, int chunk, int 
 
 /* The launch shape ewald_run_moves_batch will use: workgroup size, moves per
  * chunk, frame (1 = general), fused = 0 when the walkers do not fit the
- * fused kernel's LDS layout or are layered (then it runs the per-step
- * kernels in turn), and the waves per SIMD of the kernel (0 when not fused).
+ * fused kernel's LDS layout (then it runs the per-step
+ * kernels in turn), and the waves per SIMD a 256-thread kernel is compiled
+ * for (0 for the other workgroup sizes and when not fused), so that the
+ * values can be passed back to ewald_batch_set_tuning.
  * Any output pointer may be NULL. */
 ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, int *general_frame,
                                     int *fused, int *waves);

@@ -198,6 +198,15 @@ __device__ __forceinline__ double min_r2_ortho(const double* a, const double* b,
   return fmin(r0sq, t);
 }
 
+// A reference to one of two arrays chosen at compile time.
+template <bool B, typename A, typename C>
+__device__ __forceinline__ auto& pick_ref(A& a, C& c) {
+  if constexpr (B)
+    return c;
+  else
+    return a;
+}
+
 // Coordinates of a fractional position in the orthogonal-sublattice frame.
 template <int DIM>
 __device__ __forceinline__ void frame_coords(const double* s, const DevSys* __restrict__ S, double* x) {
@@ -618,17 +627,22 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
 // labels of the thread's own particles, sk: the moved particle's); UD: with
 // its gradient (in the geometry's frame axes) and Laplacian at the new
 // position.
-template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO, bool XTRA, bool UJ = false, bool UD = false>
+// LAY (a layered system when `lay`): partners in the other plane (mobile
+// j >= n0 against k, or an ion's plane) are dz2 further apart in r^2.
+template <int DIM, bool MIXED, int PD, int NT, int PPR, bool ORTHO, bool XTRA, bool UJ = false, bool UD = false,
+          bool LAY = false>
 __device__ __forceinline__ double real_move_own(const double* sn, const double* so, int k,
                                                 const double (&ps)[PPR][DIM], const double (&pq)[PPR],
                                                 const double* lpos, const double* lq, int n,
                                                 const DevSys* __restrict__ S, const double* c64,
                                                 const float* c32, const FrameK& K,
                                                 const int* psp = nullptr, int sk = 0,
-                                                UOut<DIM>* uo = nullptr) {
+                                                UOut<DIM>* uo = nullptr, bool lay = false, int n0 = 0,
+                                                double dz2 = 0.0) {
   PairAcc<MIXED, PD> pr(c64, c32, K);
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
+  const int lk = k >= n0 ? 1 : 0;
   {
     double qq[2 * PPR], r2[2 * PPR], ir[2 * PPR];
     double xn[UD ? PPR : 1][DIM] = {};  // zero for masked partners (their weight is zero too)
@@ -642,6 +656,10 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
       else
         r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, ps[c], S, n_cand, K) : rc2;
       r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, ps[c], S, n_cand, K) : rc2;
+      if (LAY && lay && ok && (j >= n0 ? 1 : 0) != lk) {
+        r2[2 * c] += dz2;
+        r2[2 * c + 1] += dz2;
+      }
       qq[2 * c] = pq[c];
       qq[2 * c + 1] = -pq[c];
       okc[c] = ok;
@@ -667,6 +685,10 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
     else
       r2[0] = ok ? image_r2<DIM, ORTHO>(sn, xj, S, n_cand, K) : rc2;
     r2[1] = ok ? image_r2<DIM, ORTHO>(so, xj, S, n_cand, K) : rc2;
+    if (LAY && lay && ok && (j >= n0 ? 1 : 0) != lk) {
+      r2[0] += dz2;
+      r2[1] += dz2;
+    }
     qq[0] = lq[j];
     qq[1] = -lq[j];
     ir[0] = rsqrt_pos(r2[0]);
@@ -687,6 +709,10 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
       const double qj = ok ? S->fixed_q[jj] : 0.0;
       r2[2 * c] = ok ? image_r2<DIM, ORTHO>(sn, sj, S, n_cand, K) : rc2;
       r2[2 * c + 1] = ok ? image_r2<DIM, ORTHO>(so, sj, S, n_cand, K) : rc2;
+      if (LAY && lay && ok && S->fixed_layer[jj] != lk) {
+        r2[2 * c] += dz2;
+        r2[2 * c + 1] += dz2;
+      }
       qq[2 * c] = qj;
       qq[2 * c + 1] = -qj;
     }

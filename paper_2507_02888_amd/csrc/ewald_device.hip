@@ -656,8 +656,7 @@ int accept_dim(const LaunchBatch& b, char* state, const uint8_t* accept, void* s
 
 
 int run_any(const LaunchBatch& b, const RunArgs& a) {
-  // layered systems run their sweeps through the per-step kernels
-  if (!b.all_wtab_lds || b.layered) return RUN_NO_FIT;
+  if (!b.all_wtab_lds) return RUN_NO_FIT;
   const int jm = b.has_jastrow == 0 ? 0 : a.jgrad ? 2 : 1;
   if (b.has_u) {  // the u term comes with Jastrow outputs (JM 3, 4)
     if (b.dim == 3) {

@@ -939,6 +939,14 @@ ewald_status upload_sys(ewald_sys* s, int device) {
     const int sh = s->shell[g];
     if (sh >= 0) jg2[size_t(sh)] = s->ja[g] * s->shell_g2[size_t(sh)];
   }
+  // cross-plane weight per shell (layered systems)
+  std::vector<double> wxt;
+  if (!s->wx.empty()) {
+    wxt.assign(size_t(n_wtab), 0.0);
+    for (size_t g = 0; g < ns; ++g)
+      if (s->shell[g] >= 0) wxt[size_t(s->shell[g])] = s->wx[g];
+  }
+  const size_t o_wxt = take(std::max<size_t>(1, wxt.size()) * 8);
   const size_t o_wa = take(wa.size() * 8);
   const size_t o_jg = take(jg2.size() * 8);
   const size_t o_sl = take(sl.size() * 2);
@@ -952,6 +960,7 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   std::memcpy(host.data() + o_mq, s->mobile_q.data(), s->mobile_q.size() * 8);
   if (!s->spin.empty()) std::memcpy(host.data() + o_sp, s->spin.data(), s->spin.size() * 4);
   if (!s->wx.empty()) std::memcpy(host.data() + o_wx, s->wx.data(), s->wx.size() * 8);
+  if (!wxt.empty()) std::memcpy(host.data() + o_wxt, wxt.data(), wxt.size() * 8);
   if (!s->rho_fix1.empty()) std::memcpy(host.data() + o_rf1, s->rho_fix1.data(), s->rho_fix1.size() * 8);
   if (!s->fixed_layer.empty()) std::memcpy(host.data() + o_fl, s->fixed_layer.data(), s->fixed_layer.size() * 4);
   std::memcpy(host.data() + o_wa, wa.data(), wa.size() * 8);
@@ -976,6 +985,7 @@ ewald_status upload_sys(ewald_sys* s, int device) {
   D.mobile_q = reinterpret_cast<const double*>(base + o_mq);
   D.spin = s->spin.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + o_sp);
   D.wx = s->wx.empty() ? nullptr : reinterpret_cast<const double*>(base + o_wx);
+  D.wx_tab = wxt.empty() ? nullptr : reinterpret_cast<const double*>(base + o_wxt);
   D.rho_fix1 = s->rho_fix1.empty() ? nullptr : reinterpret_cast<const double*>(base + o_rf1);
   D.fixed_layer = s->fixed_layer.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + o_fl);
   D.wa_tab = reinterpret_cast<const double*>(base + o_wa);

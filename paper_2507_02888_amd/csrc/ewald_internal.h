@@ -100,6 +100,7 @@ struct DevSys {
   int n0;
   double dz2;
   const double* wx;
+  const double* wx_tab;   // [n_wtab] the cross-plane weight per shell (0 for padding)
   const double* rho_fix1;
   const int32_t* fixed_layer;
   // erf(alpha r)/(alpha r) = sum_i p64[i] t^i for r < r_cut (p32: FP32 copy of lower accuracy)
@@ -159,7 +160,7 @@ struct LaunchBatch {
   int mixed;
   int has_jastrow;          // any system with Jastrow coefficients or a u term
   int has_u;                // any system with a Jastrow u term
-  int layered;              // any layered 2D system (the per-step kernels serve the sweep)
+  int layered;              // any layered 2D system (the fused kernels with a second plane serve the sweep)
   int max_n_seg;
   int max_nm;
   int max_particles;        // max n_mobile over systems
@@ -186,7 +187,8 @@ struct RunPlan {
   int general_frame;  // 1 = general minimum-image reduction
   int lds_bytes;
   int blocks_per_cu;  // workgroups per CU allowed by registers
-  int waves;          // waves per SIMD the kernel is compiled for (registers per lane = 512 / waves)
+  int waves;          // 256 threads: waves per SIMD the kernel is compiled for (512 / waves registers
+                      // per lane); 0 for the other shapes (their bound is fixed)
 };
 
 // Each returns 0 on success or the hipError_t of the failed launch.

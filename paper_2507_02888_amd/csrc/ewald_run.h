@@ -53,7 +53,13 @@ struct RunLds {
 // sum_H a |G|^2 Re z, z = conj(rho') e'); 3 and 4 = 1 and 2 with the
 // two-body polynomial term u of the mobile pairs added (its gradient summed
 // in the geometry's frame axes, turned Cartesian once per move).
-template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA, int WV = 2>
+// LAY: layered 2D systems (two planes, no Jastrow terms): the second
+// plane's rho in registers too, the cross-plane term 2 q sum_H w_x (rho_o . d)
+// with w_x in the shell table's second column, real-space partners in the
+// other plane sqrt(r^2 + dz^2) apart.  Walkers of a one-plane system run in
+// such a kernel with an empty second plane.
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA, int WV = 2,
+          bool LAY = false>
 __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
@@ -102,9 +108,12 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
   for (int i = tid; i < n; i += NT) lq[i] = S->mobile_q[i];
   // every system of the batch has its shell table in LDS (checked by the launcher)
   for (int i = tid; i < S->n_wtab; i += NT) {
-    ltab[i] = {WT(S->wa_tab[2 * i]), WT(S->wa_tab[2 * i + 1])};
+    ltab[i] = {WT(S->wa_tab[2 * i]), WT(LAY ? (S->wx_tab ? S->wx_tab[i] : 0.0) : S->wa_tab[2 * i + 1])};
     if (DER) ltab2[i] = WT(S->jg2_tab[i]);
   }
+  const bool lay = LAY && S->n_layers > 1;  // uniform
+  const int n0 = LAY ? S->n0 : n;
+  double* rho1 = rho + 2 * size_t(SEG) * nseg;  // the second plane (LAY)
   int counter = hdr->counter;
   int n_acc = hdr->n_accepts, n_ref = hdr->n_refresh;
   double drift = hdr->drift_max;
@@ -145,6 +154,7 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
   if (CV) fk = frame_k_vector(S);
   uint32_t an[SPT];
   cplx<double> rv[SPT][SEG];
+  cplx<double> rv2[LAY ? SPT : 1][SEG];  // LAY: the second plane
   uint32_t shp[SPT][SEG / 2];  // two 16-bit shell-table byte offsets per register
 #pragma unroll
   for (int i = 0; i < SPT; ++i) {
@@ -154,6 +164,8 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
     for (int j = 0; j < SEG; ++j) {
       const size_t g = size_t(j) * nseg + s;
       rv[i][j] = s < nseg ? cplx<double>{rho[2 * g], rho[2 * g + 1]} : cplx<double>{0.0, 0.0};
+      if constexpr (LAY)
+        rv2[i][j] = (lay && s < nseg) ? cplx<double>{rho1[2 * g], rho1[2 * g + 1]} : cplx<double>{0.0, 0.0};
     }
 #pragma unroll
     for (int j = 0; j < SEG; j += 2) {
@@ -246,8 +258,56 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
           // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)], q^2 applied to the sums
           const R q = R(qk), c2q = R(uniform_d(st_c2q[mm]));
           const R qa = acc ? q : R(0);
-          double accE64 = 0.0, accJ64 = 0.0;
-          Kahan accE32, accJ32;  // mixed form: FP32 sums per segment, compensated across segments
+          double accE64 = 0.0, accJ64 = 0.0, accX64 = 0.0;
+          Kahan accE32, accJ32, accX32;  // mixed form: FP32 sums per segment, compensated across segments
+          if constexpr (LAY) {
+            // own plane own[], other plane oth[]: the term as below plus the
+            // cross-plane sum w_x (rho_o . d); one copy of the loop per plane
+            // of the moved particle (uniform), so no per-lane selects
+            auto lay_loop = [&](auto own2) {
+              constexpr bool O2 = decltype(own2)::value;
+              auto& own = pick_ref<O2>(rv, rv2);
+              auto& oth = pick_ref<!O2>(rv, rv2);
+#pragma unroll
+              for (int i = 0; i < SPT; ++i) {
+                if (tid + i * NT < nseg) {
+                  SegWalk<R> wo(anchor<DIM, R>(to, an[i], nm), uo), wn(anchor<DIM, R>(tn, an[i], nm), un);
+                  float segE = 0.f, segX = 0.f;
+#pragma unroll
+                  for (int j = 0; j < SEG; ++j) {
+                    const cplx<R> eo = wo.cur, en = wn.cur;
+                    const uint32_t off = (shp[i][j >> 1] >> (16 * (j & 1))) & 0xffffu;
+                    const WT2 wa = ld_at_byte(ltab, off);  // (w, w_x)
+                    const R dx = en.x - eo.x, dy = en.y - eo.y;
+                    const R ux = fma(c2q, R(own[i][j].x), dx), uy = fma(c2q, R(own[i][j].y), dy);
+                    const R t = fma(ux, dx, uy * dy);
+                    const R xo = fma(R(oth[i][j].x), dx, R(oth[i][j].y) * dy);
+                    if (MIXED) {
+                      segE = fmaf(float(wa.x), float(t), segE);
+                      segX = fmaf(float(wa.y), float(xo), segX);
+                    } else {
+                      accE64 = fma(double(wa.x), double(t), accE64);
+                      accX64 = fma(double(wa.y), double(xo), accX64);
+                    }
+                    own[i][j].x += double(qa * dx);
+                    own[i][j].y += double(qa * dy);
+                    if (j + 1 < SEG) {
+                      wo.step(j);
+                      wn.step(j);
+                    }
+                  }
+                  if (MIXED) {
+                    accE32.add(segE);
+                    accX32.add(segX);
+                  }
+                }
+              }
+            };
+            if (k >= n0)
+              lay_loop(std::true_type{});
+            else
+              lay_loop(std::false_type{});
+          } else {
 #pragma unroll
           for (int i = 0; i < SPT; ++i) {
             if (tid + i * NT < nseg) {
@@ -300,12 +360,15 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
               }
             }
           }
+          }
           const double q2 = qk * qk;
           v0 = q2 * (MIXED ? accE32.value() : accE64);
+          if (LAY) v0 += 2.0 * qk * (MIXED ? accX32.value() : accX64);
           if (JAS) v1 = q2 * (MIXED ? accJ32.value() : accJ64);
           if (!UJ)
-            v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO, XTRA>(xn, xo, k, ps, pq, lpos, lq, n, S, c64,
-                                                                       c32, CV ? fk : frame_k(S));
+            v0 += qk * real_move_own<DIM, MIXED, PD, NT, PPR, ORTHO, XTRA, false, false, LAY>(
+                           xn, xo, k, ps, pq, lpos, lq, n, S, c64, c32, CV ? fk : frame_k(S), nullptr, 0, nullptr,
+                           lay, n0, LAY ? S->dz2 : 0.0);
         }
         if (UJ) {  // the u term moves with a neutral particle too
           UOut<DIM> uo;
@@ -411,8 +474,41 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
             }
           }
       }
-      rebuild_rho<DIM, SPT, NT>(rv, an, tid, S, lpos, lq, n, tabs, L.rtile);
+      if constexpr (LAY) {
+        // a layered walker: the second plane's running rho kept in its state
+        // block, each plane rebuilt from its own particles and ions
+        if (lay) {
+#pragma unroll
+          for (int i = 0; i < SPT; ++i) {
+            const int s = tid + i * NT;
+            if (s < nseg)
+#pragma unroll
+              for (int j = 0; j < SEG; ++j) {
+                const size_t g = size_t(j) * nseg + s;
+                rho1[2 * g] = rv2[i][j].x;
+                rho1[2 * g + 1] = rv2[i][j].y;
+              }
+          }
+          rebuild_rho<DIM, SPT, NT>(rv2, an, tid, S, lpos + size_t(n0) * DIM, lq + n0, n - n0, tabs, L.rtile,
+                                    S->rho_fix1);
+        }
+      }
+      rebuild_rho<DIM, SPT, NT>(rv, an, tid, S, lpos, lq, n0, tabs, L.rtile);
       double dm = 0.0;
+      if constexpr (LAY) {
+        if (lay) {
+#pragma unroll
+          for (int i = 0; i < SPT; ++i) {
+            const int s = tid + i * NT;
+            if (s < nseg)
+#pragma unroll
+              for (int j = 0; j < SEG; ++j) {
+                const size_t g = size_t(j) * nseg + s;
+                dm = fmax(dm, fmax(fabs(rv2[i][j].x - rho1[2 * g]), fabs(rv2[i][j].y - rho1[2 * g + 1])));
+              }
+          }
+        }
+      }
 #pragma unroll
       for (int i = 0; i < SPT; ++i) {
         const int s = tid + i * NT;
@@ -450,6 +546,12 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
         const size_t g = size_t(j) * nseg + s;
         rho[2 * g] = rv[i][j].x;
         rho[2 * g + 1] = rv[i][j].y;
+        if constexpr (LAY) {
+          if (lay) {
+            rho1[2 * g] = rv2[i][j].x;
+            rho1[2 * g + 1] = rv2[i][j].y;
+          }
+        }
       }
   }
   for (int i = tid; i < n * DIM; i += NT) spos[i] = lpos[i];
@@ -540,9 +642,10 @@ struct RunArgs {
   RunPlan* plan;  // non-null: resolve the launch shape only, launch nothing
 };
 
-template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA, int WV = 2>
+template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA, int WV = 2,
+          bool LAY = false>
 int run_inst(const LaunchBatch& b, const RunArgs& a) {
-  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, XTRA, WV>;
+  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, XTRA, WV, LAY>;
   constexpr bool DER = JM == 2 || JM == 4, UJ = JM >= 3;
   static const int per_cu = blocks_per_cu(kern, NT);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
@@ -554,7 +657,7 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
   while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT, SPT, DER, UJ>(b, --ch, L);
   if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
   if (a.plan) {
-    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu, NT >= 1024 ? 4 : WV};
+    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu, NT == 256 ? WV : 0};
     return 0;
   }
   if (int rc = allow_lds(kern, lds)) return rc;
@@ -594,7 +697,7 @@ inline int run_shape(int max_n_seg, int max_particles, int threads, int* nt, int
   return 0;
 }
 
-template <int DIM, bool MIXED, int JM, int PD, bool ORTHO>
+template <int DIM, bool MIXED, int JM, int PD, bool ORTHO, bool LAY = false>
 int run_jp(const LaunchBatch& b, const RunArgs& a) {
   static_assert(RUN_CHUNK <= 256, "staging uses one thread per move");
   int nt = 0, spt = 0, ppr = 0;
@@ -607,14 +710,14 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   const int wv = b.run_waves > 0 ? b.run_waves : 2;
 #define EW_RUN(NT, SPT, PPR)                                                                             \
   if (nt == NT && spt == SPT && ppr == PPR) {                                                           \
-    if (wv == 3) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 3>(b, a);               \
-    if (wv == 4) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 4>(b, a);               \
-    return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true>(b, a);                               \
+    if (wv == 3) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 3, LAY>(b, a);          \
+    if (wv == 4) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 4, LAY>(b, a);          \
+    return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 2, LAY>(b, a);                       \
   }
 #define EW_RUN_X(NT, SPT, PPR)                                                                          \
   if (nt == NT && spt == SPT && ppr == PPR)                                                            \
-    return xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true>(b, a)                       \
-                : run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, false>(b, a)
+    return xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 2, LAY>(b, a)               \
+                : run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, false, 2, LAY>(b, a)
   EW_RUN(256, 1, 1);
   EW_RUN(256, 1, 2);
   EW_RUN(256, 2, 1);
@@ -629,6 +732,12 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
 
 template <int DIM, bool MIXED, int JM, int PD>
 int run_jpo(const LaunchBatch& b, const RunArgs& a) {
+  // layered 2D batches (no Jastrow terms) take the kernels with a second plane
+  if constexpr (DIM == 2 && JM == 0) {
+    if (b.layered)
+      return b.all_ortho && !b.general_frame ? run_jp<DIM, MIXED, JM, PD, true, true>(b, a)
+                                             : run_jp<DIM, MIXED, JM, PD, false, true>(b, a);
+  }
   return b.all_ortho && !b.general_frame ? run_jp<DIM, MIXED, JM, PD, true>(b, a)
                                          : run_jp<DIM, MIXED, JM, PD, false>(b, a);
 }

@@ -688,7 +688,7 @@ def test_small_walker_shapes_vs_oracle(oracle_lib, cfg_id, precision):
             refs = [c.oracle(oracle_lib, w) for w in range(W)]
         c.batch.set_tuning(threads=threads, waves=waves)
         t = c.batch.tuning()
-        assert t["fused"] == 1 and t["threads"] == threads and t["waves"] == (waves or 4)
+        assert t["fused"] == 1 and t["threads"] == threads and t["waves"] == waves
         e0, _ = c.run_energy()
         d, dj = c.fused()
         for w in range(W):
@@ -978,8 +978,8 @@ def test_blips_full_size_sampled(oracle_lib):
 
 
 # Layered two-dimensional systems (Eq. (5) with z != 0): the electron-hole
-# bilayer against the oracle's pair-by-pair energy; the fused call runs the
-# per-step kernels for such batches.
+# bilayer against the oracle's pair-by-pair energy, through the per-step
+# kernels and the fused kernels with a second plane.
 @pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
 def test_bilayer_energy_and_moves(oracle_lib, precision):
     W, S, K = 3, 24, 4
@@ -989,7 +989,7 @@ def test_bilayer_energy_and_moves(oracle_lib, precision):
         c = Case(3, W, S, precision, refresh_every=K, jastrow=False, cfg=wl.bilayer_config())
         e0, _ = c.run_energy()
         if path == "run_moves":
-            assert c.batch.tuning()["fused"] == 0
+            assert c.batch.tuning()["fused"] == 1
         out[path] = (e0,) + (c.per_step() if path == "per-step" else c.fused())
         for w in range(W):
             h = c.batch.walker_header(w)
@@ -1040,8 +1040,20 @@ def test_layers_with_ions_and_telescoping(oracle_lib, precision):
     for m in range(S):
         b.move_delta(kt[m], nt[m], d[m])
         b.accept(at[m])
+    # the same sequence through the fused kernel (second plane in registers)
+    bf = ew.Batch([h], np.zeros(W, dtype=np.int32))
+    ef = torch.zeros(W, dtype=torch.float64, device=dev)
+    bf.energy(torch.tensor(np.concatenate(pos), device=dev), ef)
+    assert bf.tuning()["fused"] == 1
+    df = torch.zeros((S, W), dtype=torch.float64, device=dev)
+    bf.run_moves(kt, nt, at, df)
     torch.cuda.synchronize()
     e0, dd = e.cpu().numpy(), d.cpu().numpy()
+    tol_f = 1e-12 * max(1.0, float(np.max(np.abs(e0)))) if precision == FP64 else 1e-7
+    assert np.max(np.abs(df.cpu().numpy() - dd)) <= tol_f
+    for w in range(W):
+        assert np.array_equal(bf.walker_positions(w), b.walker_positions(w))
+        assert bf.walker_header(w)["n_refresh"] == b.walker_header(w)["n_refresh"]
     for w in range(W):
         r = oracle_lib.run(sysm, pos[w], k[:, w], newp[:, w], acc[:, w])
         scale = max(abs(r["energy0"]), e_scale(sysm))

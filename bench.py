@@ -158,12 +158,13 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_
         batch.close()
         s.close()
         return out
-    # per-step path (move_delta + accept per call), a short sweep for its rate
-    n_ps = 16
+    # per-step path, a short sweep of n_ps moves for its rate: move_delta +
+    # accept per move, then the step call (each move's accept folded into
+    # the next move's delta; the first delta and the last accept untimed)
+    n_ps = min(16, S - 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     batch.energy(t["pos"], energy, jas)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for m in range(n_ps):
         batch.move_delta(t["k"][m], t["new_pos"][m], delta[m], djas[m])
@@ -171,9 +172,41 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_
     e1.record(stream)
     torch.cuda.synchronize()
     out["per_step_ms_per_move"] = e0.elapsed_time(e1) / n_ps
+    batch.energy(t["pos"], energy, jas)
+    batch.step(None, t["k"][0], t["new_pos"][0], delta[0], djas[0])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for m in range(1, n_ps + 1):
+        batch.step(t["accept"][m - 1], t["k"][m], t["new_pos"][m], delta[m], djas[m])
+    e1.record(stream)
+    batch.accept(t["accept"][n_ps])
+    torch.cuda.synchronize()
+    out["step_ms_per_move"] = e0.elapsed_time(e1) / n_ps
+    out["per_step_accept_rate"] = float(b.accept[:n_ps].mean())
     batch.close()
     s.close()
     return out
+
+
+def per_step_rows(r, W: int, n_g: int, n: int, dim: int) -> dict:
+    """Rates and HBM rooflines of the per-step path.  Algorithmic bytes per
+    walker and move: rho read once (16 B per G of the half set) and the
+    positions (8 dim N B); an accepted move (rate p) writes rho back, and the
+    separate accept call reads it a second time."""
+    p = r["per_step_accept_rate"]
+    base = 16 * n_g + 8 * dim * n
+    rows = {}
+    for name, ms, nbytes, call in (
+            ("two_calls", r["per_step_ms_per_move"], base + p * 2 * 16 * n_g,
+             "ewald_move_delta_batch + ewald_accept_batch"),
+            ("step", r["step_ms_per_move"], base + p * 16 * n_g,
+             "ewald_step_batch (accept folded into the next delta)")):
+        gbs = W * nbytes / (ms * 1e-3) / 1e9
+        rows[name] = dict(deltas_per_s=round(W / (ms * 1e-3), 1), ms_per_move=round(ms, 4), call=call,
+                          roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                                        frac=round(gbs / PEAK_HBM_GBS, 4), bytes_per_move=round(nbytes, 1)))
+    rows["accept_rate"] = round(p, 4)
+    return rows
 
 
 def other_workload(cfg_id: int, precision: int, steps: int = 2, threads: int = 0):
@@ -312,10 +345,12 @@ def layers_row(forms=("mixed", "fp64"), steps: int = 2):
     second plane in registers, autotuned), deltas/s and its VALU fraction by
     the algorithmic count of the move (36 flops per G plus 5 for the
     cross-plane term, a dot product and a weighted add; 55 per pair evaluation) and of the mixed form's
-    rebuilds; and the per-step path (move_delta + accept per call) for
-    comparison, with its HBM fraction by the bytes it streams per move (both
-    planes' rho and the positions read by the delta, the moved plane's rho
-    read and written by an accepted move)."""
+    rebuilds; and the per-step path (move_delta + accept per call, and the
+    step call that folds each accept into the next delta) for comparison,
+    with its HBM fraction by the bytes it streams per move (both planes' rho
+    over the half set and the positions read by the delta; the moved plane's
+    rho written back by an accepted move, and read a second time by the
+    separate accept call)."""
     import torch
     from paper_2507_02888_amd import ewald as ew
     from paper_2507_02888_amd import workloads as wl
@@ -341,11 +376,11 @@ def layers_row(forms=("mixed", "fp64"), steps: int = 2):
         n_ref = int(np.sum(b.accept.sum(axis=0) // K)) if K else 0
         flops = W * S * (n_g * (FLOP_PER_G_DELTA + 5) + 2 * (n - 1) * FLOP_PER_PAIR_DELTA) + \
             n_ref * algorithmic_flops_per_rebuild(n_g, n)
-        # per-step path over a few moves
-        batch.energy(t["pos"], e)
+        # per-step path over a few moves: move_delta + accept, then the step call
         stream = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         n_ps = 16
+        batch.energy(t["pos"], e)
         e0.record(stream)
         for m in range(n_ps):
             batch.move_delta(t["k"][m], t["new_pos"][m], delta[m])
@@ -353,16 +388,27 @@ def layers_row(forms=("mixed", "fp64"), steps: int = 2):
         e1.record(stream)
         torch.cuda.synchronize()
         ps_ms = e0.elapsed_time(e1) / n_ps
-        slots = h.info["n_slots"]
-        p_acc = float(b.accept.mean())
-        bytes_per_move = 2 * 16 * slots + 8 * 2 * n + p_acc * 2 * 16 * slots
-        gbs = W * bytes_per_move / (ps_ms * 1e-3) / 1e9
+        batch.energy(t["pos"], e)
+        batch.step(None, t["k"][0], t["new_pos"][0], delta[0])
+        e0.record(stream)
+        for m in range(1, n_ps + 1):
+            batch.step(t["accept"][m - 1], t["k"][m], t["new_pos"][m], delta[m])
+        e1.record(stream)
+        batch.accept(t["accept"][n_ps])
+        torch.cuda.synchronize()
+        st_ms = e0.elapsed_time(e1) / n_ps
+        n_g = h.info["n_g"]
+        p_acc = float(b.accept[:n_ps].mean())
+        rows = {}
+        for name, ms_m, nbytes in (("two_calls", ps_ms, 2 * 16 * n_g + 8 * 2 * n + p_acc * 2 * 16 * n_g),
+                                   ("step", st_ms, 2 * 16 * n_g + 8 * 2 * n + p_acc * 16 * n_g)):
+            gbs = W * nbytes / (ms_m * 1e-3) / 1e9
+            rows[name] = dict(deltas_per_s=round(W / (ms_m * 1e-3), 1), ms_per_move=round(ms_m, 4),
+                              roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                                            frac=round(gbs / PEAK_HBM_GBS, 4), bytes_per_move=round(nbytes, 1)))
         out[form] = dict(run_deltas_per_s=round(W * S / (ms * 1e-3), 1), launch_ms=round(ms, 4),
                          frac=round(flops / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4), launch_shape=batch.tuning(),
-                         per_step_deltas_per_s=round(W / (ps_ms * 1e-3), 1),
-                         per_step_roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                                                frac=round(gbs / PEAK_HBM_GBS, 4),
-                                                bytes_per_move=round(bytes_per_move, 1)))
+                         per_step=rows)
         batch.close()
         h.close()
     out["call"] = ("ewald_run_moves_batch on the electron-hole bilayer (150 + 150 particles, d = 5 bohr), fused "
@@ -599,6 +645,7 @@ def main():
         r["energies_per_s"] = W / (r["energy_ms"] * 1e-3)
         r["energy_kernel"] = dict(ms=round(r["energy_ms"], 4), achieved_tflops=round(e_flops / (r["energy_ms"] * 1e-3) / 1e12, 3))
         r["per_step_deltas_per_s"] = W / (r["per_step_ms_per_move"] * 1e-3)
+        r["per_step"] = per_step_rows(r, W, n_g, n_part, sysm.dim)
         results[form] = r
 
     sweep = []
@@ -660,7 +707,8 @@ def main():
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
         "parity": None if cpu is None else head.get("parity"),
         "energies_per_s": round(head["energies_per_s"], 1),
-        "per_step_path_deltas_per_s": round(head["per_step_deltas_per_s"], 1),
+        "per_step_path_deltas_per_s": round(head["per_step"]["step"]["deltas_per_s"], 1),
+        "per_step": head["per_step"],
     }
     if sweep:
         k_main = results["mixed"]
@@ -675,8 +723,8 @@ def main():
         f = results["fp64"]
         line["fp64"] = {"value": round(f["value"], 1), "unit": "deltas/s", "ms_per_step": round(f["ms_per_step"], 3),
                         "roofline": f["roofline"], "energies_per_s": round(f["energies_per_s"], 1),
-                        "per_step_path_deltas_per_s": round(f["per_step_deltas_per_s"], 1),
-                        "parity": f.get("parity")}
+                        "per_step_path_deltas_per_s": round(f["per_step"]["step"]["deltas_per_s"], 1),
+                        "per_step": f["per_step"], "parity": f.get("parity")}
     print(json.dumps(line), flush=True)
     if not parity_ok:
         print("bench.py: GPU results differ from the oracle beyond the stated bounds", file=sys.stderr)

@@ -237,6 +237,26 @@ ewald_status ewald_move_delta_batch(ewald_batch *b, void *state, const int32_t *
  * positions in FP64.  E_STATE if no move is pending. */
 ewald_status ewald_accept_batch(ewald_batch *b, void *state, const uint8_t *accept, void *stream);
 
+/* One step of the single-particle move loop (Sec. 2.1): the accept/reject
+ * decision on the move left pending by the previous call, then the energy
+ * change of the next proposed move.  Same results and state as
+ *   ewald_accept_batch(accept_prev) followed by
+ *   ewald_move_delta_grad_batch(k, new_pos, delta, djastrow, jgrad, jlap),
+ * with the accept's update of rho (rho <- rho + delta in FP64) applied while
+ * the delta streams rho, so that rho is read once per step rather than
+ * twice for an accepted move.
+ *   accept_prev  device [n_walkers], or NULL: no decision to apply (exactly
+ *                ewald_move_delta_grad_batch); non-NULL needs a pending move
+ *                (E_STATE otherwise), as ewald_accept_batch does
+ *   k, new_pos, delta, djastrow, jgrad, jlap: as ewald_move_delta_grad_batch
+ * The new move is left pending.  In the FP32-mixed form a walker whose accept
+ * reaches refresh_every accepted moves gets rho rebuilt in FP64 before its
+ * delta is taken, as in the two-call sequence (a second, short launch).
+ * Status as for ewald_move_delta_grad_batch. */
+ewald_status ewald_step_batch(ewald_batch *b, void *state, const uint8_t *accept_prev, const int32_t *k,
+                              const double *new_pos, double *delta, double *djastrow, double *jgrad,
+                              double *jlap, void *stream);
+
 /* n_steps consecutive proposals per walker in one launch, rho kept on chip: a
  * sequence of the single-particle moves of Sec. 2.1, each with its energy
  * change as defined for ewald_move_delta_batch (Sec. 2.2, Eqs. (2)-(6)).

@@ -247,6 +247,11 @@ __device__ __forceinline__ double uniform_d(double v) {
   return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
                           __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform_r(double v) { return uniform_d(v); }
+__device__ __forceinline__ float uniform_r(float v) { return uniform_f(v); }
 
 // Kahan-compensated FP32 accumulator.
 struct Kahan {
@@ -538,11 +543,13 @@ __device__ __forceinline__ double image_disp(const double* a, const double* b, c
 // mobile pairs into uo (UD: with its gradient, in the lower-triangular
 // frame's axes, and Laplacian at the new position).
 // A layered 2D system (S->n_layers = 2) adds (z_1 - z_0)^2 to r^2 for the
-// partners in the other plane.
+// partners in the other plane.  sub_k >= 0: particle sub_k is taken at
+// sub_s instead of its stored position (a move accepted in the same launch).
 template <int DIM, bool MIXED, int PD, int NT, bool UJ = false, bool UD = false>
 __device__ __forceinline__ double real_move(const double* sn, const double* so, int k, const double* pos,
                                             const double* q, int n, const DevSys* __restrict__ S,
-                                            UOut<DIM>* uo = nullptr) {
+                                            UOut<DIM>* uo = nullptr, int sub_k = -1,
+                                            const double* sub_s = nullptr) {
   constexpr int PPR = NT >= 1024 ? 1 : 2;
   const FrameK K = frame_k(S);
   PairAcc<MIXED, PD> pr(S->p64, S->p32, K);
@@ -564,7 +571,7 @@ __device__ __forceinline__ double real_move(const double* sn, const double* so, 
       const int jj = j < n ? j : n - 1;
       double pj[DIM];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) pj[d] = pos[jj * DIM + d];
+      for (int d = 0; d < DIM; ++d) pj[d] = jj == sub_k ? sub_s[d] : pos[jj * DIM + d];
       const double qj = ok ? q[jj] : 0.0;
       if (UD)
         r2[2 * c] = ok ? min_disp<DIM>(sn, pj, S, n_cand, xn[UD ? c : 0]) : rc2;
@@ -879,6 +886,8 @@ struct SegWalk {
   R c2;
   cplx<R> u;
   __device__ __forceinline__ SegWalk(cplx<R> a, cplx<R> u_) : cur(a), prev(a), c2(R(2) * u_.x), u(u_) {}
+  // u_ and c2_ = 2 Re u_ precomputed (e.g. wave-uniform, in scalar registers)
+  __device__ __forceinline__ SegWalk(cplx<R> a, cplx<R> u_, R c2_) : cur(a), prev(a), c2(c2_), u(u_) {}
   __device__ __forceinline__ void step(int j) {  // e_j -> e_{j+1}; j is a compile-time index in unrolled loops
     if (j == 0) {
       prev = cur;

@@ -210,6 +210,64 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Per-step calls: move delta (optionally folding in the previous move's
+// accept) and accept.
+constexpr int RED_DELTA = 48;  // LDS doubles for k_delta's reduction: up to 12 sums x 4 waves
+
+// rho += q (e_new - e_old) for an accepted move: the difference and its
+// product with q in the form's precision, the sum in FP64 (the per-step
+// accept and the accept folded into the step kernel use this arithmetic,
+// the fused sweep the same expression).
+template <typename R>
+__device__ __forceinline__ void add_move(double2& r, R q, const cplx<R>& en, const cplx<R>& eo) {
+  r.x += double(q * (en.x - eo.x));
+  r.y += double(q * (en.y - eo.y));
+}
+
+// Apply an accepted move to one plane's rho, streaming its segments once
+// (to, tn: the old and new position's phase tables, already in LDS).
+template <int DIM, typename R>
+__device__ __forceinline__ void accept_stream(const DevSys* __restrict__ S, const cplx<R>* to, const cplx<R>* tn,
+                                              double* rho, R q) {
+  const int nseg = S->n_seg, nm = S->nm, tbl = 2 * nm + 1;
+  const cplx<R> uo = tab_at(to, DIM - 1, nm + 1, tbl), un = tab_at(tn, DIM - 1, nm + 1, tbl);
+  double2* rho2 = reinterpret_cast<double2*>(rho);
+  for (int s = threadIdx.x; s < nseg; s += BLOCK) {
+    double2 r[SEG];
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) r[j] = rho2[size_t(j) * nseg + s];
+    const uint32_t pn = S->seg_n[s];
+    SegWalk<R> wo(anchor<DIM, R>(to, pn, nm), uo), wn(anchor<DIM, R>(tn, pn, nm), un);
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      add_move(r[j], q, wn.cur, wo.cur);
+      rho2[size_t(j) * nseg + s] = r[j];
+      if (j + 1 < SEG) {
+        wo.step(j);
+        wn.step(j);
+      }
+    }
+  }
+}
+
+// Header side of an accept/reject (one thread): the position, the refresh
+// counter (reset first when the previous call left it at K, i.e. rho was
+// rebuilt after it) and the accept count; no move is pending afterwards.
+template <int DIM>
+__device__ __forceinline__ void accept_header(WalkerHdr* hdr, double* spos, int pk, bool acc, const double* sp,
+                                              int K) {
+  int counter = hdr->counter;
+  if (K > 0 && counter >= K) counter = 0;
+  if (acc) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) spos[pk * DIM + d] = sp[d];
+    counter += 1;
+    hdr->n_accepts += 1;
+  }
+  hdr->counter = counter;
+  hdr->pending_k = -1;
+}
+
 // Move delta: dE and dJ of moving particle k to new_pos; records the pending
 // move.  rho is streamed from the state once (slot-planar, coalesced).
 //
@@ -224,40 +282,66 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
 // shell and comes with a from the shell table.
 // UJ: dJ also takes the two-body polynomial term u of the mobile pairs (and,
 // with DER, its gradient and Laplacian at the new position).
-constexpr int RED_DELTA = 48;  // LDS doubles for k_delta's reduction: up to 12 sums x 4 waves
+//
+// Step form (accept_prev != NULL): first the accept or reject of the move
+// left pending by the previous call, with the arithmetic and header updates
+// of k_accept, folded into this call's rho stream: rho is read once and, for
+// an accepted move, written back updated, and the accepted particle's
+// position is taken from the pending record; then the new move's delta from
+// the updated rho and positions.  This saves the accept's second pass over
+// rho.  In the FP32-mixed form a walker whose accept brings the refresh
+// counter to K gets rho rebuilt by k_rebuild after this launch and its delta
+// recomputed by a second launch with redo = 1, which leaves every other
+// walker alone; the outputs are then those of k_accept + k_rebuild + k_delta.
 template <int DIM, bool MIXED, int PD, bool DER, bool UJ>
 __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ systems,
                                                  const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                                  const int32_t* __restrict__ kk, const double* __restrict__ new_pos,
                                                  double* __restrict__ delta, double* __restrict__ djas,
-                                                 double* __restrict__ jgrad, double* __restrict__ jlap, int lds_tab) {
+                                                 double* __restrict__ jgrad, double* __restrict__ jlap, int lds_tab,
+                                                 const uint8_t* __restrict__ accept_prev, int redo) {
   using R = typename std::conditional<MIXED, float, double>::type;
   using WT2 = cplx<R>;  // (weight, Jastrow coefficient) in the form's precision
   extern __shared__ double smem[];
   const DevWalker W = walkers[blockIdx.x];
   const int w = W.id, tid = threadIdx.x;
   const DevSys* __restrict__ S = systems + W.sys;
-  const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
+  const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm, K = S->refresh_every;
   const int tbl = 2 * nm + 1;
   char* st = state + W.state_off;
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
-  const double* spos = reinterpret_cast<const double*>(st + HDR_BYTES);
-  const double* rho = reinterpret_cast<const double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
-  // layered 2D system: the moved particle's plane and the other plane's rho
+  double* spos = reinterpret_cast<double*>(st + HDR_BYTES);
+  double* rho = reinterpret_cast<double*>(st + HDR_BYTES + walker_pos_bytes(n, DIM));
+  if (redo && !(K > 0 && hdr->counter >= K)) return;  // uniform: redo only where rho was just rebuilt
+  // the pending move's accept (step form)
+  const int pk = hdr->pending_k;
+  const bool acc = accept_prev != nullptr && pk >= 0 && pk < n && accept_prev[w] != 0;
+  double sp[DIM];  // the accepted particle's new position
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) sp[d] = acc ? hdr->pending_s[d] : 0.0;
+  const R qp = acc ? R(S->mobile_q[pk]) : R(0);
+  // layered 2D system: rho of plane 1 follows plane 0's
   const bool lay = DIM == 2 && S->n_layers > 1;
-  const int lk = kk[w] >= S->n0 ? 1 : 0;
-  if (lay && lk) rho += 2 * size_t(SEG) * nseg;
-  const double2* __restrict__ rhoo2 =
-      reinterpret_cast<const double2*>(lay ? (lk ? rho - 2 * size_t(SEG) * nseg : rho + 2 * size_t(SEG) * nseg) : rho);
+  const size_t plane = 2 * size_t(SEG) * nseg;
+  const int lp = lay && acc && pk >= S->n0 ? 1 : 0;
   double* red = smem;  // [NV][4], NV <= RED_DELTA / 4
   cplx<R>* to = reinterpret_cast<cplx<R>*>(smem + RED_DELTA);
   cplx<R>* tn = to + DIM * tbl;
+  cplx<R>* tpo = tn + DIM * tbl;  // the accepted move's old and new position
+  cplx<R>* tpn = tpo + DIM * tbl;
   WT2* ltab = reinterpret_cast<WT2*>(smem + RED_DELTA + lds_tab);  // shell table (when it fits)
   R* ltab2 = reinterpret_cast<R*>(ltab + S->n_wtab);      // a |G|^2 per shell (DER)
-  const double2* __restrict__ rho2 = reinterpret_cast<const double2*>(rho);
 
   const int k = kk[w];
   if (k < 0 || k >= n) {
+    if (acc) {  // the accept still applies
+      double so_p[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) so_p[d] = spos[pk * DIM + d];
+      if (tid < 2 * DIM) fill_row<R>(tpo + tid * tbl, pick_coord<DIM>(so_p, sp, tid), nm);
+      __syncthreads();
+      accept_stream<DIM, R>(S, tpo, tpn, rho + lp * plane, qp);
+    }
     if (tid == 0) {
       delta[w] = NAN;
       if (djas) djas[w] = NAN;
@@ -265,10 +349,15 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
         for (int d = 0; d < DIM; ++d) jgrad[size_t(w) * DIM + d] = NAN;
         jlap[w] = NAN;
       }
+      if (accept_prev) accept_header<DIM>(hdr, spos, pk, acc, sp, K);
       hdr->pending_k = -1;
     }
     return;
   }
+  const int lk = lay && k >= S->n0 ? 1 : 0;
+  double2* __restrict__ rho2 = reinterpret_cast<double2*>(rho + lk * plane);
+  double2* __restrict__ rhoo2 = reinterpret_cast<double2*>(rho + (1 - lk) * plane);  // the other plane (lay)
+  const bool acc_own = acc && lp == lk;  // else the other plane's
   // start streaming this thread's first segment of rho before the table barrier
   const bool wlds = S->wtab_lds != 0;
   double2 rcur[SEG];
@@ -290,15 +379,34 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
 #pragma unroll
     for (int d = 0; d < DIM; ++d) r[d] = new_pos[size_t(w) * DIM + d];
     to_frac<DIM>(r, S->Ainv, sn);
+    const bool same = acc && k == pk;  // moving the particle just accepted: from its new position
+    // the move's positions are the same in every lane: scalar registers
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) so[d] = spos[k * DIM + d];
+    for (int d = 0; d < DIM; ++d) {
+      sn[d] = uniform_d(sn[d]);
+      so[d] = uniform_d(same ? sp[d] : spos[k * DIM + d]);
+      sp[d] = uniform_d(sp[d]);
+    }
   }
   const double qk = S->mobile_q[k];
   if (tid < 2 * DIM) fill_row<R>(to + tid * tbl, pick_coord<DIM>(so, sn, tid), nm);  // to, then tn
+  if (acc && tid >= 2 * DIM && tid < 4 * DIM) {
+    double so_p[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) so_p[d] = spos[pk * DIM + d];
+    fill_row<R>(tpo + (tid - 2 * DIM) * tbl, pick_coord<DIM>(so_p, sp, tid - 2 * DIM), nm);  // tpo, then tpn
+  }
   __syncthreads();
 
   // reciprocal space: t(G) = 2 q Re(conj(rho) d) + q^2 |d|^2, d = e_new - e_old
-  const cplx<R> uo = tab_at(to, DIM - 1, nm + 1, tbl), un = tab_at(tn, DIM - 1, nm + 1, tbl);
+  // the walks' steps exp(2 pi i s_last) are the same in every lane: kept in scalar registers
+  auto ustep = [&](const cplx<R>* t) {
+    const cplx<R> u = tab_at(t, DIM - 1, nm + 1, tbl);
+    return cplx<R>{uniform_r(u.x), uniform_r(u.y)};
+  };
+  const cplx<R> uo = ustep(to), un = ustep(tn), upo = ustep(tpo), upn = ustep(tpn);
+  const R c2o = uniform_r(R(2) * uo.x), c2n = uniform_r(R(2) * un.x);
+  const R c2po = uniform_r(R(2) * upo.x), c2pn = uniform_r(R(2) * upn.x);
   const double* __restrict__ wt = S->w;
   const double* __restrict__ ja = S->ja;
   // t(G) = q^2 [dx (dx + (2/q) rho_x) + dy (dy + (2/q) rho_y)]: q^2 is applied
@@ -308,9 +416,9 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
   double dS[DIM], dL = 0.0;  // DER: S_d and sum_H a |G|^2 Re z
 #pragma unroll
   for (int d = 0; d < DIM; ++d) dS[d] = 0.0;
-  const R c2q = qk != 0.0 ? R(2.0 / qk) : R(0);
-  const R qr = R(qk);
-  for (int s = tid; s < nseg && qk != 0.0; s += BLOCK) {
+  const R c2q = uniform_r(qk != 0.0 ? R(2.0 / qk) : R(0));
+  const R qr = uniform_r(R(qk));
+  for (int s = tid; s < nseg && (qk != 0.0 || acc); s += BLOCK) {
     // prefetch the next segment while this one is consumed
     const int s2 = s + BLOCK < nseg ? s + BLOCK : s;
     double2 rnxt[SEG];
@@ -322,7 +430,29 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
       snxt[j] = S->slot_shell[g2];
     }
     const uint32_t pn = S->seg_n[s];
-    SegWalk<R> wo(anchor<DIM, R>(to, pn, nm), uo), wn(anchor<DIM, R>(tn, pn, nm), un);
+    double2 ro[SEG];  // the other plane's segment (layered system)
+    if (lay)
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) ro[j] = rhoo2[size_t(j) * nseg + s];
+    if (acc) {  // the accepted move first, written back to its plane
+      SegWalk<R> wpo(anchor<DIM, R>(tpo, pn, nm), upo, c2po), wpn(anchor<DIM, R>(tpn, pn, nm), upn, c2pn);
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) {
+        const size_t g = size_t(j) * nseg + s;
+        if (acc_own) {
+          add_move(rcur[j], qp, wpn.cur, wpo.cur);
+          rho2[g] = rcur[j];
+        } else if (lay) {
+          add_move(ro[j], qp, wpn.cur, wpo.cur);
+          rhoo2[g] = ro[j];
+        }
+        if (j + 1 < SEG) {
+          wpo.step(j);
+          wpn.step(j);
+        }
+      }
+    }
+    SegWalk<R> wo(anchor<DIM, R>(to, pn, nm), uo, c2o), wn(anchor<DIM, R>(tn, pn, nm), un, c2n);
     float segE = 0.f, segJ = 0.f, segX = 0.f;  // mixed form: FP32 sums per segment, compensated across segments
     R sT = R(0), sT2 = R(0), sL = R(0);  // DER: per-segment sums of a Im z, j a Im z, a |G|^2 Re z
 #pragma unroll
@@ -351,8 +481,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
         if (ja) accJ64 = fma(double(aj), double(t), accJ64);
       }
       if (lay) {  // other plane: w_x (rho_o . d)
-        const double2 ro = rhoo2[g];
-        const R xo = fma(R(ro.x), dx, R(ro.y) * dy);
+        const R xo = fma(R(ro[j].x), dx, R(ro[j].y) * dy);
         if (MIXED)
           segX = fmaf(float(S->wx[g]), float(xo), segX);
         else
@@ -388,9 +517,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
       scur[j] = snxt[j];
     }
   }
-  // real space
+  // real space (the accepted particle at its new position)
   UOut<DIM> ut;
-  const double er = real_move<DIM, MIXED, PD, BLOCK, UJ, UJ && DER>(sn, so, k, spos, S->mobile_q, n, S, &ut);
+  const double er = real_move<DIM, MIXED, PD, BLOCK, UJ, UJ && DER>(sn, so, k, spos, S->mobile_q, n, S, &ut,
+                                                                    acc ? pk : -1, sp);
   const double q2 = qk * qk;
   constexpr int NP = DER ? 3 + DIM : 2;         // energy, J, and the p-term derivative sums
   constexpr int NV = NP + (UJ && DER ? DIM + 1 : 0);  // and the u term's gradient (frame axes) and Laplacian
@@ -409,7 +539,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
     for (int d = 0; d < DIM; ++d) v[NP + d] = ut.g[d];
     v[NV - 1] = ut.l;
   }
-  block_sum<NV>(v, red);
+  block_sum<NV>(v, red);  // (its barriers also order every read of the header and positions before the writes below)
   if (tid == 0) {
     delta[w] = v[0];
     if (djas) djas[w] = v[1];
@@ -425,6 +555,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_delta(const DevSys* __restrict__ s
       }
       jlap[w] = -2.0 * qk * v[NP - 1] + 2.0 * q2 * S->jlap_c + (UJ ? v[NV - 1] : 0.0);
     }
+    if (accept_prev) accept_header<DIM>(hdr, spos, pk, acc, sp, K);
     hdr->pending_k = k;
 #pragma unroll
     for (int d = 0; d < 3; ++d) hdr->pending_s[d] = d < DIM ? sn[d] : 0.0;
@@ -443,7 +574,7 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
   const DevWalker W = walkers[blockIdx.x];
   const int w = W.id, tid = threadIdx.x;
   const DevSys* __restrict__ S = systems + W.sys;
-  const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm, K = S->refresh_every;
+  const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
   const int tbl = 2 * nm + 1;
   char* st = state + W.state_off;
   WalkerHdr* hdr = reinterpret_cast<WalkerHdr*>(st);
@@ -453,9 +584,8 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
   cplx<R>* tn = to + DIM * tbl;
 
   const int pk = hdr->pending_k;
-  int counter = hdr->counter;
   const bool acc = pk >= 0 && pk < n && accept[w] != 0;
-  double so[DIM], sn[DIM];
+  double so[DIM], sn[DIM] = {};
   if (acc) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -466,40 +596,11 @@ __global__ __launch_bounds__(BLOCK) void k_accept(const DevSys* __restrict__ sys
   }
   __syncthreads();  // every thread has read the header and pending position
   if (acc) {
-    const R q = R(S->mobile_q[pk]);
-    const cplx<R> uo = tab_at(to, DIM - 1, nm + 1, tbl), un = tab_at(tn, DIM - 1, nm + 1, tbl);
     // a layered system's second plane keeps its rho after the first's
-    if (DIM == 2 && S->n_layers > 1 && pk >= S->n0) rho += 2 * size_t(SEG) * nseg;
-    double2* rho2 = reinterpret_cast<double2*>(rho);
-    for (int s = tid; s < nseg; s += BLOCK) {
-      double2 r[SEG];
-#pragma unroll
-      for (int j = 0; j < SEG; ++j) r[j] = rho2[size_t(j) * nseg + s];
-      const uint32_t pn = S->seg_n[s];
-      SegWalk<R> wo(anchor<DIM, R>(to, pn, nm), uo), wn(anchor<DIM, R>(tn, pn, nm), un);
-#pragma unroll
-      for (int j = 0; j < SEG; ++j) {
-        r[j].x += double(q * (wn.cur.x - wo.cur.x));
-        r[j].y += double(q * (wn.cur.y - wo.cur.y));
-        rho2[size_t(j) * nseg + s] = r[j];
-        if (j + 1 < SEG) {
-          wo.step(j);
-          wn.step(j);
-        }
-      }
-    }
+    const bool l1 = DIM == 2 && S->n_layers > 1 && pk >= S->n0;
+    accept_stream<DIM, R>(S, to, tn, rho + (l1 ? 2 * size_t(SEG) * nseg : 0), R(S->mobile_q[pk]));
   }
-  if (tid == 0) {
-    if (K > 0 && counter >= K) counter = 0;  // rho was rebuilt after the previous call
-    if (acc) {
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) spos[pk * DIM + d] = sn[d];
-      counter += 1;
-      hdr->n_accepts += 1;
-    }
-    hdr->counter = counter;
-    hdr->pending_k = -1;
-  }
+  if (tid == 0) accept_header<DIM>(hdr, spos, pk, acc, sn, S->refresh_every);
 }
 
 // Rebuild rho in FP64 for walkers whose accepted-move counter reached K.
@@ -607,15 +708,17 @@ int energy_dim(const LaunchBatch& b, const double* pos, char* state, double* ene
 
 template <int DIM, bool MIXED>
 int delta_dim(const LaunchBatch& b, char* state, const int32_t* k, const double* new_pos, double* delta,
-              double* djas, double* jgrad, double* jlap, void* stream) {
+              double* djas, double* jgrad, double* jlap, void* stream, const uint8_t* accept_prev = nullptr,
+              int redo = 0) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  const size_t mtab = size_t(2) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
+  // phase tables of the proposed move and of the accepted one (step form)
+  const size_t mtab = size_t(4) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<R>);
   const int lds_tab = even(int((mtab + 7) / 8));  // in doubles
   const bool der = jgrad != nullptr;
   const size_t lds = RED_DELTA * 8 + size_t(lds_tab) * 8 + size_t(b.max_wtab) * (sizeof(cplx<R>) + (der ? sizeof(R) : 0));
 #define EW_DELTA(PD, DER, UJ)                                                                                     \
   hipLaunchKernelGGL((k_delta<DIM, MIXED, PD, DER, UJ>), dim3(b.n_walkers), dim3(BLOCK), lds, as_stream(stream), \
-                     b.d_sys, b.d_walk, state, k, new_pos, delta, djas, jgrad, jlap, lds_tab)
+                     b.d_sys, b.d_walk, state, k, new_pos, delta, djas, jgrad, jlap, lds_tab, accept_prev, redo)
 #define EW_DELTA_U(PD, DER) \
   if (b.has_u)              \
     EW_DELTA(PD, DER, true); \
@@ -639,6 +742,15 @@ int delta_dim(const LaunchBatch& b, char* state, const int32_t* k, const double*
   return last_launch();
 }
 
+template <int DIM>
+int rebuild_launch(const LaunchBatch& b, char* state, void* stream) {
+  const size_t lds_r = size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>);
+  const int chunks = (b.max_n_seg + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL((k_rebuild<DIM>), dim3(b.n_walkers, chunks), dim3(BLOCK), lds_r, as_stream(stream), b.d_sys,
+                     b.d_walk, state);
+  return last_launch();
+}
+
 template <int DIM, bool MIXED>
 int accept_dim(const LaunchBatch& b, char* state, const uint8_t* accept, void* stream) {
   using R = typename std::conditional<MIXED, float, double>::type;
@@ -647,11 +759,20 @@ int accept_dim(const LaunchBatch& b, char* state, const uint8_t* accept, void* s
                      b.d_walk, state, accept);
   int rc = last_launch();
   if (rc || !MIXED || b.refresh_every <= 0) return rc;
-  const size_t lds_r = size_t(TILE_P) * DIM * (2 * b.max_nm + 1) * sizeof(cplx<double>);
-  const int chunks = (b.max_n_seg + BLOCK - 1) / BLOCK;
-  hipLaunchKernelGGL((k_rebuild<DIM>), dim3(b.n_walkers, chunks), dim3(BLOCK), lds_r, as_stream(stream), b.d_sys,
-                     b.d_walk, state);
-  return last_launch();
+  return rebuild_launch<DIM>(b, state, stream);
+}
+
+// Step: the previous move's accept folded into the new move's delta; in the
+// FP32-mixed form the walkers whose accept reached the refresh count are
+// rebuilt and their deltas recomputed from the rebuilt rho.
+template <int DIM, bool MIXED>
+int step_dim(const LaunchBatch& b, char* state, const uint8_t* accept_prev, const int32_t* k,
+             const double* new_pos, double* delta, double* djas, double* jgrad, double* jlap, void* stream) {
+  int rc = delta_dim<DIM, MIXED>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream, accept_prev, 0);
+  if (rc || !accept_prev || !MIXED || b.refresh_every <= 0) return rc;
+  rc = rebuild_launch<DIM>(b, state, stream);
+  if (rc) return rc;
+  return delta_dim<DIM, MIXED>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream, nullptr, 1);
 }
 
 
@@ -688,6 +809,15 @@ int launch_delta(const LaunchBatch& b, char* state, const int32_t* k, const doub
                                  : delta_dim<3, false>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream);
   return b.mixed ? delta_dim<2, true>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream)
                  : delta_dim<2, false>(b, state, k, new_pos, delta, djas, jgrad, jlap, stream);
+}
+
+int launch_step(const LaunchBatch& b, char* state, const uint8_t* accept_prev, const int32_t* k,
+                const double* new_pos, double* delta, double* djas, double* jgrad, double* jlap, void* stream) {
+  if (b.dim == 3)
+    return b.mixed ? step_dim<3, true>(b, state, accept_prev, k, new_pos, delta, djas, jgrad, jlap, stream)
+                   : step_dim<3, false>(b, state, accept_prev, k, new_pos, delta, djas, jgrad, jlap, stream);
+  return b.mixed ? step_dim<2, true>(b, state, accept_prev, k, new_pos, delta, djas, jgrad, jlap, stream)
+                 : step_dim<2, false>(b, state, accept_prev, k, new_pos, delta, djas, jgrad, jlap, stream);
 }
 
 int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void* stream) {

@@ -1171,6 +1171,21 @@ ewald_status ewald_accept_batch(ewald_batch* b, void* state, const uint8_t* acce
   return check_state(b, state, 0, 1);
 }
 
+ewald_status ewald_step_batch(ewald_batch* b, void* state, const uint8_t* accept_prev, const int32_t* k,
+                              const double* new_pos, double* delta, double* djastrow, double* jgrad, double* jlap,
+                              void* stream) {
+  if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (!state || !k || !new_pos || !delta) return fail(EWALD_E_ARG, "state, k, new_pos and delta must be non-NULL");
+  if ((jgrad == nullptr) != (jlap == nullptr)) return fail(EWALD_E_ARG, "jgrad and jlap must both be given or both NULL");
+  if (jgrad && !b->lb.has_jastrow) return fail(EWALD_E_ARG, "Jastrow derivatives need Jastrow coefficients or a u term");
+  ewald_status st = check_state(b, state, accept_prev ? 2 : 1, -1);
+  if (st != EWALD_OK) return st;
+  int rc = launch_step(b->lb, static_cast<char*>(state), accept_prev, k, new_pos, delta, djastrow, jgrad, jlap,
+                       stream);
+  if (rc) return launch_status(rc, "step");
+  return check_state(b, state, 0, 2);
+}
+
 ewald_status ewald_run_moves_grad_batch(ewald_batch* b, void* state, int n_steps, const int32_t* k,
                                         const double* new_pos, const uint8_t* accept, double* delta,
                                         double* djastrow, double* jgrad, double* jlap, void* stream) {

@@ -200,6 +200,11 @@ int launch_energy(const LaunchBatch& b, const double* pos, char* state, double* 
 int launch_delta(const LaunchBatch& b, char* state, const int32_t* k, const double* new_pos,
                  double* delta, double* djastrow, double* jgrad, double* jlap, void* stream);
 int launch_accept(const LaunchBatch& b, char* state, const uint8_t* accept, void* stream);
+// accept_prev != NULL: the accept of the pending move folded into the delta
+// of the next (NULL: launch_delta).
+int launch_step(const LaunchBatch& b, char* state, const uint8_t* accept_prev, const int32_t* k,
+                const double* new_pos, double* delta, double* djastrow, double* jgrad, double* jlap,
+                void* stream);
 int launch_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k,
                const double* new_pos, const uint8_t* accept, double* delta, double* djastrow,
                double* jgrad, double* jlap, void* stream);

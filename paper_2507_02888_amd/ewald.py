@@ -30,7 +30,7 @@ EXPORTS = ("ewald_setup", "ewald_sys_query", "ewald_sys_tables", "ewald_sys_cand
            "ewald_sys_geometry", "ewald_sys_destroy", "ewald_batch_create", "ewald_batch_layout", "ewald_state_offsets",
            "ewald_batch_destroy", "ewald_energy_batch", "ewald_move_delta_batch",
            "ewald_accept_batch", "ewald_run_moves_batch", "ewald_move_delta_grad_batch",
-           "ewald_run_moves_grad_batch", "ewald_batch_set_tuning",
+           "ewald_run_moves_grad_batch", "ewald_step_batch", "ewald_batch_set_tuning",
            "ewald_batch_get_tuning", "ewald_autotune", "ewald_blip_create", "ewald_blip_destroy",
            "ewald_blip_eval_batch", "ewald_last_error")
 
@@ -86,6 +86,7 @@ def load() -> ctypes.CDLL:
     lib.ewald_run_moves_batch.argtypes = [vp, vp, c_int, vp, vp, vp, vp, vp, vp]
     lib.ewald_move_delta_grad_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ewald_run_moves_grad_batch.argtypes = [vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ewald_step_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ewald_batch_set_tuning.argtypes = [vp, c_int, c_int, c_int, c_int]
     lib.ewald_batch_get_tuning.argtypes = [vp, P(c_int), P(c_int), P(c_int), P(c_int), P(c_int)]
     lib.ewald_autotune.argtypes = [vp, vp, c_int, ctypes.c_char_p, vp]
@@ -279,6 +280,15 @@ def ewald_move_delta_grad_batch(batch_h, state_ptr, k_ptr, new_pos_ptr, delta_pt
                                               ctypes.c_void_p(stream or None)))
 
 
+def ewald_step_batch(batch_h, state_ptr, accept_prev_ptr, k_ptr, new_pos_ptr, delta_ptr, djastrow_ptr=0,
+                     jgrad_ptr=0, jlap_ptr=0, stream=0) -> None:
+    _check(load().ewald_step_batch(ctypes.c_void_p(batch_h), ctypes.c_void_p(state_ptr),
+                                   ctypes.c_void_p(accept_prev_ptr or None), ctypes.c_void_p(k_ptr),
+                                   ctypes.c_void_p(new_pos_ptr), ctypes.c_void_p(delta_ptr),
+                                   ctypes.c_void_p(djastrow_ptr or None), ctypes.c_void_p(jgrad_ptr or None),
+                                   ctypes.c_void_p(jlap_ptr or None), ctypes.c_void_p(stream or None)))
+
+
 def ewald_run_moves_grad_batch(batch_h, state_ptr, n_steps, k_ptr, new_pos_ptr, accept_ptr, delta_ptr,
                                djastrow_ptr=0, jgrad_ptr=0, jlap_ptr=0, stream=0) -> None:
     _check(load().ewald_run_moves_grad_batch(ctypes.c_void_p(batch_h), ctypes.c_void_p(state_ptr), int(n_steps),
@@ -378,6 +388,12 @@ class Batch:
     def accept(self, accept):
         ewald_accept_batch(self.handle, self.state.data_ptr(), accept.data_ptr(), self.stream())
 
+    def step(self, accept_prev, k, new_pos, delta, djastrow=None, jgrad=None, jlap=None):
+        ewald_step_batch(self.handle, self.state.data_ptr(), 0 if accept_prev is None else accept_prev.data_ptr(),
+                         k.data_ptr(), new_pos.data_ptr(), delta.data_ptr(),
+                         0 if djastrow is None else djastrow.data_ptr(), 0 if jgrad is None else jgrad.data_ptr(),
+                         0 if jlap is None else jlap.data_ptr(), self.stream())
+
     def run_moves(self, k, new_pos, accept, delta, djastrow=None):
         ewald_run_moves_batch(self.handle, self.state.data_ptr(), int(k.shape[0]), k.data_ptr(),
                               new_pos.data_ptr(), accept.data_ptr(), delta.data_ptr(),
@@ -403,10 +419,12 @@ class Batch:
     def autotune(self, n_moves=32, cache_path=None):
         ewald_autotune(self.handle, self.state.data_ptr(), n_moves, cache_path, self.stream())
 
-    def walker_rho(self, w: int) -> np.ndarray:
-        """rho of walker w (valid and padding slots) as complex numpy, after a sync."""
+    def walker_rho(self, w: int, plane: int = 0) -> np.ndarray:
+        """rho of walker w (valid and padding slots) as complex numpy, after a
+        sync; plane 1: a layered system's second plane (stored after the first)."""
         _, _, r = ewald_state_offsets(self.handle, w)
         ns = self.systems[self.walker_sys[w]].info["n_slots"]
+        r += plane * ns * 16
         raw = self.state[r: r + ns * 16].cpu().numpy().view(np.float64)
         return raw[0::2] + 1j * raw[1::2]
 

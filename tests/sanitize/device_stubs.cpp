@@ -19,6 +19,10 @@ int launch_delta(const LaunchBatch&, char*, const int32_t*, const double*, doubl
   return kNoDevice;
 }
 int launch_accept(const LaunchBatch&, char*, const uint8_t*, void*) { return kNoDevice; }
+int launch_step(const LaunchBatch&, char*, const uint8_t*, const int32_t*, const double*, double*, double*, double*,
+                double*, void*) {
+  return kNoDevice;
+}
 int launch_run(const LaunchBatch&, char*, int, const int32_t*, const double*, const uint8_t*, double*, double*,
                double*, double*, void*) {
   return kNoDevice;

@@ -88,6 +88,17 @@ class Case:
         torch.cuda.synchronize()
         return d.cpu().numpy(), dj.cpu().numpy()
 
+    def stepped(self):
+        """The same sequence through the step call: each move's accept folded
+        into the next move's delta, the last one through the accept call."""
+        d = torch.zeros((self.S, self.W), dtype=torch.float64, device="cuda")
+        dj = torch.zeros_like(d)
+        for m in range(self.S):
+            self.batch.step(self.accept[m - 1] if m else None, self.k[m], self.new_pos[m], d[m], dj[m])
+        self.batch.accept(self.accept[self.S - 1])
+        torch.cuda.synchronize()
+        return d.cpu().numpy(), dj.cpu().numpy()
+
     def fused(self, steps=None):
         S = self.S if steps is None else steps
         d = torch.zeros((S, self.W), dtype=torch.float64, device="cuda")
@@ -717,7 +728,7 @@ def test_n1024_long_sweep_with_rebuilds(oracle_lib, precision):
     element."""
     W, S = 2, 280
     refs = None
-    for path in ("per-step", 1024, 512):
+    for path in ("per-step", "step", 1024, 512):
         say(f"[n1024 long] precision={precision} path={path}")
         c = Case(5, W, S, precision)
         if refs is None:
@@ -725,6 +736,8 @@ def test_n1024_long_sweep_with_rebuilds(oracle_lib, precision):
         e0, j0 = c.run_energy()
         if path == "per-step":
             d, dj = c.per_step()
+        elif path == "step":
+            d, dj = c.stepped()
         else:
             c.batch.set_tuning(threads=path)
             assert c.batch.tuning()["threads"] == path and c.batch.tuning()["fused"] == 1
@@ -1066,3 +1079,185 @@ def test_layers_with_ions_and_telescoping(oracle_lib, precision):
         e_fin = oracle_lib.energy(sysm, *oracle_lib.particles(sysm, fin))["total"]
         tel = e0[w] + float(np.sum(dd[acc[:, w].astype(bool), w]))
         assert abs(tel - e_fin) <= (1e-10 * scale if precision == FP64 else 1e-6 * scale + 1e-5 * S)
+
+
+# The step call (the previous move's accept folded into the next delta)
+# against the two-call sequence move_delta + accept: the same arithmetic in
+# the same order, so every output and the whole final state agree bit for bit.
+def same_state(a, b, W):
+    for w in range(W):
+        ha, hb = a.batch.walker_header(w), b.batch.walker_header(w)
+        for key in ("counter", "pending_k", "n_accepts", "n_refresh", "drift_max"):
+            assert ha[key] == hb[key], (w, key, ha[key], hb[key])
+        assert np.array_equal(a.batch.walker_positions(w), b.batch.walker_positions(w)), w
+        assert np.array_equal(a.batch.walker_rho(w), b.batch.walker_rho(w)), w
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [1, 2, 3, 4, 5])
+def test_step_matches_two_calls(cfg_id, precision):
+    W, S, w0 = SUBSETS[cfg_id]
+    S = max(S, 12)
+    say(f"[step vs two calls] cfg={cfg_id} precision={precision} walkers={W} steps={S}")
+    # K = 3: the mixed form rebuilds rho (and recomputes the folded deltas) often
+    a = Case(cfg_id, W, S, precision, walker_start=w0, refresh_every=3)
+    a.run_energy()
+    d1, j1 = a.per_step()
+    b = Case(cfg_id, W, S, precision, walker_start=w0, refresh_every=3)
+    b.run_energy()
+    d2, j2 = b.stepped()
+    assert np.array_equal(d1, d2) and np.array_equal(j1, j2)
+    same_state(a, b, W)
+    if precision == MIXED:
+        assert any(a.batch.walker_header(w)["n_refresh"] > 0 for w in range(W))
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [1, 5])
+def test_step_vs_oracle(oracle_lib, cfg_id, precision):
+    """Step-call deltas and Jastrow deltas against the oracle, telescoped
+    energy against a fresh energy of the final positions."""
+    W, S, w0 = SUBSETS[cfg_id]
+    say(f"[step vs oracle] cfg={cfg_id} precision={precision}")
+    c = Case(cfg_id, W, S, precision, walker_start=w0)
+    e0, _ = c.run_energy()
+    d, dj = c.stepped()
+    for w in range(W):
+        r = c.oracle(oracle_lib, w)
+        scale = max(abs(r["energy0"]), e_scale(c.system(w)))
+        if precision == FP64:
+            assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale
+            assert np.max(np.abs(dj[:, w] - r["djas"])) <= 1e-10 * max(1.0, abs(r["j0"]))
+        else:
+            assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5
+            assert np.max(np.abs(dj[:, w] - r["djas"])) <= djas_bound(c, w)
+        fin = c.batch.walker_positions(w) @ c.system(w).lattice[: c.dim, : c.dim]
+        e_fin = oracle_lib.energy(c.system(w), *oracle_lib.particles(c.system(w), fin))["total"]
+        tel = e0[w] + float(np.sum(d[c.b.accept[:, w].astype(bool), w]))
+        assert abs(tel - e_fin) <= (1e-10 * scale if precision == FP64 else 1e-6 * scale + 1e-5 * S)
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("u_term", [False, True], ids=["p", "p+u"])
+def test_step_grad_matches_two_calls(precision, u_term):
+    """Jastrow gradient and Laplacian outputs of the step call against
+    move_delta_grad + accept (and the u term's pair loop with the accepted
+    particle taken from the pending record)."""
+    cfg_id = 2
+    W, S = 2, 12
+    say(f"[step grad] precision={precision} u_term={u_term}")
+    outs = []
+    for path in ("two calls", "step"):
+        c = Case(cfg_id, W, S, precision, refresh_every=3, u_term=u_term)
+        c.run_energy()
+        d = torch.zeros((S, W), dtype=torch.float64, device="cuda")
+        dj = torch.zeros_like(d)
+        g = torch.zeros((S, W, c.dim), dtype=torch.float64, device="cuda")
+        lp = torch.zeros_like(d)
+        for m in range(S):
+            if path == "two calls":
+                c.batch.move_delta_grad(c.k[m], c.new_pos[m], d[m], dj[m], g[m], lp[m])
+                c.batch.accept(c.accept[m])
+            else:
+                c.batch.step(c.accept[m - 1] if m else None, c.k[m], c.new_pos[m], d[m], dj[m], g[m], lp[m])
+        if path == "step":
+            c.batch.accept(c.accept[S - 1])
+        torch.cuda.synchronize()
+        outs.append((c, [x.cpu().numpy() for x in (d, dj, g, lp)]))
+    (a, ra), (b, rb) = outs
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y)
+    same_state(a, b, W)
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_step_bilayer_matches_two_calls(precision):
+    """Layered system: an accepted move in either plane folded into a delta
+    of a particle in the same or the other plane."""
+    say(f"[step bilayer] precision={precision}")
+    base = wl.bilayer(6, 2.2)
+    sysm = dataclasses.replace(base, n_mobile=9, mobile_q=np.array([-1.0] * 5 + [1.0] * 4),
+                               mobile_layer=np.array([0] * 5 + [1] * 4, dtype=np.int32),
+                               fixed_pos=np.array([[3.0, 4.0], [40.0, 17.0]]), fixed_q=np.array([1.0, -0.5]),
+                               fixed_layer=np.array([1, 0], dtype=np.int32))
+    rng = np.random.default_rng(78)
+    lat = sysm.lattice[:2, :2]
+    W, S = 3, 24
+    pos = np.concatenate([rng.random((9, 2)) @ lat for _ in range(W)])
+    k = rng.integers(0, 9, (S, W)).astype(np.int32)
+    newp = rng.random((S, W, 2)) @ lat
+    acc = (rng.random((S, W)) < 0.6).astype(np.uint8)
+    dev = "cuda"
+    kt, nt, at = (torch.tensor(x, device=dev) for x in (k, newp, acc))
+    h = ew.System(sysm, precision=precision, refresh_every=2 if precision == MIXED else 0)
+    res = []
+    for path in ("two calls", "step"):
+        b = ew.Batch([h], np.zeros(W, dtype=np.int32))
+        b.energy(torch.tensor(pos, device=dev), torch.zeros(W, dtype=torch.float64, device=dev))
+        d = torch.zeros((S, W), dtype=torch.float64, device=dev)
+        for m in range(S):
+            if path == "two calls":
+                b.move_delta(kt[m], nt[m], d[m])
+                b.accept(at[m])
+            else:
+                b.step(at[m - 1] if m else None, kt[m], nt[m], d[m])
+        if path == "step":
+            b.accept(at[S - 1])
+        torch.cuda.synchronize()
+        res.append((b, d.cpu().numpy()))
+    (ba, da), (bb, db) = res
+    assert np.array_equal(da, db)
+    for w in range(W):
+        assert np.array_equal(ba.walker_positions(w), bb.walker_positions(w))
+        for plane in (0, 1):
+            assert np.array_equal(ba.walker_rho(w, plane), bb.walker_rho(w, plane))
+        ha, hb = ba.walker_header(w), bb.walker_header(w)
+        assert all(np.array_equal(ha[x], hb[x]) for x in ha), (ha, hb)
+
+
+def test_step_invalid_k_still_applies_accept():
+    """A step whose new move has an invalid particle index gives NaN for it
+    but still applies the previous move's accept (as accept + move_delta)."""
+    say("[step invalid k]")
+    res = []
+    for path in ("two calls", "step"):
+        c = Case(2, 3, 2, FP64)
+        c.run_energy()
+        d = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+        ones = torch.ones(3, dtype=torch.uint8, device="cuda")
+        bad = torch.tensor([-1, 1, 250], dtype=torch.int32, device="cuda")
+        if path == "two calls":
+            c.batch.move_delta(c.k[0], c.new_pos[0], d[0])
+            c.batch.accept(ones)
+            c.batch.move_delta(bad, c.new_pos[1], d[1])
+        else:
+            c.batch.step(None, c.k[0], c.new_pos[0], d[0])
+            c.batch.step(ones, bad, c.new_pos[1], d[1])
+        c.batch.accept(ones)
+        torch.cuda.synchronize()
+        res.append((c, d.cpu().numpy()))
+    (a, da), (b, db) = res
+    assert np.isnan(db[1, 0]) and np.isfinite(db[1, 1]) and np.isnan(db[1, 2])
+    assert np.array_equal(da, db, equal_nan=True)
+    same_state(a, b, 3)
+    assert b.batch.walker_header(0)["n_accepts"] == 1 and b.batch.walker_header(1)["n_accepts"] == 2
+
+
+def test_step_call_order():
+    say("[step call order]")
+    c = Case(1, 1, 3, FP64)
+    d = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ew.EwaldError) as e:
+        c.batch.step(None, c.k[0], c.new_pos[0], d)
+    assert e.value.status == ew.EWALD_E_STATE
+    c.run_energy()
+    with pytest.raises(ew.EwaldError) as e:  # nothing pending to accept
+        c.batch.step(c.accept[0], c.k[0], c.new_pos[0], d)
+    assert e.value.status == ew.EWALD_E_STATE
+    c.batch.step(None, c.k[0], c.new_pos[0], d)
+    c.batch.step(c.accept[0], c.k[1], c.new_pos[1], d)
+    with pytest.raises(ew.EwaldError) as e:  # a move is pending
+        c.fused(1)
+    assert e.value.status == ew.EWALD_E_STATE
+    c.batch.accept(c.accept[1])
+    c.fused(1)

@@ -725,6 +725,8 @@ def main():
                         "roofline": f["roofline"], "energies_per_s": round(f["energies_per_s"], 1),
                         "per_step_path_deltas_per_s": round(f["per_step"]["step"]["deltas_per_s"], 1),
                         "per_step": f["per_step"], "parity": f.get("parity")}
+    if os.environ.get("EWALD_TIMING", "0") not in ("", "0"):
+        line["call_timers"] = ew.ewald_timing_report()  # per ABI call, over the whole run (warm-up included)
     print(json.dumps(line), flush=True)
     if not parity_ok:
         print("bench.py: GPU results differ from the oracle beyond the stated bounds", file=sys.stderr)

@@ -380,6 +380,26 @@ void ewald_blip_destroy(ewald_blip *b);
 ewald_status ewald_blip_eval_batch(const ewald_blip *b, const double *coef, int n_points, const double *pos,
                                    double *val, double *grad, double *lap, void *stream);
 
+/* Per-call timers (the role of the paper's subroutine timers, Sec. 3.2:
+ * invocations and times per activity, reported at the end of a run).  When
+ * on, every call that enqueues GPU work (ewald_energy_batch, the move-delta,
+ * accept, step and run-moves calls, ewald_autotune, ewald_blip_eval_batch)
+ * counts an invocation, its host time, and the GPU time between two events
+ * recorded on its stream around the work it enqueues (not recorded while the
+ * stream is being captured into a graph).  The events are read only when a
+ * report is made, so timing adds no synchronisation to the calls.  Initially
+ * on iff the environment variable EWALD_TIMING is set to a value other than
+ * "0"; process-wide.
+ *   ewald_timing_enable: on (!= 0) or off; always EWALD_OK
+ *   ewald_timing_report: waits for the recorded events, then writes one
+ *     header line and one line per call name,
+ *       "<call> <calls> <gpu_calls> <gpu_ms_total> <gpu_ms_mean> <host_ms_total>",
+ *     NUL-terminated, into buf (len bytes, caller-owned); reset != 0 clears
+ *     the counts afterwards.  E_ARG if buf is NULL with len > 0, or if the
+ *     report did not fit (it is then truncated). */
+ewald_status ewald_timing_enable(int on);
+ewald_status ewald_timing_report(char *buf, size_t len, int reset);
+
 /* Thread-local message for the last non-OK status of this thread. */
 const char *ewald_last_error(void);
 

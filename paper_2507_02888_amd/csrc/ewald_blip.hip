@@ -24,6 +24,7 @@
 #include <string>
 
 #include "ewald.h"
+#include "ewald_internal.h"
 
 namespace ewald {
 // thread-local message shared with the rest of the library
@@ -234,6 +235,7 @@ void ewald_blip_destroy(ewald_blip* b) { delete b; }
 
 ewald_status ewald_blip_eval_batch(const ewald_blip* b, const double* coef, int n_points, const double* pos,
                                    double* val, double* grad, double* lap, void* stream) {
+  ewald::CallTimer timer("ewald_blip_eval_batch", stream);
   if (!b) {
     ewald::set_last_error("blip handle is NULL");
     return EWALD_E_ARG;

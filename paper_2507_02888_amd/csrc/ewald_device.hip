@@ -22,6 +22,8 @@
 // kernels, the fused kernel's dispatch, and the device memory helpers; the
 // fused kernels themselves are compiled in ewald_run_d*.hip.
 
+#include <new>
+
 #include "ewald_run.h"
 
 namespace ewald {
@@ -874,6 +876,47 @@ int time_run(const LaunchBatch& b, char* state, int n_steps, const int32_t* k, c
   (void)hipEventDestroy(e1);
   *best_ms = best;
   return rc;
+}
+
+int event_pair_create(void** pair) {
+  hipEvent_t* e = new (std::nothrow) hipEvent_t[2];
+  if (!e) return int(hipErrorOutOfMemory);
+  hipError_t r = hipEventCreate(&e[0]);
+  if (r == hipSuccess) {
+    r = hipEventCreate(&e[1]);
+    if (r != hipSuccess) (void)hipEventDestroy(e[0]);
+  }
+  if (r != hipSuccess) {
+    delete[] e;
+    return int(r);
+  }
+  *pair = e;
+  return 0;
+}
+
+int event_pair_record(void* pair, int which, void* stream) {
+  return int(hipEventRecord(static_cast<hipEvent_t*>(pair)[which], as_stream(stream)));
+}
+
+int event_pair_elapsed(void* pair, float* ms) {
+  hipEvent_t* e = static_cast<hipEvent_t*>(pair);
+  hipError_t r = hipEventSynchronize(e[1]);
+  if (r == hipSuccess) r = hipEventElapsedTime(ms, e[0], e[1]);
+  return int(r);
+}
+
+void event_pair_destroy(void* pair) {
+  hipEvent_t* e = static_cast<hipEvent_t*>(pair);
+  (void)hipEventDestroy(e[0]);
+  (void)hipEventDestroy(e[1]);
+  delete[] e;
+}
+
+int stream_capturing(void* stream, int* capturing) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  hipError_t r = hipStreamIsCapturing(as_stream(stream), &st);
+  *capturing = st != hipStreamCaptureStatusNone;
+  return int(r);
 }
 
 int stream_sync(void* stream) {

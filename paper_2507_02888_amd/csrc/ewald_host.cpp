@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -373,9 +374,135 @@ struct ewald_batch {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Per-call timers: invocations, host time and GPU time per ABI call, reported
+// on request (the role of the paper's subroutine timers, Sec. 3.2).  GPU
+// times come from event pairs resolved lazily (at a report, or when many are
+// pending), so timing adds no synchronisation to the calls themselves.
+namespace {
+
+struct TimingRec {
+  long calls = 0, gpu_calls = 0;
+  double host_ms = 0.0, gpu_ms = 0.0;
+};
+
+struct TimingState {
+  std::mutex mu;
+  int on = -1;  // -1: EWALD_TIMING not read yet
+  std::map<std::string, TimingRec> recs;
+  std::vector<std::pair<std::string, void*>> pending;  // recorded event pairs
+  std::vector<void*> pool;                             // free event pairs
+};
+
+TimingState& timing_state() {
+  static TimingState* t = new TimingState;  // never destroyed: calls may come during exit
+  return *t;
+}
+
+bool timing_on(TimingState& t) {
+  if (t.on < 0) {
+    const char* e = std::getenv("EWALD_TIMING");
+    t.on = (e && *e && std::strcmp(e, "0") != 0) ? 1 : 0;
+  }
+  return t.on == 1;
+}
+
+void timing_resolve(TimingState& t) {
+  for (auto& p : t.pending) {
+    float ms = 0.f;
+    if (event_pair_elapsed(p.second, &ms) == 0) {
+      TimingRec& r = t.recs[p.first];
+      r.gpu_ms += ms;
+      r.gpu_calls += 1;
+    }
+    t.pool.push_back(p.second);
+  }
+  t.pending.clear();
+}
+
+double host_now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+namespace ewald {
+
+CallTimer::CallTimer(const char* name, void* stream) : name_(name), stream_(stream) {
+  TimingState& t = timing_state();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (!timing_on(t)) return;
+  on_ = true;
+  t0_ = host_now_ms();
+  int capturing = 0;
+  if (stream_capturing(stream, &capturing) != 0 || capturing) return;  // no events inside a graph capture
+  if (t.pool.empty()) {
+    void* p = nullptr;
+    if (event_pair_create(&p) == 0) t.pool.push_back(p);
+  }
+  if (t.pool.empty()) return;
+  pair_ = t.pool.back();
+  t.pool.pop_back();
+  if (event_pair_record(pair_, 0, stream) != 0) {
+    t.pool.push_back(pair_);
+    pair_ = nullptr;
+  }
+}
+
+CallTimer::~CallTimer() {
+  if (!on_) return;
+  const double host = host_now_ms() - t0_;
+  TimingState& t = timing_state();
+  std::lock_guard<std::mutex> lk(t.mu);
+  TimingRec& r = t.recs[name_];
+  r.calls += 1;
+  r.host_ms += host;
+  if (pair_) {
+    if (event_pair_record(pair_, 1, stream_) == 0)
+      t.pending.emplace_back(name_, pair_);
+    else
+      t.pool.push_back(pair_);
+  }
+  if (t.pending.size() >= 4096) timing_resolve(t);
+}
+
+}  // namespace ewald
+
 extern "C" {
 
 const char* ewald_last_error(void) { return g_last_error.c_str(); }
+
+ewald_status ewald_timing_enable(int on) {
+  TimingState& t = timing_state();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.on = on ? 1 : 0;
+  return EWALD_OK;
+}
+
+ewald_status ewald_timing_report(char* buf, size_t len, int reset) {
+  if (!buf && len > 0) return fail(EWALD_E_ARG, "buf is NULL");
+  TimingState& t = timing_state();
+  std::lock_guard<std::mutex> lk(t.mu);
+  timing_resolve(t);
+  std::string out = "call calls gpu_calls gpu_ms_total gpu_ms_mean host_ms_total\n";
+  for (const auto& kv : t.recs) {
+    const TimingRec& r = kv.second;
+    char line[256];
+    std::snprintf(line, sizeof line, "%s %ld %ld %.6f %.6f %.6f\n", kv.first.c_str(), r.calls, r.gpu_calls,
+                  r.gpu_ms, r.gpu_calls ? r.gpu_ms / double(r.gpu_calls) : 0.0, r.host_ms);
+    out += line;
+  }
+  if (reset) t.recs.clear();
+  if (len > 0) {
+    const size_t n = std::min(out.size(), len - 1);
+    std::memcpy(buf, out.data(), n);
+    buf[n] = '\0';
+    if (out.size() >= len) return fail(EWALD_E_ARG, "buf too small for the report (" + std::to_string(out.size() + 1) +
+                                                     " bytes needed); truncated");
+  }
+  return EWALD_OK;
+}
 
 ewald_status ewald_setup(const ewald_sys_desc* desc, ewald_sys** out) try {
   if (!out) return fail(EWALD_E_ARG, "out is NULL");
@@ -1134,6 +1261,7 @@ void ewald_batch_destroy(ewald_batch* b) { delete b; }
 
 ewald_status ewald_energy_batch(ewald_batch* b, const double* pos, void* state, double* energy,
                                 double* jastrow, void* stream) {
+  CallTimer timer("ewald_energy_batch", stream);
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (!pos || !state || !energy) return fail(EWALD_E_ARG, "pos, state and energy must be non-NULL");
   int rc = launch_energy(b->lb, pos, static_cast<char*>(state), energy, jastrow, stream);
@@ -1144,6 +1272,7 @@ ewald_status ewald_energy_batch(ewald_batch* b, const double* pos, void* state, 
 ewald_status ewald_move_delta_grad_batch(ewald_batch* b, void* state, const int32_t* k, const double* new_pos,
                                          double* delta, double* djastrow, double* jgrad, double* jlap,
                                          void* stream) {
+  CallTimer timer(jgrad ? "ewald_move_delta_grad_batch" : "ewald_move_delta_batch", stream);
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (!state || !k || !new_pos || !delta) return fail(EWALD_E_ARG, "state, k, new_pos and delta must be non-NULL");
   if ((jgrad == nullptr) != (jlap == nullptr)) return fail(EWALD_E_ARG, "jgrad and jlap must both be given or both NULL");
@@ -1162,6 +1291,7 @@ ewald_status ewald_move_delta_batch(ewald_batch* b, void* state, const int32_t* 
 }
 
 ewald_status ewald_accept_batch(ewald_batch* b, void* state, const uint8_t* accept, void* stream) {
+  CallTimer timer("ewald_accept_batch", stream);
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (!state || !accept) return fail(EWALD_E_ARG, "state and accept must be non-NULL");
   ewald_status st = check_state(b, state, 2, -1);
@@ -1174,6 +1304,7 @@ ewald_status ewald_accept_batch(ewald_batch* b, void* state, const uint8_t* acce
 ewald_status ewald_step_batch(ewald_batch* b, void* state, const uint8_t* accept_prev, const int32_t* k,
                               const double* new_pos, double* delta, double* djastrow, double* jgrad, double* jlap,
                               void* stream) {
+  CallTimer timer("ewald_step_batch", stream);
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (!state || !k || !new_pos || !delta) return fail(EWALD_E_ARG, "state, k, new_pos and delta must be non-NULL");
   if ((jgrad == nullptr) != (jlap == nullptr)) return fail(EWALD_E_ARG, "jgrad and jlap must both be given or both NULL");
@@ -1189,6 +1320,7 @@ ewald_status ewald_step_batch(ewald_batch* b, void* state, const uint8_t* accept
 ewald_status ewald_run_moves_grad_batch(ewald_batch* b, void* state, int n_steps, const int32_t* k,
                                         const double* new_pos, const uint8_t* accept, double* delta,
                                         double* djastrow, double* jgrad, double* jlap, void* stream) {
+  CallTimer timer(jgrad ? "ewald_run_moves_grad_batch" : "ewald_run_moves_batch", stream);
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (n_steps < 0) return fail(EWALD_E_ARG, "n_steps must be >= 0");
   if (!state) return fail(EWALD_E_ARG, "state must be non-NULL");
@@ -1281,6 +1413,7 @@ bool cache_lookup(const char* path, const std::string& key, int* t, int* c, int*
 }  // namespace
 
 ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char* cache_path, void* stream) {
+  CallTimer timer("ewald_autotune", stream);
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   if (!state) return fail(EWALD_E_ARG, "state must be non-NULL");
   if (n_moves < 1 || n_moves > 4096) return fail(EWALD_E_ARG, "n_moves must be in [1, 4096]");

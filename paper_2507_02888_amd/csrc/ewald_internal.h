@@ -226,4 +226,30 @@ int dev_memset(void* p, int value, size_t bytes);
 int dev_copy(void* dst, const void* src, size_t bytes);  // device to device, synchronous
 int stream_sync(void* stream);  // waits for the work queued on `stream`
 
+// Event pairs for the per-call timers (ewald_device.hip); return 0 on success.
+int event_pair_create(void** pair);
+int event_pair_record(void* pair, int which, void* stream);  // which: 0 start, 1 end
+int event_pair_elapsed(void* pair, float* ms);                // waits for the end event
+void event_pair_destroy(void* pair);
+int stream_capturing(void* stream, int* capturing);
+
+// Per-call timer (enabled by EWALD_TIMING=1 or ewald_timing_enable): counts
+// the call, its host time and, outside graph capture, the GPU time between
+// two events recorded on its stream around it.  One per ABI call that
+// launches work, constructed first thing in the call.
+class CallTimer {
+ public:
+  CallTimer(const char* name, void* stream);
+  ~CallTimer();
+  CallTimer(const CallTimer&) = delete;
+  CallTimer& operator=(const CallTimer&) = delete;
+
+ private:
+  const char* name_;
+  void* stream_;
+  void* pair_ = nullptr;
+  bool on_ = false;
+  double t0_ = 0.0;
+};
+
 }  // namespace ewald

@@ -32,7 +32,7 @@ EXPORTS = ("ewald_setup", "ewald_sys_query", "ewald_sys_tables", "ewald_sys_cand
            "ewald_accept_batch", "ewald_run_moves_batch", "ewald_move_delta_grad_batch",
            "ewald_run_moves_grad_batch", "ewald_step_batch", "ewald_batch_set_tuning",
            "ewald_batch_get_tuning", "ewald_autotune", "ewald_blip_create", "ewald_blip_destroy",
-           "ewald_blip_eval_batch", "ewald_last_error")
+           "ewald_blip_eval_batch", "ewald_timing_enable", "ewald_timing_report", "ewald_last_error")
 
 
 class EwaldError(RuntimeError):
@@ -94,6 +94,8 @@ def load() -> ctypes.CDLL:
     lib.ewald_blip_destroy.argtypes = [vp]
     lib.ewald_blip_destroy.restype = None
     lib.ewald_blip_eval_batch.argtypes = [vp, vp, c_int, vp, vp, vp, vp, vp]
+    lib.ewald_timing_enable.argtypes = [c_int]
+    lib.ewald_timing_report.argtypes = [ctypes.c_char_p, c_size, c_int]
     lib.ewald_last_error.argtypes = []
     lib.ewald_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -287,6 +289,23 @@ def ewald_step_batch(batch_h, state_ptr, accept_prev_ptr, k_ptr, new_pos_ptr, de
                                    ctypes.c_void_p(new_pos_ptr), ctypes.c_void_p(delta_ptr),
                                    ctypes.c_void_p(djastrow_ptr or None), ctypes.c_void_p(jgrad_ptr or None),
                                    ctypes.c_void_p(jlap_ptr or None), ctypes.c_void_p(stream or None)))
+
+
+def ewald_timing_enable(on: bool) -> None:
+    _check(load().ewald_timing_enable(1 if on else 0))
+
+
+def ewald_timing_report(reset: bool = False) -> dict:
+    """The per-call timer table: {call: {calls, gpu_calls, gpu_ms_total,
+    gpu_ms_mean, host_ms_total}}."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().ewald_timing_report(buf, len(buf), 1 if reset else 0))
+    out = {}
+    for line in buf.value.decode().splitlines()[1:]:
+        name, calls, gcalls, gms, gmean, hms = line.split()
+        out[name] = dict(calls=int(calls), gpu_calls=int(gcalls), gpu_ms_total=float(gms),
+                         gpu_ms_mean=float(gmean), host_ms_total=float(hms))
+    return out
 
 
 def ewald_run_moves_grad_batch(batch_h, state_ptr, n_steps, k_ptr, new_pos_ptr, accept_ptr, delta_ptr,

@@ -49,5 +49,19 @@ int dev_arch(char* buf, int len) {
 int dev_memset(void*, int, size_t) { return kNoDevice; }
 int dev_copy(void*, const void*, size_t) { return kNoDevice; }
 int stream_sync(void*) { return kNoDevice; }
+int event_pair_create(void** pair) {
+  *pair = nullptr;
+  return kNoDevice;
+}
+int event_pair_record(void*, int, void*) { return kNoDevice; }
+int event_pair_elapsed(void*, float* ms) {
+  *ms = 0.f;
+  return kNoDevice;
+}
+void event_pair_destroy(void*) {}
+int stream_capturing(void*, int* capturing) {
+  *capturing = 0;
+  return 0;
+}
 
 }  // namespace ewald

@@ -230,6 +230,21 @@ int main() {
   ewald_sys* s = nullptr;
   CHECK(ewald_setup(nullptr, &s) == EWALD_E_ARG);
   CHECK(std::strlen(ewald_last_error()) > 0);
+  // per-call timers: bookkeeping of calls that fail before any launch
+  CHECK(ewald_timing_enable(1) == EWALD_OK);
+  for (int i = 0; i < 3; ++i) CHECK(ewald_energy_batch(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == EWALD_E_ARG);
+  CHECK(ewald_accept_batch(nullptr, nullptr, nullptr, nullptr) == EWALD_E_ARG);
+  char rep[512];
+  CHECK(ewald_timing_report(rep, sizeof rep, 1) == EWALD_OK);
+  CHECK(std::strstr(rep, "ewald_energy_batch 3 0 ") != nullptr);
+  CHECK(std::strstr(rep, "ewald_accept_batch 1 0 ") != nullptr);
+  CHECK(ewald_timing_report(rep, sizeof rep, 0) == EWALD_OK);
+  CHECK(std::strstr(rep, "ewald_energy_batch") == nullptr);  // reset
+  CHECK(ewald_accept_batch(nullptr, nullptr, nullptr, nullptr) == EWALD_E_ARG);
+  char small[8];
+  CHECK(ewald_timing_report(small, sizeof small, 0) == EWALD_E_ARG && std::strlen(small) == 7);
+  CHECK(ewald_timing_report(nullptr, 4, 0) == EWALD_E_ARG);
+  CHECK(ewald_timing_enable(0) == EWALD_OK);
   if (failures) {
     std::fprintf(stderr, "%d checks failed\n", failures);
     return 1;

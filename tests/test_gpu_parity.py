@@ -1261,3 +1261,51 @@ def test_step_call_order():
     assert e.value.status == ew.EWALD_E_STATE
     c.batch.accept(c.accept[1])
     c.fused(1)
+
+
+def test_call_timers():
+    """Per-call timers: invocation counts per call name, GPU times from event
+    pairs around the enqueued work (positive, and within the wall time of the
+    calls), nothing recorded on the GPU for a call made during graph capture,
+    and reset."""
+    say("[timers]")
+    ew.ewald_timing_report(reset=True)
+    ew.ewald_timing_enable(True)
+    try:
+        c = Case(2, 4, 6, FP64)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        c.run_energy()
+        d = torch.zeros((6, 4), dtype=torch.float64, device="cuda")
+        for m in range(2):
+            c.batch.move_delta(c.k[m], c.new_pos[m], d[m])
+            c.batch.accept(c.accept[m])
+        for m in range(2, 5):
+            c.batch.step(c.accept[m - 1] if m > 2 else None, c.k[m], c.new_pos[m], d[m])
+        c.batch.accept(c.accept[4])
+        t1.record()
+        torch.cuda.synchronize()
+        wall = t0.elapsed_time(t1)
+        rep = ew.ewald_timing_report()
+        assert rep["ewald_energy_batch"]["calls"] == 1
+        assert rep["ewald_move_delta_batch"]["calls"] == 2
+        assert rep["ewald_accept_batch"]["calls"] == 3
+        assert rep["ewald_step_batch"]["calls"] == 3
+        for name, r in rep.items():
+            assert r["gpu_calls"] == r["calls"], name
+            assert r["gpu_ms_total"] > 0.0 and r["host_ms_total"] >= 0.0, name
+        assert sum(r["gpu_ms_total"] for r in rep.values()) <= wall * 1.01 + 0.05
+        # a call captured into a graph is counted without GPU events
+        k_buf, np_buf, d_buf = c.k[5].clone(), c.new_pos[5].clone(), torch.zeros(4, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            c.batch.move_delta(k_buf, np_buf, d_buf)
+        torch.cuda.synchronize()
+        rep = ew.ewald_timing_report(reset=True)
+        assert rep["ewald_move_delta_batch"]["calls"] == 3 and rep["ewald_move_delta_batch"]["gpu_calls"] == 2
+        assert ew.ewald_timing_report() == {}
+    finally:
+        ew.ewald_timing_enable(False)
+        ew.ewald_timing_report(reset=True)

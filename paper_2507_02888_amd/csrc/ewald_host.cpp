@@ -429,42 +429,62 @@ double host_now_ms() {
 
 namespace ewald {
 
-CallTimer::CallTimer(const char* name, void* stream) : name_(name), stream_(stream) {
-  TimingState& t = timing_state();
-  std::lock_guard<std::mutex> lk(t.mu);
-  if (!timing_on(t)) return;
-  on_ = true;
-  t0_ = host_now_ms();
-  int capturing = 0;
-  if (stream_capturing(stream, &capturing) != 0 || capturing) return;  // no events inside a graph capture
-  if (t.pool.empty()) {
-    void* p = nullptr;
-    if (event_pair_create(&p) == 0) t.pool.push_back(p);
-  }
-  if (t.pool.empty()) return;
-  pair_ = t.pool.back();
-  t.pool.pop_back();
-  if (event_pair_record(pair_, 0, stream) != 0) {
-    t.pool.push_back(pair_);
-    pair_ = nullptr;
+// Timing never fails a call: an allocation failure here only loses the
+// record (the guard's constructor and destructor catch everything).
+CallTimer::CallTimer(const char* name, void* stream) noexcept : name_(name), stream_(stream) {
+  try {
+    TimingState& t = timing_state();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!timing_on(t)) return;
+    on_ = true;
+    t0_ = host_now_ms();
+    int capturing = 0;
+    if (stream_capturing(stream, &capturing) != 0 || capturing) return;  // no events inside a graph capture
+    if (t.pool.empty()) {
+      void* p = nullptr;
+      if (event_pair_create(&p) == 0) {
+        try {
+          t.pool.push_back(p);
+        } catch (...) {
+          event_pair_destroy(p);
+          throw;
+        }
+      }
+    }
+    if (t.pool.empty()) return;
+    pair_ = t.pool.back();
+    t.pool.pop_back();
+    if (event_pair_record(pair_, 0, stream) != 0) {
+      t.pool.push_back(pair_);  // capacity is there: the pair was just taken out
+      pair_ = nullptr;
+    }
+  } catch (...) {
+    // no record for this call's GPU time; a taken event pair is not leaked
+    // (only the push into an empty pool can throw, before any pair is taken)
   }
 }
 
 CallTimer::~CallTimer() {
   if (!on_) return;
-  const double host = host_now_ms() - t0_;
-  TimingState& t = timing_state();
-  std::lock_guard<std::mutex> lk(t.mu);
-  TimingRec& r = t.recs[name_];
-  r.calls += 1;
-  r.host_ms += host;
-  if (pair_) {
-    if (event_pair_record(pair_, 1, stream_) == 0)
-      t.pending.emplace_back(name_, pair_);
-    else
-      t.pool.push_back(pair_);
+  try {
+    const double host = host_now_ms() - t0_;
+    TimingState& t = timing_state();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (pair_) {
+      if (event_pair_record(pair_, 1, stream_) == 0) {
+        t.pending.emplace_back(name_, pair_);
+      } else {
+        t.pool.push_back(pair_);
+      }
+      pair_ = nullptr;
+    }
+    TimingRec& r = t.recs[name_];
+    r.calls += 1;
+    r.host_ms += host;
+    if (t.pending.size() >= 4096) timing_resolve(t);
+  } catch (...) {
+    if (pair_) event_pair_destroy(pair_);  // not recorded anywhere
   }
-  if (t.pending.size() >= 4096) timing_resolve(t);
 }
 
 }  // namespace ewald

@@ -239,7 +239,7 @@ int stream_capturing(void* stream, int* capturing);
 // launches work, constructed first thing in the call.
 class CallTimer {
  public:
-  CallTimer(const char* name, void* stream);
+  CallTimer(const char* name, void* stream) noexcept;
   ~CallTimer();
   CallTimer(const CallTimer&) = delete;
   CallTimer& operator=(const CallTimer&) = delete;

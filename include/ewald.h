@@ -319,25 +319,41 @@ ewald_status ewald_run_moves_grad_batch(ewald_batch *b, void *state, int n_steps
  *                  vector registers), 3 or 4 = more workgroups per CU with the
  *                  constants in scalar registers; 3 and 4 give E_ARG when the
  *                  shape is not 256 threads
- * Results do not depend on the choice beyond rounding order.  Not to be
+ *   walkers_per_block  0 = one workgroup per walker, dispatched by the
+ *                  hardware in the batch's launch order (most expensive
+ *                  walker first); W > 0 = ceil(n_walkers / W) workgroups,
+ *                  each taking the next walker, in the same order, from a
+ *                  work counter until all are done (the counter is the int32
+ *                  at byte 192 of the state buffer, inside the first walker's
+ *                  header; it is reset by a kernel launched on the stream
+ *                  before the sweep, so such calls stay graph-capturable);
+ *                  E_ARG if negative, or if > 0 with waves 3 or 4 (the
+ *                  queue-mode kernels are compiled for two waves per SIMD)
+ * Results do not depend on the choice beyond rounding order (the queue mode
+ * computes each walker exactly as one workgroup per walker does).  Not to be
  * called concurrently with launches on the same batch. */
-ewald_status ewald_batch_set_tuning(ewald_batch *b, int threads, int chunk, int general_frame, int waves);
+ewald_status ewald_batch_set_tuning(ewald_batch *b, int threads, int chunk, int general_frame, int waves,
+                                    int walkers_per_block);
 
 /* The launch shape ewald_run_moves_batch will use: workgroup size, moves per
  * chunk, frame (1 = general), fused = 0 when the walkers do not fit the
  * fused kernel's LDS layout (then it runs the per-step
  * kernels in turn), and the waves per SIMD a 256-thread kernel is compiled
- * for (0 for the other workgroup sizes and when not fused), so that the
- * values can be passed back to ewald_batch_set_tuning.
+ * for (0 for the other workgroup sizes and when not fused), and the walkers
+ * per workgroup (0: one workgroup per walker, and when not fused), so that
+ * the values can be passed back to ewald_batch_set_tuning.
  * Any output pointer may be NULL. */
 ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, int *general_frame,
-                                    int *fused, int *waves);
+                                    int *fused, int *waves, int *walkers_per_block);
 
 /* The launch-shape choice that Sec. 3.3 makes by hand for each GPU (gang and
  * vector sizes), made by measurement: time every launch shape of
  * ewald_run_moves_batch on this batch and keep the fastest
  * (ewald_batch_set_tuning); shapes within 8 % of the fastest
- * are timed twice more, interleaved, and compared by their best time.  The
+ * are timed twice more, interleaved, and compared by their best time; then
+ * the queue mode of ewald_batch_set_tuning (walkers_per_block 1, and the
+ * count that leaves as many workgroups as that shape fits on the device at
+ * once) is timed against one workgroup per walker, interleaved.  The
  * probe runs n_moves (1..4096)
  * proposals per walker, every other one accepted, on a device copy of
  * `state`, which must be ready (after ewald_energy_batch, no pending move)

@@ -954,6 +954,13 @@ int dev_upload(void* dst, const void* src, size_t bytes) {
   hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
   return e == hipSuccess ? 0 : int(e);
 }
+int dev_cu_count(int* n_cu) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  return e == hipSuccess ? 0 : int(e);
+}
+
 int dev_current(int* device) {
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);

@@ -1212,6 +1212,7 @@ ewald_status ewald_batch_create(ewald_sys* const* sys, int n_sys, const int* wal
   B->state_bytes = off;
   std::vector<DevSys> ds;
   LaunchBatch& L = B->lb;
+  if (dev_cu_count(&L.n_cu) != 0 || L.n_cu < 1) L.n_cu = 1;
   L.all_wtab_lds = 1;
   L.all_ortho = 1;
   L.n_walkers = n_walkers;
@@ -1363,8 +1364,12 @@ ewald_status ewald_run_moves_batch(ewald_batch* b, void* state, int n_steps, con
   return ewald_run_moves_grad_batch(b, state, n_steps, k, new_pos, accept, delta, djastrow, nullptr, nullptr, stream);
 }
 
-ewald_status ewald_batch_set_tuning(ewald_batch* b, int threads, int chunk, int general_frame, int waves) {
+ewald_status ewald_batch_set_tuning(ewald_batch* b, int threads, int chunk, int general_frame, int waves,
+                                    int walkers_per_block) {
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
+  if (walkers_per_block < 0) return fail(EWALD_E_ARG, "walkers_per_block must be >= 0");
+  if (walkers_per_block > 0 && waves > 2)
+    return fail(EWALD_E_ARG, "walkers_per_block > 0 runs kernels compiled for two waves per SIMD: waves must be 0 or 2");
   if (!run_threads_valid(b->lb.max_n_seg, threads))
     return fail(EWALD_E_ARG, "threads is not a fused-kernel workgroup size for this batch's segment count");
   if (chunk < 0 || chunk > RUN_CHUNK) return fail(EWALD_E_ARG, "chunk must be in [0, 64]");
@@ -1382,11 +1387,12 @@ ewald_status ewald_batch_set_tuning(ewald_batch* b, int threads, int chunk, int 
   b->lb.run_chunk = chunk;
   b->lb.general_frame = general_frame;
   b->lb.run_waves = waves;
+  b->lb.run_wpb = walkers_per_block;
   return EWALD_OK;
 }
 
 ewald_status ewald_batch_get_tuning(ewald_batch* b, int* threads, int* chunk, int* general_frame,
-                                    int* fused, int* waves) {
+                                    int* fused, int* waves, int* walkers_per_block) {
   if (!b) return fail(EWALD_E_ARG, "batch is NULL");
   RunPlan p{};
   {
@@ -1398,6 +1404,7 @@ ewald_status ewald_batch_get_tuning(ewald_batch* b, int* threads, int* chunk, in
   if (general_frame) *general_frame = p.fused ? p.general_frame : 1;
   if (fused) *fused = p.fused;
   if (waves) *waves = p.fused ? p.waves : 0;
+  if (walkers_per_block) *walkers_per_block = p.fused ? p.walkers_per_block : 0;
   return EWALD_OK;
 }
 
@@ -1415,7 +1422,7 @@ std::string tune_key(const ewald_batch* b) {
   return buf;
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* t, int* c, int* g, int* v) {
+bool cache_lookup(const char* path, const std::string& key, int* t, int* c, int* g, int* v, int* q) {
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char line[1024];
@@ -1424,7 +1431,9 @@ bool cache_lookup(const char* path, const std::string& key, int* t, int* c, int*
     std::string l(line);
     const size_t bar = l.find('|');
     if (bar == std::string::npos || l.substr(0, bar) != key) continue;
-    found = std::sscanf(l.c_str() + bar + 1, "threads=%d chunk=%d general_frame=%d waves=%d", t, c, g, v) == 4;
+    *q = 0;  // lines written before the queue mode existed have no walkers_per_block
+    found = std::sscanf(l.c_str() + bar + 1, "threads=%d chunk=%d general_frame=%d waves=%d walkers_per_block=%d", t,
+                        c, g, v, q) >= 4;
   }
   std::fclose(f);
   return found;
@@ -1440,8 +1449,8 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   ewald_status st = check_state(b, state, 3, -1);
   if (st != EWALD_OK) return st;
   const std::string key = tune_key(b);
-  int t = 0, c = 0, g = 0, v = 0;
-  if (cache_path && cache_lookup(cache_path, key, &t, &c, &g, &v)) return ewald_batch_set_tuning(b, t, c, g, v);
+  int t = 0, c = 0, g = 0, v = 0, q = 0;
+  if (cache_path && cache_lookup(cache_path, key, &t, &c, &g, &v, &q)) return ewald_batch_set_tuning(b, t, c, g, v, q);
   // probe: proposals spread over each cell, every other move accepted, run on
   // a copy of the walkers' state (which is left as it was)
   const int W = b->lb.n_walkers, dim = b->lb.dim;
@@ -1488,7 +1497,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   }
   // candidates: every workgroup shape for the segment count, chunk sizes, both frames
   struct Cand {
-    int threads, chunk, general, waves;
+    int threads, chunk, general, waves, wpb;
     float ms;
   };
   std::vector<Cand> cands;
@@ -1499,6 +1508,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
     L.run_chunk = c.chunk;
     L.general_frame = c.general;
     L.run_waves = c.waves;
+    L.run_wpb = c.wpb;
     float ms = 0.f;
     const int r = time_run(L, static_cast<char*>(ds), n_moves, static_cast<int32_t*>(dk), static_cast<double*>(dp),
                            static_cast<uint8_t*>(da), static_cast<double*>(dd), stream, reps, &ms);
@@ -1519,7 +1529,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
         RunPlan p{};
         plan_run(L, &p);
         if (!p.fused || (waves > 2 && p.threads != 256)) continue;
-        cands.push_back({threads, chunk, general, waves, -1.f});
+        cands.push_back({threads, chunk, general, waves, 0, -1.f});
         rc = probe(cands.back(), 2);
         if (rc) {
           release();
@@ -1543,16 +1553,56 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
       }
     }
   std::stable_sort(cands.begin(), cands.begin() + n_close, by_time);
+  // walkers per workgroup: for the chosen shape, a queue (1 walker per
+  // workgroup on average, and as many walkers per workgroup as leave one
+  // workgroup per slot the device holds at once, when that is more) against
+  // the hardware's dispatch of one workgroup per walker, interleaved, each
+  // timed three times
+  if (!cands.empty()) {
+    Cand hw = cands[0];
+    LaunchBatch L = saved;
+    L.run_threads = hw.threads;
+    L.run_chunk = hw.chunk;
+    L.general_frame = hw.general;
+    L.run_waves = 2;  // the queue mode's kernels are compiled for two waves per SIMD
+    RunPlan p{};
+    plan_run(L, &p);
+    if (p.fused) {
+      const int resident = std::max(1, p.blocks_per_cu) * std::max(1, saved.n_cu);
+      std::vector<Cand> qs;
+      for (int wpb : {1, (W + resident - 1) / resident}) {
+        if (!qs.empty() && qs.back().wpb == wpb) continue;
+        Cand qc = hw;
+        qc.waves = 2;
+        qc.wpb = wpb;
+        qc.ms = -1.f;
+        qs.push_back(qc);
+      }
+      for (int pass = 0; pass < 3 && !rc; ++pass) {
+        rc = probe(hw, 1);
+        for (Cand& qc : qs)
+          if (!rc) rc = probe(qc, 1);
+      }
+      if (rc) {
+        release();
+        return launch_status(rc, "autotune");
+      }
+      cands[0] = hw;
+      for (const Cand& qc : qs)
+        if (qc.ms >= 0.f && qc.ms < cands[0].ms) cands[0] = qc;
+    }
+  }
   const float best = cands.empty() ? -1.f : cands[0].ms;
   const int bt = cands.empty() ? 0 : cands[0].threads, bc = cands.empty() ? 0 : cands[0].chunk,
-            bg = cands.empty() ? 0 : cands[0].general, bv = cands.empty() ? 0 : cands[0].waves;
+            bg = cands.empty() ? 0 : cands[0].general, bv = cands.empty() ? 0 : cands[0].waves,
+            bq = cands.empty() ? 0 : cands[0].wpb;
   release();
   if (best < 0.f) return EWALD_OK;  // the fused kernel does not fit: nothing to tune
-  st = ewald_batch_set_tuning(b, bt, bc, bg, bv);
+  st = ewald_batch_set_tuning(b, bt, bc, bg, bv, bq);
   if (st != EWALD_OK || !cache_path) return st;
   if (FILE* f = std::fopen(cache_path, "a")) {
-    std::fprintf(f, "%s|threads=%d chunk=%d general_frame=%d waves=%d ms=%.4f\n", key.c_str(), bt, bc, bg, bv,
-                 double(best));
+    std::fprintf(f, "%s|threads=%d chunk=%d general_frame=%d waves=%d walkers_per_block=%d ms=%.4f\n", key.c_str(),
+                 bt, bc, bg, bv, bq, double(best));
     std::fclose(f);
   }
   return EWALD_OK;

@@ -18,6 +18,9 @@ constexpr int BLOCK = 256;        // threads per workgroup of every kernel
 constexpr int MAX_CAND = 16;      // +-pairs of minimum-image candidate offsets
 constexpr int MAX_COSET = 1;      // nonzero cosets of an orthogonal sublattice (index <= 2)
 constexpr int HDR_BYTES = 256;    // per-walker state header
+// Byte offset, in the state buffer (inside the first walker's header), of the
+// fused kernel's work counter when its workgroups take walkers from a queue.
+constexpr int QUEUE_OFF = 192;
 constexpr int MAX_SPT = 8;        // segments per thread held in registers (MAX_SEGMENTS / BLOCK)
 constexpr int TILE_P = 8;         // particles per phase-table tile when rebuilding rho (tiles are even)
 static_assert(TILE_P % 2 == 0, "rebuild tiles hold whole particle pairs");
@@ -36,7 +39,7 @@ struct WalkerHdr {
   double pending_s[3];  // wrapped fractional position of the pending move
   double drift_max;     // max |rho_running - rho_rebuilt| (bits updated with atomicMax)
 };
-static_assert(sizeof(WalkerHdr) <= HDR_BYTES, "header too large");
+static_assert(sizeof(WalkerHdr) <= QUEUE_OFF && QUEUE_OFF + 4 <= HDR_BYTES, "header too large");
 
 // One system as the kernels see it (lives in device memory).
 struct DevSys {
@@ -173,6 +176,9 @@ struct LaunchBatch {
   int run_threads;          // fused kernel: workgroup size (0: default for the segment count)
   int run_waves;            // fused kernel, 256 threads: waves per SIMD it is compiled for (0: 2)
   int run_chunk;            // fused kernel: moves per chunk (0: as many as LDS allows, <= RUN_CHUNK)
+  int run_wpb;              // fused kernel: walkers per workgroup taken from a queue (0: one
+                            // walker per workgroup, dispatched by the hardware)
+  int n_cu;                 // compute units of the device
   int general_frame;        // fused kernel: 1 = general minimum-image reduction even if all_ortho
 };
 
@@ -189,6 +195,8 @@ struct RunPlan {
   int blocks_per_cu;  // workgroups per CU allowed by registers
   int waves;          // 256 threads: waves per SIMD the kernel is compiled for (512 / waves registers
                       // per lane); 0 for the other shapes (their bound is fixed)
+  int walkers_per_block;  // 0: one walker per workgroup; else the queue mode's walkers per workgroup
+  int grid;               // workgroups launched
 };
 
 // Each returns 0 on success or the hipError_t of the failed launch.
@@ -220,6 +228,7 @@ int dev_alloc(void** p, size_t bytes);
 int dev_free(void* p);
 int dev_upload(void* dst, const void* src, size_t bytes);
 int dev_current(int* device);
+int dev_cu_count(int* n_cu);  // compute units of the current device
 const char* dev_error_string(int code);
 int dev_arch(char* buf, int len);  // the current device's architecture name
 int dev_memset(void* p, int value, size_t bytes);

@@ -35,6 +35,7 @@ struct RunLds {
   uint32_t q, red, wtab, ctab, sn, so, xn, xo, c2q, part, k, acc, cnt;
   uint32_t wtab2, part2;  // Jastrow derivatives: a |G|^2 per shell, and the per-move partial sums
   uint32_t rcopy;  // 0, or the LDS copy of the running rho during a rebuild
+  uint32_t next;   // queue mode: the next walker's index, broadcast to the workgroup
   int ch;     // moves per chunk
   int rtile;  // particles per rebuild tile (the tiles reuse the chunk tables)
 };
@@ -58,14 +59,21 @@ struct RunLds {
 // with w_x in the shell table's second column, real-space partners in the
 // other plane sqrt(r^2 + dz^2) apart.  Walkers of a one-plane system run in
 // such a kernel with an empty second plane.
+// QUEUE = false: one walker per workgroup (walkers[blockIdx.x]; queue is
+// unused).  QUEUE = true: `queue` is a work counter (zeroed before the
+// launch) from which each workgroup takes the next walker index until all
+// are done, in the launch order of `walkers` (most expensive first), so
+// fewer workgroups than walkers serve the batch.  (A separate instantiation:
+// the loop over walkers costs the one-walker kernels registers.)
 template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA, int WV = 2,
-          bool LAY = false>
+          bool LAY = false, bool QUEUE = false>
 __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* __restrict__ systems,
                                             const DevWalker* __restrict__ walkers, char* __restrict__ state,
                                             int n_steps, int n_walkers, const int32_t* __restrict__ kk,
                                             const double* __restrict__ new_pos, const uint8_t* __restrict__ accept,
                                             double* __restrict__ delta, double* __restrict__ djas,
-                                            double* __restrict__ jgrad, double* __restrict__ jlap, RunLds L) {
+                                            double* __restrict__ jgrad, double* __restrict__ jlap, RunLds L,
+                                            int* __restrict__ queue) {
   constexpr bool JAS = JM > 0, DER = JM == 2 || JM == 4, UJ = JM >= 3;
   constexpr int NDP = DIM + 1;               // p-term derivative sums per move: S_0 .. S_{DIM-1}, L
   constexpr int NDV = UJ ? 2 * NDP : NDP;    // plus the u term's gradient (frame axes) and Laplacian
@@ -75,7 +83,16 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
   constexpr int NW = NT / 64;
   // PPR: own particles per thread held in registers (particles j = t + c NT, c < PPR)
   extern __shared__ __align__(16) char lds[];
-  const DevWalker W = walkers[blockIdx.x];
+  for (int wi = blockIdx.x;;) {
+  if (QUEUE) {
+    int* st_next = reinterpret_cast<int*>(lds + L.next);
+    if (threadIdx.x == 0) *st_next = atomicAdd(queue, 1);
+    __syncthreads();
+    wi = uniform_i(*st_next);  // the walker is the same for every lane: its fields stay scalar
+    __syncthreads();          // every thread has read the index before it is replaced
+    if (wi >= n_walkers) break;
+  }
+  const DevWalker W = walkers[wi];
   const int w = W.id, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const DevSys* __restrict__ S = systems + W.sys;
   const int n = W.n_mobile, nseg = S->n_seg, nm = S->nm;
@@ -562,6 +579,17 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : WV) void k_run(const DevSys* _
     hdr->pending_k = -1;
     hdr->drift_max = drift;
   }
+  if (!QUEUE) break;
+  __syncthreads();  // the next walker reuses LDS
+  }
+}
+
+// The fused kernel's work counter, zeroed on the stream before a queue-mode
+// launch (a kernel rather than a memset, so that graph capture records it
+// as a kernel node).
+template <int D>
+__global__ void k_queue_reset(int* queue) {
+  if (threadIdx.x == 0) *queue = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -604,6 +632,8 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   o = up16(o + size_t(ch) * 4);
   L.cnt = uint32_t(o);
   o = up16(o + size_t(ch) * 4);
+  L.next = uint32_t(o);
+  o = up16(o + 4);
   L.wtab2 = L.part2 = 0;
   if (DER) {
     L.wtab2 = uint32_t(o);
@@ -643,9 +673,9 @@ struct RunArgs {
 };
 
 template <int DIM, bool MIXED, int NT, int SPT, int PPR, int JM, int PD, bool ORTHO, bool XTRA, int WV = 2,
-          bool LAY = false>
+          bool LAY = false, bool QUEUE = false>
 int run_inst(const LaunchBatch& b, const RunArgs& a) {
-  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, XTRA, WV, LAY>;
+  auto* kern = k_run<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, XTRA, WV, LAY, QUEUE>;
   constexpr bool DER = JM == 2 || JM == 4, UJ = JM >= 3;
   static const int per_cu = blocks_per_cu(kern, NT);
   const size_t budget = RUN_LDS_BUDGET / size_t(per_cu);
@@ -656,13 +686,23 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
     while (lds > budget && ch > 8) lds = run_layout<DIM, MIXED, NT, SPT, DER, UJ>(b, --ch, L);
   while (lds > RUN_LDS_BUDGET && ch > 1) lds = run_layout<DIM, MIXED, NT, SPT, DER, UJ>(b, --ch, L);
   if (lds > RUN_LDS_BUDGET) return RUN_NO_FIT;
+  // queue mode: ceil(W / walkers_per_block) workgroups take walkers from a
+  // counter in the state buffer
+  const int wpb = QUEUE ? b.run_wpb : 0;
+  const int grid = wpb > 0 ? (b.n_walkers + wpb - 1) / wpb : b.n_walkers;
   if (a.plan) {
-    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu, NT == 256 ? WV : 0};
+    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu, NT == 256 ? WV : 0, wpb, grid};
     return 0;
   }
   if (int rc = allow_lds(kern, lds)) return rc;
-  hipLaunchKernelGGL(kern, dim3(b.n_walkers), dim3(NT), lds, as_stream(a.stream), b.d_sys, b.d_walk, a.state,
-                     a.n_steps, b.n_walkers, a.k, a.new_pos, a.accept, a.delta, a.djas, a.jgrad, a.jlap, L);
+  int* queue = nullptr;
+  if (QUEUE) {
+    queue = reinterpret_cast<int*>(a.state + QUEUE_OFF);
+    hipLaunchKernelGGL(k_queue_reset<0>, dim3(1), dim3(64), 0, as_stream(a.stream), queue);
+    if (int rc = last_launch()) return rc;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, as_stream(a.stream), b.d_sys, b.d_walk, a.state,
+                     a.n_steps, b.n_walkers, a.k, a.new_pos, a.accept, a.delta, a.djas, a.jgrad, a.jlap, L, queue);
   return last_launch();
 }
 
@@ -708,16 +748,22 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   // registers there and runs slower).
   const bool xtra = b.max_particles > ppr * nt || b.max_fixed > 0;
   const int wv = b.run_waves > 0 ? b.run_waves : 2;
+  // the queue mode is compiled for two waves per SIMD; the host rejects it
+  // with other wave counts
+  const bool queue = b.run_wpb > 0;
 #define EW_RUN(NT, SPT, PPR)                                                                             \
   if (nt == NT && spt == SPT && ppr == PPR) {                                                           \
     if (wv == 3) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 3, LAY>(b, a);          \
     if (wv == 4) return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 4, LAY>(b, a);          \
-    return run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 2, LAY>(b, a);                       \
+    return queue ? run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 2, LAY, true>(b, a)          \
+                 : run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 2, LAY>(b, a);               \
   }
 #define EW_RUN_X(NT, SPT, PPR)                                                                          \
   if (nt == NT && spt == SPT && ppr == PPR)                                                            \
-    return xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 2, LAY>(b, a)               \
-                : run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, false, 2, LAY>(b, a)
+    return queue ? (xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 2, LAY, true>(b, a)   \
+                         : run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, false, 2, LAY, true>(b, a)) \
+                 : (xtra ? run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, true, 2, LAY>(b, a)         \
+                         : run_inst<DIM, MIXED, NT, SPT, PPR, JM, PD, ORTHO, false, 2, LAY>(b, a))
   EW_RUN(256, 1, 1);
   EW_RUN(256, 1, 2);
   EW_RUN(256, 2, 1);

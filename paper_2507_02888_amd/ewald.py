@@ -87,8 +87,8 @@ def load() -> ctypes.CDLL:
     lib.ewald_move_delta_grad_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ewald_run_moves_grad_batch.argtypes = [vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ewald_step_batch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-    lib.ewald_batch_set_tuning.argtypes = [vp, c_int, c_int, c_int, c_int]
-    lib.ewald_batch_get_tuning.argtypes = [vp, P(c_int), P(c_int), P(c_int), P(c_int), P(c_int)]
+    lib.ewald_batch_set_tuning.argtypes = [vp, c_int, c_int, c_int, c_int, c_int]
+    lib.ewald_batch_get_tuning.argtypes = [vp, P(c_int), P(c_int), P(c_int), P(c_int), P(c_int), P(c_int)]
     lib.ewald_autotune.argtypes = [vp, vp, c_int, ctypes.c_char_p, vp]
     lib.ewald_blip_create.argtypes = [P((ctypes.c_double * 3) * 3), P(c_int * 3), c_int, P(vp)]
     lib.ewald_blip_destroy.argtypes = [vp]
@@ -317,15 +317,16 @@ def ewald_run_moves_grad_batch(batch_h, state_ptr, n_steps, k_ptr, new_pos_ptr, 
                                              ctypes.c_void_p(jlap_ptr or None), ctypes.c_void_p(stream or None)))
 
 
-def ewald_batch_set_tuning(batch_h, threads=0, chunk=0, general_frame=0, waves=0) -> None:
+def ewald_batch_set_tuning(batch_h, threads=0, chunk=0, general_frame=0, waves=0, walkers_per_block=0) -> None:
     _check(load().ewald_batch_set_tuning(ctypes.c_void_p(batch_h), int(threads), int(chunk), int(general_frame),
-                                         int(waves)))
+                                         int(waves), int(walkers_per_block)))
 
 
 def ewald_batch_get_tuning(batch_h) -> dict:
-    v = [ctypes.c_int() for _ in range(5)]
+    v = [ctypes.c_int() for _ in range(6)]
     _check(load().ewald_batch_get_tuning(ctypes.c_void_p(batch_h), *[ctypes.byref(x) for x in v]))
-    return dict(threads=v[0].value, chunk=v[1].value, general_frame=v[2].value, fused=v[3].value, waves=v[4].value)
+    return dict(threads=v[0].value, chunk=v[1].value, general_frame=v[2].value, fused=v[3].value, waves=v[4].value,
+                walkers_per_block=v[5].value)
 
 
 def ewald_autotune(batch_h, state_ptr, n_moves=32, cache_path=None, stream=0) -> None:
@@ -429,8 +430,8 @@ class Batch:
                                    0 if djastrow is None else djastrow.data_ptr(), jgrad.data_ptr(),
                                    jlap.data_ptr(), self.stream())
 
-    def set_tuning(self, threads=0, chunk=0, general_frame=0, waves=0):
-        ewald_batch_set_tuning(self.handle, threads, chunk, general_frame, waves)
+    def set_tuning(self, threads=0, chunk=0, general_frame=0, waves=0, walkers_per_block=0):
+        ewald_batch_set_tuning(self.handle, threads, chunk, general_frame, waves, walkers_per_block)
 
     def tuning(self) -> dict:
         return ewald_batch_get_tuning(self.handle)

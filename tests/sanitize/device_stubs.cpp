@@ -41,6 +41,10 @@ int dev_alloc(void** p, size_t) {
 int dev_free(void*) { return 0; }
 int dev_upload(void*, const void*, size_t) { return kNoDevice; }
 int dev_current(int*) { return kNoDevice; }
+int dev_cu_count(int* n_cu) {
+  *n_cu = 0;
+  return kNoDevice;
+}
 const char* dev_error_string(int) { return "no device (sanitizer build)"; }
 int dev_arch(char* buf, int len) {
   if (len > 0) buf[0] = '\0';

@@ -99,8 +99,8 @@ def test_validation_errors(lib):
     assert lib.ewald_run_moves_batch(None, None, 1, None, None, None, None, None, None) == ew.EWALD_E_ARG
     assert lib.ewald_sys_query(None, None, None, None, None, None) == ew.EWALD_E_ARG
     assert lib.ewald_batch_layout(None, None, None) == ew.EWALD_E_ARG
-    assert lib.ewald_batch_set_tuning(None, 0, 0, 0, 0) == ew.EWALD_E_ARG
-    assert lib.ewald_batch_get_tuning(None, None, None, None, None, None) == ew.EWALD_E_ARG
+    assert lib.ewald_batch_set_tuning(None, 0, 0, 0, 0, 0) == ew.EWALD_E_ARG
+    assert lib.ewald_batch_get_tuning(None, None, None, None, None, None, None) == ew.EWALD_E_ARG
     assert lib.ewald_autotune(None, None, 8, None, None) == ew.EWALD_E_ARG
     assert lib.ewald_sys_geometry(None, None, None) == ew.EWALD_E_ARG
 

@@ -1309,3 +1309,100 @@ def test_call_timers():
     finally:
         ew.ewald_timing_enable(False)
         ew.ewald_timing_report(reset=True)
+
+
+# Queue mode of the fused sweep (walkers_per_block > 0: fewer workgroups than
+# walkers, each taking the next walker from a work counter): every walker is
+# computed as with one workgroup per walker, so outputs and states agree bit
+# for bit.
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [2, 4, 5])
+def test_queue_mode_matches_one_walker_per_workgroup(cfg_id, precision):
+    W, S = {2: (9, 12), 4: (12, 12), 5: (3, 8)}[cfg_id]
+    say(f"[queue] cfg={cfg_id} precision={precision} walkers={W}")
+    ref = Case(cfg_id, W, S, precision, refresh_every=3)
+    ref.run_energy()
+    d0, j0 = ref.fused()
+    for wpb in (1, 4, W):
+        c = Case(cfg_id, W, S, precision, refresh_every=3)
+        c.run_energy()
+        c.batch.set_tuning(walkers_per_block=wpb)
+        t = c.batch.tuning()
+        assert t["walkers_per_block"] == wpb and t["fused"] == 1
+        d, j = c.fused()
+        assert np.array_equal(d, d0) and np.array_equal(j, j0), wpb
+        same_state(ref, c, W)
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_queue_mode_graph_replay(precision):
+    """The counter reset is a kernel, so a captured queue-mode sweep replays
+    correctly: three replays equal three eager sweeps."""
+    W, S = 10, 8
+    say(f"[queue graph] cfg=4 precision={precision}")
+    eager = Case(4, W, S, precision, refresh_every=3)
+    eager.run_energy()
+    eager.batch.set_tuning(walkers_per_block=3)
+    ref = [eager.fused() for _ in range(3)]
+    g_case = Case(4, W, S, precision, refresh_every=3)
+    g_case.run_energy()
+    g_case.batch.set_tuning(walkers_per_block=3)
+    d = torch.zeros((S, W), dtype=torch.float64, device="cuda")
+    dj = torch.zeros_like(d)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        g_case.batch.run_moves(g_case.k, g_case.new_pos, g_case.accept, d, dj)
+    torch.cuda.synchronize()
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(d.cpu().numpy(), ref[r][0]), r
+        assert np.array_equal(dj.cpu().numpy(), ref[r][1]), r
+    same_state(eager, g_case, W)
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_queue_mode_derivs_u_term(precision):
+    """Queue mode with the Jastrow derivative outputs and the u term."""
+    W, S = 5, 8
+    say(f"[queue derivs] cfg=2 precision={precision}")
+    outs = []
+    for wpb in (0, 2):
+        c = Case(2, W, S, precision, refresh_every=3, u_term=True)
+        c.run_energy()
+        c.batch.set_tuning(walkers_per_block=wpb)
+        d = torch.zeros((S, W), dtype=torch.float64, device="cuda")
+        dj = torch.zeros_like(d)
+        g = torch.zeros((S, W, c.dim), dtype=torch.float64, device="cuda")
+        lp = torch.zeros_like(d)
+        c.batch.run_moves_grad(c.k, c.new_pos, c.accept, d, dj, g, lp)
+        torch.cuda.synchronize()
+        outs.append((c, [x.cpu().numpy() for x in (d, dj, g, lp)]))
+    for x, y in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(x, y)
+    same_state(outs[0][0], outs[1][0], W)
+
+
+def test_queue_mode_arguments_and_autotune():
+    """walkers_per_block < 0 is an argument error; with more walkers than
+    workgroups fit at once the autotuner times the queue mode too, and the
+    tuned sweep equals one workgroup per walker."""
+    say("[queue autotune] cfg=3 fp64")
+    c = Case(3, 1100, 6, FP64)
+    with pytest.raises(ew.EwaldError) as e:
+        c.batch.set_tuning(walkers_per_block=-1)
+    assert e.value.status == ew.EWALD_E_ARG
+    with pytest.raises(ew.EwaldError) as e:  # the queue kernels are compiled for two waves per SIMD
+        c.batch.set_tuning(threads=256, waves=4, walkers_per_block=2)
+    assert e.value.status == ew.EWALD_E_ARG
+    c.run_energy()
+    c.batch.autotune(n_moves=6)
+    t = c.batch.tuning()
+    assert t["fused"] == 1 and t["walkers_per_block"] >= 0
+    d1, j1 = c.fused()
+    ref = Case(3, 1100, 6, FP64)
+    ref.run_energy()
+    ref.batch.set_tuning(**{k: v for k, v in t.items() if k not in ("fused", "walkers_per_block")})
+    d0, j0 = ref.fused()
+    assert np.array_equal(d0, d1) and np.array_equal(j0, j1)

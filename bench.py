@@ -81,8 +81,9 @@ def traffic_from_profiles(form: str, shape: dict):
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     for sh in d.get("shapes", []):  # one entry per profiled workgroup size
+        # the queue mode (walkers_per_block > 0) is its own kernel; its traffic does not depend on the count
         if (sh.get("threads") == shape.get("threads") and sh.get("general_frame", 0) == shape.get("general_frame")
-                and sh.get("walkers_per_block", 0) == shape.get("walkers_per_block", 0)):
+                and (sh.get("walkers_per_block", 0) > 0) == (shape.get("walkers_per_block", 0) > 0)):
             f = sh.get("forms", {}).get(form)
             return None if f is None else f.get("hbm_bytes_per_launch")
     return None

@@ -1560,6 +1560,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   // timed three times
   if (!cands.empty()) {
     Cand hw = cands[0];
+    hw.ms = -1.f;  // timed afresh, as many times as each queue setting
     LaunchBatch L = saved;
     L.run_threads = hw.threads;
     L.run_chunk = hw.chunk;

@@ -234,7 +234,7 @@ def other_workload(cfg_id: int, precision: int, steps: int = 2, threads: int = 0
     delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
     batch.energy(pos, energy)
     if threads:
-        batch.set_tuning(threads=threads, walkers_per_block=walkers_per_block)
+        batch.set_tuning(threads=threads)
     else:
         batch.autotune(n_moves=max(64, 2 * K) if K else 64)
     stream = torch.cuda.current_stream()

@@ -70,7 +70,7 @@ def kernel_source_hash() -> str:
 def traffic_from_profiles(form: str, shape: dict):
     """Measured HBM bytes per fused launch from the committed counter summary,
     or None when it is missing, was taken on another kernel source, or on
-    another launch shape (workgroup size, frame, walkers per workgroup)."""
+    another launch shape (workgroup size, frame, walkers per workgroup, waves per SIMD)."""
     p = os.path.join(ROOT, "profiles", "k_run_n1024_counters.json")
     if not os.path.exists(p):
         return None
@@ -81,16 +81,18 @@ def traffic_from_profiles(form: str, shape: dict):
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     for sh in d.get("shapes", []):  # one entry per profiled workgroup size
-        # the queue mode (walkers_per_block > 0) is its own kernel; its traffic does not depend on the count
+        # the queue mode (walkers_per_block > 0) is its own kernel; its traffic does not depend on the count;
+        # each waves-per-SIMD bound is its own kernel too
         if (sh.get("threads") == shape.get("threads") and sh.get("general_frame", 0) == shape.get("general_frame")
-                and (sh.get("walkers_per_block", 0) > 0) == (shape.get("walkers_per_block", 0) > 0)):
+                and (sh.get("walkers_per_block", 0) > 0) == (shape.get("walkers_per_block", 0) > 0)
+                and sh.get("waves", 0) == shape.get("waves", 0)):
             f = sh.get("forms", {}).get(form)
             return None if f is None else f.get("hbm_bytes_per_launch")
     return None
 
 
 def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_step: bool = True,
-             threads: int = 0, n_parity: int = 64, walkers_per_block: int = 0):
+             threads: int = 0, n_parity: int = 64, walkers_per_block: int = 0, waves: int = 0):
     import torch
     from paper_2507_02888_amd import ewald as ew
     cfg, b = batch_inputs["cfg"], batch_inputs["b"]
@@ -104,7 +106,7 @@ def run_form(precision: int, batch_inputs, steps: int, warmup: int, K: int, per_
     # state, outside the timed region), or a fixed workgroup size
     batch.energy(t["pos"], torch.zeros(b.walkers, dtype=torch.float64, device=dev))
     if threads:
-        batch.set_tuning(threads=threads, walkers_per_block=walkers_per_block)
+        batch.set_tuning(threads=threads, waves=waves, walkers_per_block=walkers_per_block)
     else:
         batch.autotune(n_moves=max(64, 2 * K) if precision == ew.EWALD_FP32_MIXED and K > 0 else 64)
     tuning = batch.tuning()
@@ -571,6 +573,8 @@ def main():
                     help="fixed fused-kernel workgroup size instead of the autotuner's choice")
     ap.add_argument("--walkers-per-block", type=int, default=0,
                     help="with --threads: the fused kernel's queue mode (walkers per workgroup; 0 = one each)")
+    ap.add_argument("--waves", type=int, default=0,
+                    help="with --threads: waves per SIMD the fused kernel is compiled for (0 = default)")
     ap.add_argument("--k-sweep", default="128,256,512,0",
                     help="further refresh intervals K timed for the mixed form (0 = no rebuild); empty to skip")
     ap.add_argument("--other", default="2,3,4",
@@ -633,7 +637,7 @@ def main():
     for form in args.forms.split(","):
         prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
         r = run_form(prec, inputs, args.steps, args.warmup, K, threads=args.threads, n_parity=args.cpu_walkers,
-                     walkers_per_block=args.walkers_per_block)
+                     walkers_per_block=args.walkers_per_block, waves=args.waves)
         flops_run = deltas_per_step * algorithmic_flops_per_delta(n_g, n_part) + \
             r["n_refresh"] * algorithmic_flops_per_rebuild(n_g, n_part)
         achieved = flops_run / (r["run_ms"] * 1e-3) / 1e12

@@ -314,11 +314,15 @@ ewald_status ewald_run_moves_grad_batch(ewald_batch *b, void *state, int n_steps
  *   general_frame  1 = the general minimum-image reduction even when the
  *                  cell has an orthogonal-sublattice frame (ewald_sys_geometry);
  *                  applies to ewald_energy_batch as well
- *   waves          waves per SIMD the 256-thread kernel is compiled for:
- *                  0 or 2 = default (256 registers per lane, constants in
- *                  vector registers), 3 or 4 = more workgroups per CU with the
- *                  constants in scalar registers; 3 and 4 give E_ARG when the
- *                  shape is not 256 threads
+ *   waves          waves per SIMD the kernel is compiled for, for workgroups
+ *                  of 256 and 512 threads: 0 or 2 = default (256 registers
+ *                  per lane, constants in vector registers), 3 or 4 = more
+ *                  workgroups per CU with the constants in scalar registers
+ *                  (256 threads: 3 or 4; 512 threads with 2 segments per
+ *                  thread: 4); other combinations give E_ARG (1024-thread
+ *                  workgroups run at four waves per SIMD by construction).
+ *                  The Jastrow-derivative sweep (ewald_run_moves_grad_batch)
+ *                  runs 512 x 2 at two waves whatever this says
  *   walkers_per_block  0 = one workgroup per walker, dispatched by the
  *                  hardware in the batch's launch order (most expensive
  *                  walker first); W > 0 = ceil(n_walkers / W) workgroups,
@@ -338,8 +342,8 @@ ewald_status ewald_batch_set_tuning(ewald_batch *b, int threads, int chunk, int 
 /* The launch shape ewald_run_moves_batch will use: workgroup size, moves per
  * chunk, frame (1 = general), fused = 0 when the walkers do not fit the
  * fused kernel's LDS layout (then it runs the per-step
- * kernels in turn), and the waves per SIMD a 256-thread kernel is compiled
- * for (0 for the other workgroup sizes and when not fused), and the walkers
+ * kernels in turn), and the waves per SIMD a 256- or 512-thread kernel is
+ * compiled for (0 for 1024 threads and when not fused), and the walkers
  * per workgroup (0: one workgroup per walker, and when not fused), so that
  * the values can be passed back to ewald_batch_set_tuning.
  * Any output pointer may be NULL. */

@@ -1375,12 +1375,14 @@ ewald_status ewald_batch_set_tuning(ewald_batch* b, int threads, int chunk, int 
   if (chunk < 0 || chunk > RUN_CHUNK) return fail(EWALD_E_ARG, "chunk must be in [0, 64]");
   if (general_frame != 0 && general_frame != 1) return fail(EWALD_E_ARG, "general_frame must be 0 or 1");
   if (waves != 0 && waves != 2 && waves != 3 && waves != 4) return fail(EWALD_E_ARG, "waves must be 0, 2, 3 or 4");
-  if (waves > 2) {  // only the 256-thread kernels come in these variants
+  if (waves > 2) {  // the 256-thread kernels come in these variants, and 512 x 2 at four waves
     LaunchBatch L = b->lb;
     L.run_threads = threads;
     RunPlan p{};
     plan_run(L, &p);
-    if (p.threads != 256) return fail(EWALD_E_ARG, "waves 3 and 4 apply to 256-thread workgroups only");
+    const bool ok = p.threads == 256 || (waves == 4 && p.threads == 512 && p.spt == 2);
+    if (!ok)
+      return fail(EWALD_E_ARG, "waves 3 and 4 apply to 256-thread workgroups (and 4 to 512 x 2 segments) only");
   }
   std::lock_guard<std::mutex> lk(b->mu);
   b->lb.run_threads = threads;
@@ -1528,7 +1530,7 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
         L.run_waves = waves;
         RunPlan p{};
         plan_run(L, &p);
-        if (!p.fused || (waves > 2 && p.threads != 256)) continue;
+        if (!p.fused || p.waves != (waves == 2 ? (p.threads <= 512 ? 2 : 0) : waves)) continue;  // no such variant
         cands.push_back({threads, chunk, general, waves, 0, -1.f});
         rc = probe(cands.back(), 2);
         if (rc) {

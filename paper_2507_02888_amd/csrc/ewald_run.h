@@ -691,7 +691,7 @@ int run_inst(const LaunchBatch& b, const RunArgs& a) {
   const int wpb = QUEUE ? b.run_wpb : 0;
   const int grid = wpb > 0 ? (b.n_walkers + wpb - 1) / wpb : b.n_walkers;
   if (a.plan) {
-    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu, NT == 256 ? WV : 0, wpb, grid};
+    *a.plan = RunPlan{1, NT, SPT, PPR, ch, ORTHO ? 0 : 1, int(lds), per_cu, NT <= 512 ? WV : 0, wpb, grid};
     return 0;
   }
   if (int rc = allow_lds(kern, lds)) return rc;
@@ -769,6 +769,14 @@ int run_jp(const LaunchBatch& b, const RunArgs& a) {
   EW_RUN(256, 2, 1);
   EW_RUN(256, 2, 2);
   EW_RUN_X(1024, 1, 1);
+  // 512 x 2 also at four waves per SIMD (two workgroups per CU, 128
+  // registers): faster for the FP32-mixed form, slower for FP64.  The
+  // Jastrow-derivative kernels (JM 2, 4) need more registers: they stay at
+  // two waves whatever the tuning says (the autotuner probes without them).
+  constexpr bool DERJ = JM == 2 || JM == 4;
+  if (!DERJ && nt == 512 && spt == 2 && ppr == 2 && wv == 4 && !queue)
+    return xtra ? run_inst<DIM, MIXED, 512, 2, 2, JM, PD, ORTHO, true, 4, LAY>(b, a)
+                : run_inst<DIM, MIXED, 512, 2, 2, JM, PD, ORTHO, false, 4, LAY>(b, a);
   EW_RUN_X(512, 2, 2);
   EW_RUN_X(512, 4, 2);
 #undef EW_RUN_X

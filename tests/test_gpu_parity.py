@@ -496,11 +496,13 @@ def test_tuning_shapes_agree(precision):
     # differ with the shape, so the form's own per-delta bound applies
     scale = max(1.0, max(abs(x) for x in ref.energy.cpu().numpy()))
     tol = 1e-12 * scale if precision == FP64 else 1e-5
-    for threads, chunk, general in ((512, 0, 0), (1024, 5, 0), (512, 1, 1), (0, 64, 1)):
+    for threads, chunk, general, waves in ((512, 0, 0, 0), (1024, 5, 0, 0), (512, 1, 1, 0), (0, 64, 1, 0),
+                                           (512, 0, 0, 4), (512, 3, 1, 4)):
         c = Case(5, W, S, precision, walker_start=w0, refresh_every=3)
-        c.batch.set_tuning(threads, chunk, general)
+        c.batch.set_tuning(threads, chunk, general, waves)
         t = c.batch.tuning()
         assert t["threads"] == (threads or 1024) and t["general_frame"] == general
+        assert t["waves"] == (waves or (2 if t["threads"] <= 512 else 0))
         if chunk:  # an upper bound: fewer moves per chunk when LDS does not hold them
             assert t["chunk"] == chunk if chunk <= 8 else 8 <= t["chunk"] <= chunk
         c.run_energy()
@@ -514,7 +516,9 @@ def test_tuning_shapes_agree(precision):
     with pytest.raises(ew.EwaldError):
         ref.batch.set_tuning(chunk=65)
     with pytest.raises(ew.EwaldError):
-        ref.batch.set_tuning(threads=512, waves=4)  # the wave variants are 256-thread kernels
+        ref.batch.set_tuning(threads=512, waves=3)  # 512 x 2 comes at two and four waves per SIMD
+    with pytest.raises(ew.EwaldError):
+        ref.batch.set_tuning(threads=1024, waves=4)  # 1024 threads: four waves per SIMD by construction
 
 
 @pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])

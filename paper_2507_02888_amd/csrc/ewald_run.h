@@ -611,6 +611,13 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   o = up16(o + size_t(NW) * 8);
   L.wtab = uint32_t(o);
   o = up16(o + size_t(b.max_wtab) * sizeof(cplx<R>));
+  // DER: a |G|^2 per shell, read by every move of the sweep, so it sits
+  // before the region that the rebuild between chunks reuses
+  L.wtab2 = 0;
+  if (DER) {
+    L.wtab2 = uint32_t(o);
+    o = up16(o + size_t(b.max_wtab) * sizeof(R));
+  }
   L.ctab = uint32_t(o);
   const size_t ctab = std::max(size_t(ch) * mtab, size_t(TILE_P) * rpart);
   o = up16(o + ctab);
@@ -634,19 +641,17 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
   o = up16(o + size_t(ch) * 4);
   L.next = uint32_t(o);
   o = up16(o + 4);
-  L.wtab2 = L.part2 = 0;
+  L.part2 = 0;
   if (DER) {
-    L.wtab2 = uint32_t(o);
-    o = up16(o + size_t(b.max_wtab) * sizeof(R));
     L.part2 = uint32_t(o);
     o = up16(o + size_t(ch) * NW * 4 * (DIM + 1) * (UJ ? 2 : 1) * 8);
   }
   L.ch = ch;
   L.rtile = int(std::min<size_t>(ctab / rpart, 64)) & ~1;  // even (the tiles interleave particle pairs)
-  // Between chunks the tables and the staging area are free: the mixed form's
-  // rebuild keeps the running rho there (for the drift check) when it fits
-  // beside tiles of at least TILE_P particles, instead of a round trip
-  // through HBM.
+  // Between chunks the tables and the staging area (everything from ctab on:
+  // per-chunk data only) are free: the mixed form's rebuild keeps the running
+  // rho there (for the drift check) when it fits beside tiles of at least
+  // TILE_P particles, instead of a round trip through HBM.
   L.rcopy = 0;
   const size_t rcopy = size_t(SPT) * NT * SEG * sizeof(cplx<double>);
   const size_t region = o - L.ctab;

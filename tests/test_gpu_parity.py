@@ -852,21 +852,23 @@ def test_jastrow_derivs_fused(oracle_lib, cfg_id, precision):
 # FP32-mixed form at a refresh interval of 3 accepts: the fused sweep rebuilds
 # rho between chunks several times, reusing the chunk's LDS for the rebuild
 # tiles and the running-rho copy; the per-shell tables the moves read must
-# survive it.  (cfg, tuning): each workload's default shape and another one.
-DERIV_REBUILD_CASES = [(2, dict()), (2, dict(threads=256, waves=3)), (2, dict(threads=1024)),
-                       (3, dict()), (3, dict(threads=1024)), (5, dict()), (5, dict(threads=512))]
+# survive it.  (cfg, tuning, u term): each workload's default shape and
+# another one, and the p term with the two-body u term.
+DERIV_REBUILD_CASES = [(2, dict(), False), (2, dict(threads=256, waves=3), False), (2, dict(threads=1024), False),
+                       (3, dict(), False), (3, dict(threads=1024), False), (5, dict(), False),
+                       (5, dict(threads=512), False), (2, dict(), True), (5, dict(), True)]
 
 
-@pytest.mark.parametrize("cfg_id,tuning", DERIV_REBUILD_CASES,
-                         ids=[f"cfg{c}-" + ("-".join(f"{k}{v}" for k, v in t.items()) or "default")
-                              for c, t in DERIV_REBUILD_CASES])
-def test_jastrow_derivs_with_rebuilds(oracle_lib, cfg_id, tuning):
+@pytest.mark.parametrize("cfg_id,tuning,u_term", DERIV_REBUILD_CASES,
+                         ids=[f"cfg{c}-" + ("-".join(f"{k}{v}" for k, v in t.items()) or "default") + ("-u" if u else "")
+                              for c, t, u in DERIV_REBUILD_CASES])
+def test_jastrow_derivs_with_rebuilds(oracle_lib, cfg_id, tuning, u_term):
     """Gradient and Laplacian of every proposed move through several rebuilds
     (fused sweep and per-step calls) against the oracle; the fused deltas and
     final state equal those of the plain fused sweep at the same shape."""
     W, S, K = 2, (12 if cfg_id == 5 else 24), 3
-    c = Case(cfg_id, W, S, MIXED, refresh_every=K)
-    say(f"[jastrow derivs with rebuilds] cfg={cfg_id} K={K} tuning={tuning}")
+    c = Case(cfg_id, W, S, MIXED, refresh_every=K, u_term=u_term)
+    say(f"[jastrow derivs with rebuilds] cfg={cfg_id} K={K} tuning={tuning} u_term={u_term}")
     if tuning:
         c.batch.set_tuning(**tuning)
     c.run_energy()
@@ -877,7 +879,7 @@ def test_jastrow_derivs_with_rebuilds(oracle_lib, cfg_id, tuning):
     c.batch.run_moves_grad(c.k, c.new_pos, c.accept, d, dj, g, l)
     torch.cuda.synchronize()
     assert all(c.batch.walker_header(w)["n_refresh"] >= 2 for w in range(W))
-    ref = Case(cfg_id, W, S, MIXED, refresh_every=K)
+    ref = Case(cfg_id, W, S, MIXED, refresh_every=K, u_term=u_term)
     if tuning:
         ref.batch.set_tuning(**tuning)
     ref.run_energy()
@@ -888,7 +890,7 @@ def test_jastrow_derivs_with_rebuilds(oracle_lib, cfg_id, tuning):
     for w in range(W):
         assert np.max(np.abs(c.batch.walker_rho(w) - ref.batch.walker_rho(w))) <= 1e-12 * math.sqrt(c.system(w).n_mobile)
     check_derivs(c, oracle_lib, g.cpu().numpy(), l.cpu().numpy(), MIXED, "fused, rebuilds")
-    p = Case(cfg_id, W, S, MIXED, refresh_every=K)
+    p = Case(cfg_id, W, S, MIXED, refresh_every=K, u_term=u_term)
     p.run_energy()
     for m in range(S):
         p.batch.move_delta_grad(p.k[m], p.new_pos[m], d[m], dj[m], g[m], l[m])

@@ -727,12 +727,12 @@ def test_n1024_long_sweep_with_rebuilds(oracle_lib, precision):
     K=64: 2 walkers x 280 moves, so that the FP32-mixed form rebuilds rho in
     FP64 twice per walker mid-sequence.  The per-step kernels (accept plus the
     rebuild kernel) and the fused sweep at 1024 threads (running rho kept in
-    LDS during its rebuild) and at 512 threads are each compared with the
-    oracle on every delta and Jastrow delta, and the final rho element by
-    element."""
+    LDS during its rebuild) and at 512 threads (two and four waves per SIMD)
+    are each compared with the oracle on every delta and Jastrow delta, and
+    the final rho element by element."""
     W, S = 2, 280
     refs = None
-    for path in ("per-step", "step", 1024, 512):
+    for path in ("per-step", "step", 1024, 512, "512w4"):
         say(f"[n1024 long] precision={precision} path={path}")
         c = Case(5, W, S, precision)
         if refs is None:
@@ -743,8 +743,10 @@ def test_n1024_long_sweep_with_rebuilds(oracle_lib, precision):
         elif path == "step":
             d, dj = c.stepped()
         else:
-            c.batch.set_tuning(threads=path)
-            assert c.batch.tuning()["threads"] == path and c.batch.tuning()["fused"] == 1
+            threads, waves = (512, 4) if path == "512w4" else (path, 0)
+            c.batch.set_tuning(threads=threads, waves=waves)
+            tn = c.batch.tuning()
+            assert tn["threads"] == threads and tn["fused"] == 1 and tn["waves"] == (waves or tn["waves"])
             d, dj = c.fused()
         for w in range(W):
             r, sysw = refs[w], c.system(w)

@@ -521,6 +521,61 @@ def test_tuning_shapes_agree(precision):
         ref.batch.set_tuning(threads=1024, waves=4)  # 1024 threads: four waves per SIMD by construction
 
 
+def test_largest_sizes(oracle_lib):
+    """Near the library's limits: 2040 electrons (EWALD_MAX_PARTICLES is
+    2048) and 1960 G segments (EWALD_MAX_SEGMENTS is 2048), which only the
+    512-thread four-segment fused kernel and the eight-segment energy kernel
+    take.  Energies and every delta of a fused sweep and of the per-step calls
+    against the oracle, in both forms (the mixed form at K = 3, so that it
+    rebuilds rho between chunks and after accepts)."""
+    n, W, S = 2040, 2, 8
+    L = (4 * math.pi * n / 3) ** (1 / 3)
+    sy = wl.System("max2040", 3, np.eye(3) * L, n, -np.ones(n), np.zeros((0, 3)), np.zeros(0), 5.0 / L, 0.5 * L,
+                   15.0 * 2 * math.pi / L)
+    rng = np.random.default_rng(2040)
+    pos = rng.uniform(0, L, (W, n, 3))
+    k = rng.integers(0, n, (S, W)).astype(np.int32)
+    newp = np.stack([pos[w][k[:, w]] + rng.normal(0, 0.5, (S, 3)) for w in range(W)], axis=1)
+    acc = (rng.uniform(size=(S, W)) < 0.6).astype(np.uint8)
+    say("[largest sizes] oracle")
+    refs = [oracle_lib.run(sy, pos[w], k[:, w], newp[:, w], acc[:, w]) for w in range(W)]
+    packed = torch.tensor(pos.reshape(W * n, 3), device="cuda")
+    kt, nt, at = (torch.tensor(x, device="cuda") for x in (k, newp, acc))
+    for precision in (FP64, MIXED):
+        for path in ("fused", "per-step"):
+            say(f"[largest sizes] precision={precision} path={path}")
+            h = ew.System(sy, precision=precision, refresh_every=3 if precision == MIXED else 0)
+            assert 1024 < ew.ewald_sys_query(h.handle)["n_slots"] // 4 <= 2048
+            b = ew.Batch([h], np.zeros(W, dtype=np.int32))
+            e = torch.zeros(W, dtype=torch.float64, device="cuda")
+            b.energy(packed, e)
+            d = torch.zeros((S, W), dtype=torch.float64, device="cuda")
+            if path == "fused":
+                t = b.tuning()
+                assert t["fused"] == 1 and t["threads"] == 512
+                b.run_moves(kt, nt, at, d)
+            else:
+                for m in range(S):
+                    b.move_delta(kt[m], nt[m], d[m])
+                    b.accept(at[m])
+            torch.cuda.synchronize()
+            en, dn = e.cpu().numpy(), d.cpu().numpy()
+            for w in range(W):
+                r = refs[w]
+                scale = max(1.0, abs(r["energy0"]))
+                h_w = b.walker_header(w)
+                assert h_w["n_accepts"] == int(acc[:, w].sum())
+                if precision == MIXED:
+                    assert h_w["n_refresh"] >= 1
+                    assert abs(en[w] - r["energy0"]) <= 1e-6 * scale
+                    assert np.max(np.abs(dn[:, w] - r["delta"])) <= 1e-5, (path, w)
+                else:
+                    assert abs(en[w] - r["energy0"]) <= 1e-10 * scale
+                    assert np.max(np.abs(dn[:, w] - r["delta"])) <= 1e-10 * scale, (path, w)
+            b.close()
+            h.close()
+
+
 @pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
 def test_extra_particles_and_ions_at_large_shapes(precision):
     """The 512- and 1024-thread fused kernels built with their loops over
@@ -1317,6 +1372,39 @@ def test_step_call_order():
     assert e.value.status == ew.EWALD_E_STATE
     c.batch.accept(c.accept[1])
     c.fused(1)
+
+
+def test_empty_inputs():
+    """Degenerate sizes through the C ABI: a sweep of zero moves is a no-op
+    (state byte for byte as before, outputs untouched), so is a blip
+    evaluation at zero points; a negative move or point count and a batch of
+    no walkers are rejected with E_ARG."""
+    say("[empty inputs]")
+    c = Case(2, 3, 2, FP64)
+    c.run_energy()
+    before = c.batch.state.clone()
+    d = torch.full((1, 3), 7.0, dtype=torch.float64, device="cuda")
+    args = (c.k.data_ptr(), c.new_pos.data_ptr(), c.accept.data_ptr(), d.data_ptr())
+    ew.ewald_run_moves_batch(c.batch.handle, c.batch.state.data_ptr(), 0, *args)
+    torch.cuda.synchronize()
+    assert torch.equal(c.batch.state, before) and bool((d == 7.0).all())
+    with pytest.raises(ew.EwaldError) as e:
+        ew.ewald_run_moves_batch(c.batch.handle, c.batch.state.data_ptr(), -1, *args)
+    assert e.value.status == ew.EWALD_E_ARG
+    with pytest.raises(ew.EwaldError) as e:
+        ew.ewald_batch_create([c.systems[0].handle], np.zeros(0, dtype=np.int32))
+    assert e.value.status == ew.EWALD_E_ARG
+    bl = ew.Blips(SKEW, (4, 4, 4), 2)
+    coef = torch.ones((4, 4, 4, 2), dtype=torch.float64, device="cuda")
+    pos = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    val = torch.full((1, 2), 7.0, dtype=torch.float64, device="cuda")
+    ew.ewald_blip_eval_batch(bl.handle, coef.data_ptr(), 0, pos.data_ptr(), val.data_ptr())
+    torch.cuda.synchronize()
+    assert bool((val == 7.0).all())
+    with pytest.raises(ew.EwaldError) as e:
+        ew.ewald_blip_eval_batch(bl.handle, coef.data_ptr(), -1, pos.data_ptr(), val.data_ptr())
+    assert e.value.status == ew.EWALD_E_ARG
+    bl.close()
 
 
 def test_call_timers():

@@ -4,6 +4,7 @@ Tolerances (relative to E_ref = max(|E_oracle|, (alpha/sqrt(pi)) sum q^2)):
   FP64 form   energies and move deltas within 1e-10 E_ref;
   FP32-mixed  energies within 1e-6 E_ref, each move delta within 1e-5 Ha.
 """
+import copy
 import dataclasses
 import math
 import os
@@ -188,6 +189,38 @@ def test_moves_per_step(oracle_lib, cfg_id, precision):
         scale = max(abs(e_fin[w]), e_scale(c.system(w)))
         tol = 1e-10 * scale if precision == FP64 else 1e-6 * scale + 1e-5 * S
         assert abs(e_tel[w] - e_fin[w]) <= tol
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cfg_id", [2, 3])
+def test_degree32_pair_polynomial(oracle_lib, cfg_id, precision):
+    """alpha r_c = 3.5 (above 2.83): the pair potential's fit of erf(sqrt y)/sqrt y
+    takes the degree-32 FP64 (degree-22 FP32) polynomial in the energy,
+    per-step and fused kernels; energies and every delta and Jastrow delta of
+    both paths against the oracle (the mixed form at K = 3)."""
+    cfg = wl.config(cfg_id)
+    s0 = cfg.systems[0]
+    L = s0.length
+    cfg.systems = [dataclasses.replace(s0, alpha=7.0 / L, r_cut=0.5 * L, g_cut=s0.g_cut * 1.4)]
+    assert cfg.systems[0].alpha * cfg.systems[0].r_cut > 2.83
+    W, S = 2, 16
+    say(f"[degree-32 polynomial] cfg={cfg_id} precision={precision}")
+    for path in ("per-step", "fused"):
+        c = Case(cfg_id, W, S, precision, refresh_every=3, cfg=copy.deepcopy(cfg))
+        e0, _ = c.run_energy()
+        d, dj = c.per_step() if path == "per-step" else c.fused()
+        for w in range(W):
+            sysw = c.system(w)
+            r = c.oracle(oracle_lib, w)
+            scale = max(abs(r["energy0"]), e_scale(sysw))
+            if precision == FP64:
+                assert abs(e0[w] - r["energy0"]) <= 1e-10 * scale, path
+                assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-10 * scale, path
+                assert np.max(np.abs(dj[:, w] - r["djas"])) <= 1e-10 * max(1.0, abs(r["j0"])), path
+            else:
+                assert abs(e0[w] - r["energy0"]) <= 1e-6 * scale, path
+                assert np.max(np.abs(d[:, w] - r["delta"])) <= 1e-5, path
+                assert np.max(np.abs(dj[:, w] - r["djas"])) <= djas_bound(c, w), path
 
 
 @pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])

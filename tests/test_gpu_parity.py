@@ -554,6 +554,75 @@ def test_tuning_shapes_agree(precision):
         ref.batch.set_tuning(threads=1024, waves=4)  # 1024 threads: four waves per SIMD by construction
 
 
+def two_d_systems():
+    """A 2D hexagonal gas of 1000 electrons with 643 G segments (the
+    1024-thread and 512 x 2 fused shapes) and a 64-electron oblique cell,
+    which has no orthogonal-sublattice frame (general minimum image)."""
+    n = 1000
+    area = math.pi * n
+    L = math.sqrt(area)
+    big = wl.System("hex1000", 2, wl.hex_cell(area), n, -np.ones(n), np.zeros((0, 2)), np.zeros(0), 5.0 / L,
+                    0.5 * L, 40 * 2 * math.pi / L)
+    n = 64
+    L = math.sqrt(math.pi * n)
+    ob = np.zeros((3, 3))
+    ob[0, 0], ob[1, 0], ob[1, 1], ob[2, 2] = L, 0.31 * L, 0.93 * L, 1.0
+    obl = wl.System("oblique64", 2, ob, n, -np.ones(n), np.zeros((0, 2)), np.zeros(0), 5.0 / L, 0.42 * L,
+                    12 * 2 * math.pi / L)
+    return big, obl
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_two_d_larger_shapes_and_oblique_cell(oracle_lib, precision):
+    """2D cells beyond the workloads' shapes: energies and every delta of the
+    per-step calls and of the fused sweep at each available workgroup size,
+    against the oracle (the mixed form at K = 3)."""
+    W, S = 2, 12
+    for sy, shapes in zip(two_d_systems(), ((1024, 512), (0, 1024))):
+        rng = np.random.default_rng([2, sy.n_mobile])
+        lat = sy.lattice[:2, :2]
+        pos = rng.random((W, sy.n_mobile, 2)) @ lat
+        k = rng.integers(0, sy.n_mobile, (S, W)).astype(np.int32)
+        newp = np.stack([pos[w][k[:, w]] + rng.normal(0, 0.6, (S, 2)) for w in range(W)], axis=1)
+        acc = (rng.uniform(size=(S, W)) < 0.6).astype(np.uint8)
+        say(f"[2d shapes] {sy.name} oracle")
+        refs = [oracle_lib.run(sy, pos[w], k[:, w], newp[:, w], acc[:, w]) for w in range(W)]
+        packed = torch.tensor(pos.reshape(W * sy.n_mobile, 2), device="cuda")
+        kt, nt, at = (torch.tensor(x, device="cuda") for x in (k, newp, acc))
+        for path in ("per-step",) + shapes:
+            say(f"[2d shapes] {sy.name} precision={precision} path={path}")
+            h = ew.System(sy, precision=precision, refresh_every=3 if precision == MIXED else 0)
+            if sy.name.startswith("oblique"):
+                assert ew.ewald_sys_geometry(h.handle)[0] == 0
+            b = ew.Batch([h], np.zeros(W, dtype=np.int32))
+            e = torch.zeros(W, dtype=torch.float64, device="cuda")
+            b.energy(packed, e)
+            d = torch.zeros((S, W), dtype=torch.float64, device="cuda")
+            if path == "per-step":
+                for m in range(S):
+                    b.move_delta(kt[m], nt[m], d[m])
+                    b.accept(at[m])
+            else:
+                b.set_tuning(threads=path)
+                t = b.tuning()
+                assert t["fused"] == 1 and (path == 0 or t["threads"] == path)
+                b.run_moves(kt, nt, at, d)
+            torch.cuda.synchronize()
+            en, dn = e.cpu().numpy(), d.cpu().numpy()
+            for w in range(W):
+                r = refs[w]
+                scale = max(abs(r["energy0"]), e_scale(sy))
+                assert b.walker_header(w)["n_accepts"] == int(acc[:, w].sum())
+                if precision == MIXED:
+                    assert abs(en[w] - r["energy0"]) <= 1e-6 * scale
+                    assert np.max(np.abs(dn[:, w] - r["delta"])) <= 1e-5, (path, w)
+                else:
+                    assert abs(en[w] - r["energy0"]) <= 1e-10 * scale
+                    assert np.max(np.abs(dn[:, w] - r["delta"])) <= 1e-10 * scale, (path, w)
+            b.close()
+            h.close()
+
+
 def test_largest_sizes(oracle_lib):
     """Near the library's limits: 2040 electrons (EWALD_MAX_PARTICLES is
     2048) and 1960 G segments (EWALD_MAX_SEGMENTS is 2048), which only the

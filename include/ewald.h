@@ -364,8 +364,9 @@ ewald_status ewald_batch_get_tuning(ewald_batch *b, int *threads, int *chunk, in
  * and is left unchanged; in the FP32-mixed form n_moves >= 2 refresh_every
  * makes the probe include rho rebuilds.  With a
  * cache_path, a tuning stored there for the same device architecture and
- * batch shape is applied without timing, and a new one is appended (one text
- * line per shape).  Allocates temporary device buffers and synchronises
+ * batch shape is applied without timing (one that ewald_batch_set_tuning
+ * rejects is measured afresh), and a new one is appended (one text line per
+ * shape; the last line for a shape wins).  Allocates temporary device buffers and synchronises
  * `stream`: a set-up call, not for graph capture.  Status: E_ARG, E_STATE,
  * E_HIP. */
 ewald_status ewald_autotune(ewald_batch *b, void *state, int n_moves, const char *cache_path,

@@ -1452,7 +1452,11 @@ ewald_status ewald_autotune(ewald_batch* b, void* state, int n_moves, const char
   if (st != EWALD_OK) return st;
   const std::string key = tune_key(b);
   int t = 0, c = 0, g = 0, v = 0, q = 0;
-  if (cache_path && cache_lookup(cache_path, key, &t, &c, &g, &v, &q)) return ewald_batch_set_tuning(b, t, c, g, v, q);
+  // a cached tuning that this library rejects (an edited file, or one from
+  // another build) is measured afresh, and the new choice appended
+  if (cache_path && cache_lookup(cache_path, key, &t, &c, &g, &v, &q) &&
+      ewald_batch_set_tuning(b, t, c, g, v, q) == EWALD_OK)
+    return EWALD_OK;
   // probe: proposals spread over each cell, every other move accepted, run on
   // a copy of the walkers' state (which is left as it was)
   const int W = b->lb.n_walkers, dim = b->lb.dim;

@@ -762,6 +762,14 @@ def test_autotune_keeps_state_and_caches(tmp_path, oracle_lib):
     c2.batch.autotune(n_moves=8, cache_path=str(cache))  # from the cache: no new line
     assert c2.batch.tuning() == t1
     assert len(cache.read_text().strip().splitlines()) == 1
+    # a cached line the library rejects (no such workgroup size) is measured
+    # afresh and the new choice appended
+    key = lines[0].split("|")[0]
+    cache.write_text(key + "|threads=999 chunk=0 general_frame=0 waves=2 walkers_per_block=0\n")
+    c2.batch.autotune(n_moves=8, cache_path=str(cache))
+    assert c2.batch.tuning()["fused"] == 1
+    lines2 = cache.read_text().strip().splitlines()
+    assert len(lines2) == 2 and lines2[1].startswith(key + "|threads=") and "threads=999" not in lines2[1]
     d, _ = c.fused()
     for w in range(W):
         r = c.oracle(oracle_lib, w)

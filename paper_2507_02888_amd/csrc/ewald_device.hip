@@ -168,7 +168,38 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
     const double qi = lq[i];
     const int spi = UJ ? S->spin[i] : 0;
     const int li = i >= n0 ? 1 : 0;  // plane of particle i (layered systems)
-    const int n_mob = half + (((n & 1) == 0 && i < n / 2) ? 1 : 0);
+    // the partners i + 1 .. i + half (cyclically), which every particle has:
+    // the group bounds are the same for every lane and no partner is an ion
+    for (int m0 = 0; m0 < half; m0 += 4) {
+      double qq[4], r2[4], ir[4];
+      bool uneq[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        int j = i + m0 + c + 1;
+        if (j >= n) j -= n;
+        if (m0 + c < half) {
+          double sj[DIM];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) sj[d] = lpos[d * lds_pos + j];
+          qq[c] = qi * lq[j];
+          r2[c] = image_r2<DIM, ORTHO>(si, sj, S, n_cand, K);
+          if (lay) r2[c] += ((j >= n0 ? 1 : 0) != li) ? S->dz2 : 0.0;
+          uneq[c] = UJ && S->spin[j] != spi;
+        } else {
+          qq[c] = 0.0;
+          r2[c] = rc2;
+          uneq[c] = false;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ir[c] = rsqrt_pos(r2[c]);
+      pr.template add_ir<4>(qq, r2, ir);
+      if (UJ)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) eu += u_pair(S, m0 + c < half, uneq[c], r2[c], ir[c]);
+    }
+    // then i + n/2 for i < n/2 when n is even, and every fixed ion
+    const int n_mob = ((n & 1) == 0 && i < n / 2) ? 1 : 0;
     const int n_part = n_mob + nfix;
     for (int m0 = 0; m0 < n_part; m0 += 4) {
       double qq[4], r2[4], ir[4];
@@ -177,7 +208,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_energy(const DevSys* __restrict__ 
       for (int c = 0; c < 4; ++c) {
         const int m = m0 + c;
         const bool mob = m < n_mob, fix = !mob && m < n_part;
-        int j = i + m + 1;
+        int j = i + half + m + 1;
         if (j >= n) j -= n;
         double sj[DIM];
         if (mob) {

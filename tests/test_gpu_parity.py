@@ -1219,10 +1219,13 @@ def test_bilayer_energy_and_moves(oracle_lib, precision):
     W, S, K = 3, 24, 4
     say(f"[bilayer] precision={precision}")
     out = {}
-    for path in ("per-step", "run_moves"):
+    for path in ("per-step", "run_moves", "run_moves_1024"):
         c = Case(3, W, S, precision, refresh_every=K, jastrow=False, cfg=wl.bilayer_config())
         e0, _ = c.run_energy()
-        if path == "run_moves":
+        if path == "run_moves_1024":
+            c.batch.set_tuning(threads=1024)
+            assert c.batch.tuning()["threads"] == 1024
+        if path != "per-step":
             assert c.batch.tuning()["fused"] == 1
         out[path] = (e0,) + (c.per_step() if path == "per-step" else c.fused())
         for w in range(W):

@@ -650,12 +650,16 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
   const int n_cand = S->n_cand;
   const double rc2 = S->rc2;
   const int lk = k >= n0 ? 1 : 0;
-  {
-    double qq[2 * PPR], r2[2 * PPR], ir[2 * PPR];
-    double xn[UD ? PPR : 1][DIM] = {};  // zero for masked partners (their weight is zero too)
-    bool okc[PPR];
+  // the own particles c < NC; a wave evaluates only the c for which some
+  // lane holds a particle (the count is the same for every lane of the
+  // wave), so small walkers in a large workgroup skip the empty ones
+  auto own = [&](auto nc) {
+    constexpr int NC = decltype(nc)::value;
+    double qq[2 * NC], r2[2 * NC], ir[2 * NC];
+    double xn[UD ? NC : 1][DIM] = {};  // zero for masked partners (their weight is zero too)
+    bool okc[NC];
 #pragma unroll
-    for (int c = 0; c < PPR; ++c) {
+    for (int c = 0; c < NC; ++c) {
       const int j = threadIdx.x + c * NT;
       const bool ok = j < n && j != k;
       if (UD)
@@ -672,13 +676,22 @@ __device__ __forceinline__ double real_move_own(const double* sn, const double* 
       okc[c] = ok;
     }
 #pragma unroll
-    for (int e = 0; e < 2 * PPR; ++e) ir[e] = rsqrt_pos(r2[e]);
-    pr.template add_ir<2 * PPR>(qq, r2, ir);
+    for (int e = 0; e < 2 * NC; ++e) ir[e] = rsqrt_pos(r2[e]);
+    pr.template add_ir<2 * NC>(qq, r2, ir);
     if (UJ)
 #pragma unroll
-      for (int c = 0; c < PPR; ++c)
+      for (int c = 0; c < NC; ++c)
         u_move_term<DIM, UD>(S, okc[c], psp[c] != sk, r2[2 * c], ir[2 * c], r2[2 * c + 1], ir[2 * c + 1],
                              xn[UD ? c : 0], *uo);
+  };
+  static_assert(PPR == 1 || PPR == 2, "own particles per thread: 1 or 2");
+  {
+    const int wbase = uniform_i(int(threadIdx.x) & ~63);  // the wave's first thread
+    const int cw = n > wbase ? min(PPR, (n - wbase + NT - 1) / NT) : 0;
+    if (cw >= PPR)
+      own(std::integral_constant<int, PPR>{});
+    else if (PPR > 1 && cw == 1)
+      own(std::integral_constant<int, 1>{});
   }
   if (!XTRA) return pr.value();
   for (int j = threadIdx.x + PPR * NT; j < n; j += NT) {

@@ -525,10 +525,14 @@ def test_tuning_shapes_agree(precision):
     assert t["fused"] == 1 and t["threads"] == 1024 and 1 <= t["chunk"] <= 64
     ref.run_energy()
     d0, j0 = ref.fused()
-    # FP64: rounding order only; FP32-mixed: per-thread FP32 partial sums
-    # differ with the shape, so the form's own per-delta bound applies
+    # FP64: rounding order only.  FP32-mixed: the FP32 partial sums run over
+    # segment groups that differ with the shape (9e-8 Ha on deltas and 3e-7
+    # on Jastrow deltas between the 1024- and 512-thread layouts here); the
+    # bounds sit ten times above that, well inside the form's 1e-5 budget,
+    # so a shape-specific error shows
     scale = max(1.0, max(abs(x) for x in ref.energy.cpu().numpy()))
-    tol = 1e-12 * scale if precision == FP64 else 1e-5
+    tol = 1e-12 * scale if precision == FP64 else 1e-6
+    tol_j = 1e-12 * scale if precision == FP64 else 3e-6
     for threads, chunk, general, waves in ((512, 0, 0, 0), (1024, 5, 0, 0), (512, 1, 1, 0), (0, 64, 1, 0),
                                            (512, 0, 0, 4), (512, 3, 1, 4)):
         c = Case(5, W, S, precision, walker_start=w0, refresh_every=3)
@@ -540,8 +544,10 @@ def test_tuning_shapes_agree(precision):
             assert t["chunk"] == chunk if chunk <= 8 else 8 <= t["chunk"] <= chunk
         c.run_energy()
         d, j = c.fused()
+        say(f"  shape {threads, chunk, general, waves}: max |d - d0| = {np.max(np.abs(d - d0)):.3e}, "
+            f"max |j - j0| = {np.max(np.abs(j - j0)):.3e}")
         assert np.max(np.abs(d - d0)) <= tol, (threads, chunk, general)
-        assert np.max(np.abs(j - j0)) <= tol
+        assert np.max(np.abs(j - j0)) <= tol_j
         for w in range(W):
             assert np.max(np.abs(c.batch.walker_rho(w) - ref.batch.walker_rho(w))) <= 1e-9
     with pytest.raises(ew.EwaldError):

@@ -647,7 +647,9 @@ size_t run_layout(const LaunchBatch& b, int ch, RunLds& L) {
     o = up16(o + size_t(ch) * NW * 4 * (DIM + 1) * (UJ ? 2 : 1) * 8);
   }
   L.ch = ch;
-  L.rtile = int(std::min<size_t>(ctab / rpart, 64)) & ~1;  // even (the tiles interleave particle pairs)
+  // between chunks everything from ctab on holds per-chunk data only, so the
+  // rebuild tiles may fill all of it; even (the tiles interleave particle pairs)
+  L.rtile = int(std::min<size_t>((o - L.ctab) / rpart, 64)) & ~1;
   // Between chunks the tables and the staging area (everything from ctab on:
   // per-chunk data only) are free: the mixed form's rebuild keeps the running
   // rho there (for the drift check) when it fits beside tiles of at least

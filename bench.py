@@ -213,7 +213,7 @@ def per_step_rows(r, W: int, n_g: int, n: int, dim: int) -> dict:
     return rows
 
 
-def other_workload(cfg_id: int, precision: int, steps: int = 2, threads: int = 0):
+def other_workload(cfg_id: int, precision: int, steps: int = 2, threads: int = 0, waves: int = 0):
     """A whole-workload sweep of one of the smaller configurations (energy plus
     the fused sweep, autotuned launch shape): deltas/s and the fused kernel's
     VALU fraction by the same algorithmic count."""
@@ -236,7 +236,7 @@ def other_workload(cfg_id: int, precision: int, steps: int = 2, threads: int = 0
     delta = torch.zeros((S, W), dtype=torch.float64, device=dev)
     batch.energy(pos, energy)
     if threads:
-        batch.set_tuning(threads=threads)
+        batch.set_tuning(threads=threads, waves=waves)
     else:
         batch.autotune(n_moves=max(64, 2 * K) if K else 64)
     stream = torch.cuda.current_stream()
@@ -615,7 +615,7 @@ def main():
         for cid in [int(x) for x in args.other.split(",") if x]:
             for form in args.forms.split(","):
                 prec = ew.EWALD_FP32_MIXED if form == "mixed" else ew.EWALD_FP64
-                print(json.dumps(other_workload(cid, prec, threads=args.threads)), flush=True)
+                print(json.dumps(other_workload(cid, prec, threads=args.threads, waves=args.waves)), flush=True)
         want = set(x for x in args.next.split(",") if x)
         if "blips" in want:
             print(json.dumps({"blips": blip_row()}), flush=True)
